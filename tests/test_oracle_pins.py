@@ -1,0 +1,387 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU needed).
+
+Each test names the passage it checks.  None of them re-types the oracle's own formula: they use
+closed forms, library routines for special cases, brute force on tiny inputs, exact identities of the
+paper's equations evaluated independently with numpy, and statistical properties.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2411_06158_amd import synth
+
+
+def small_data(N=3000, D=48, n_comp=16, seed=7, nq=20, cluster_dims=8):
+    spec = synth.MixtureSpec(D=D, n_comp=n_comp, decay=1.0, cluster_dims=cluster_dims, model_seed=seed)
+    m = synth.build_model(spec)
+    return synth.sample(m, N, 1), synth.sample(m, nq, 2), spec
+
+
+# ---- generator ---------------------------------------------------------------------------------
+
+def test_generator_spectrum_matches_construction():
+    """The PCA spectrum of the synthetic data follows lambda_i ~ i^-alpha (Section 3.2's long tail)."""
+    spec = synth.MixtureSpec(D=64, n_comp=1, decay=1.0, model_seed=11)
+    X = synth.sample(synth.build_model(spec), 40000, 1).astype(np.float64)
+    ev = np.linalg.eigvalsh(np.cov(X.T, bias=True))[::-1]
+    for d in (8, 16, 32):
+        assert abs(ev[:d].sum() / ev.sum() - synth.variance_fraction(spec, d)) < 0.01
+    # the named small workload: closed-form share of the top 32 axes is 0.747
+    assert abs(synth.variance_fraction(synth.WORKLOADS["small"]["spec"], 32) - 0.7470) < 5e-4
+
+
+# ---- randomness ---------------------------------------------------------------------------------
+
+def test_gaussian_moments(orc):
+    g = orc.gaussian(123, 200_000)
+    se = 1.0 / math.sqrt(g.size)
+    assert abs(g.mean()) < 4 * se
+    assert abs(g.var() - 1.0) < 4 * math.sqrt(2.0) * se
+    assert abs(np.mean(g ** 4) - 3.0) < 0.05
+
+
+# ---- PCA / eigensolver (Algorithm 1, PCA steps) -------------------------------------------------
+
+def test_eigh_residual_orthogonality_and_library_agreement(orc):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((40, 40))
+    S = A @ A.T / 40
+    w, V = orc.eigh(S)
+    lmax = w.max()
+    assert np.all(np.diff(w) <= 0)                                    # descending
+    for i in range(40):
+        assert np.linalg.norm(S @ V[i] - w[i] * V[i]) <= 1e-10 * lmax
+    assert np.abs(V @ V.T - np.eye(40)).max() <= 1e-12
+    ref = np.linalg.eigvalsh(S)[::-1]                                 # library special case
+    assert np.allclose(w, ref, rtol=0, atol=1e-12 * lmax)
+    for i in range(40):                                               # sign rule: max-|.| entry > 0
+        assert V[i][np.argmax(np.abs(V[i]))] > 0
+
+
+def test_pca_preserves_distances_and_decorrelates(orc):
+    X, Q, _ = small_data()
+    ix = orc.Index.build(X, d=16, B=1, nlist=8)
+    P, mu, lam = ix.get("Pp"), ix.get("mu"), ix.get("lam")
+    Xp = (X.astype(np.float64) - mu) @ P.T
+    qp = (Q[0].astype(np.float64) - mu) @ P.T
+    d_orig = ((X.astype(np.float64) - Q[0].astype(np.float64)) ** 2).sum(1)
+    d_rot = ((Xp - qp) ** 2).sum(1)
+    assert np.allclose(d_rot, d_orig, rtol=1e-12, atol=0)            # Eq 1 with an orthogonal P_p
+    cov = Xp.T @ Xp / X.shape[0]                                      # 1/N covariance of x_p
+    assert np.abs(cov - np.diag(lam)).max() <= 1e-9 * lam.max()
+
+
+# ---- Eq 6: residual variance is an exact identity once PCA decorrelates the tail ----------------
+
+def test_eq6_variance_identity_and_chebyshev(orc):
+    X, Q, _ = small_data(N=4000)
+    d = 16
+    ix = orc.Index.build(X, d=d, B=1, nlist=8)
+    P, mu, lam = ix.get("Pp"), ix.get("mu"), ix.get("lam")
+    Xp = (X.astype(np.float64) - mu) @ P.T
+    prm = orc.params(m=3.0)
+    for qi in range(5):
+        qp = (Q[qi].astype(np.float64) - mu) @ P.T
+        ip_r = Xp[:, d:] @ qp[d:]
+        sig, *_ = ix.pair_trace(Q[qi], 0, prm)
+        sigma = sig["sigma"]
+        assert abs(ip_r.var() - sigma ** 2) <= 1e-9 * sigma ** 2      # Eq 6, exact over the dataset
+        for m in (2.0, 3.0, 4.0):                                     # Chebyshev (Section 4.2)
+            assert np.mean(np.abs(ip_r - ip_r.mean()) >= m * sigma) <= 1.0 / m ** 2
+        assert abs(sig["er"] - 2 * 3.0 * sigma) <= 1e-12 * max(sigma, 1.0)
+
+
+# ---- Eq 2, 3, 7 evaluated independently -----------------------------------------------------------
+
+@pytest.mark.parametrize("B", [1, 4])
+def test_eq3_and_eq7_decompositions(orc, B):
+    X, Q, _ = small_data(N=1500, D=32, cluster_dims=6)
+    d = 12
+    ix = orc.Index.build(X, d=d, B=B, nlist=6)
+    P, mu, Cc = ix.get("Pp"), ix.get("mu"), ix.get("C")
+    off, lid = ix.get("off"), ix.get("lid")
+    nx, tx, ax = ix.get("nx"), ix.get("tx"), ix.get("ax")
+    Xp = (X.astype(np.float64) - mu) @ P.T
+    for qi in range(3):
+        qp = (Q[qi].astype(np.float64) - mu) @ P.T
+        for j in range(ix.nlist):
+            qs, _, _, ids, cand = ix.pair_trace(Q[qi], j)
+            c = Cc[j]
+            pos = np.arange(off[j], off[j + 1])
+            assert np.array_equal(ids, lid[pos])
+            xd, xr = Xp[ids, :d], Xp[ids, d:]
+            qd, qr = qp[:d], qp[d:]
+            n_x = np.linalg.norm(xd - c, axis=1)
+            n_q = np.linalg.norm(qd - c)
+            assert np.allclose(nx[pos], n_x, rtol=1e-12, atol=1e-12)
+            assert np.allclose(tx[pos], (xr ** 2).sum(1), rtol=1e-10, atol=1e-10)
+            assert abs(qs["nq"] - n_q) <= 1e-12 * max(n_q, 1)
+            assert abs(qs["Tq"] - (qr ** 2).sum()) <= 1e-10 * max(qs["Tq"], 1)
+            xb = (xd - c) / n_x[:, None]
+            qb = (qd - c) / n_q
+            exact = ((X[ids].astype(np.float64) - Q[qi].astype(np.float64)) ** 2).sum(1)
+            assert np.allclose(cand["dis"], exact, rtol=1e-13, atol=0)
+            eq3 = n_x ** 2 + n_q ** 2 + (xr ** 2).sum(1) + (qr ** 2).sum() \
+                - 2 * n_x * n_q * (xb @ qb) - 2 * (xr @ qr)
+            assert np.allclose(eq3, exact, rtol=1e-9, atol=1e-9)         # Eq 3
+            eq7 = (Xp[ids] ** 2).sum(1) + (qp ** 2).sum() - 2 * (xd @ qd)
+            assert np.allclose(cand["diso"], eq7, rtol=1e-10, atol=1e-10)  # Eq 7
+            assert np.allclose(ax[pos], (Xp[ids] ** 2).sum(1), rtol=1e-12)
+            assert np.allclose(cand["diso"] - 2 * (xr @ qr), exact, rtol=1e-9, atol=1e-9)
+
+
+def test_full_dimension_special_case(orc):
+    """d = D: no tail, so t_x = T_q = sigma = eps_r = 0 and Eq 7 is the exact distance."""
+    X, Q, _ = small_data(N=800, D=16, cluster_dims=4)
+    ix = orc.Index.build(X, d=16, B=1, nlist=4)
+    assert np.abs(ix.get("tx")).max() <= 1e-12 * ix.get("ax").max()
+    for j in range(4):
+        qs, _, _, _, cand = ix.pair_trace(Q[0], j)
+        assert abs(qs["Tq"]) < 1e-20 and qs["sigma"] == 0 and qs["er"] == 0
+        assert np.allclose(cand["diso"], cand["dis"], rtol=1e-11, atol=1e-11)
+
+
+# ---- codes and the estimator (Section 4.2) ---------------------------------------------------------
+
+def _xi_mean_closed_form(d):
+    return math.sqrt(d) * math.exp(math.lgamma(d / 2) - math.lgamma((d + 1) / 2)) / math.sqrt(math.pi)
+
+
+def test_xi_mean_closed_form(orc):
+    """E<xbar, x> over random unit x equals sqrt(d) Gamma(d/2) / (sqrt(pi) Gamma((d+1)/2))."""
+    assert abs(_xi_mean_closed_form(32) - 0.8041) < 1e-4
+    assert abs(_xi_mean_closed_form(128) - 0.7994) < 1e-4
+    rng = np.random.default_rng(9)
+    for d in (32, 128):
+        v = rng.standard_normal((20000, d))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        xs = np.array([orc.encode_sign(r)[1] for r in v])
+        assert np.all(xs >= 1 / math.sqrt(d) - 1e-12) and np.all(xs <= 1 + 1e-12)
+        se = xs.std() / math.sqrt(xs.size)
+        assert abs(xs.mean() - _xi_mean_closed_form(d)) < 4 * se
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_estimator_unbiased_over_haar_rotations(orc, B):
+    """<xbar, q>/<xbar, x> is unbiased for <x, q> over the random rotation (Section 4.2)."""
+    d = 24
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(d); x /= np.linalg.norm(x)
+    q = rng.standard_normal(d); q -= 0.5 * x; q /= np.linalg.norm(q)
+    truth = x @ q
+    est, fails = [], {1.0: 0, 1.9: 0, 3.0: 0}
+    M = 3000
+    h = ((1 << B) - 1) / 2
+    for r in range(M):
+        P = orc.haar(d, 10_000 + r)
+        xp, qp = P.T @ x, P.T @ q
+        if B == 1:
+            bits, xi = orc.encode_sign(xp)
+            y = 2.0 * bits - 1.0
+        else:
+            u, xi = orc.encode_ext(xp, B)
+            y = u - h
+        e = (y @ qp) / (np.linalg.norm(y) * xi)
+        est.append(e)
+        for eps0 in fails:
+            if abs(e - truth) > math.sqrt((1 - xi ** 2) / xi ** 2) * eps0 / math.sqrt(d - 1):
+                fails[eps0] += 1
+    est = np.array(est)
+    assert abs(est.mean() - truth) < 4 * est.std() / math.sqrt(M)
+    # Eq 5: the failure rate falls as eps0 grows (c0 unknown: the constant itself is unpinned)
+    assert fails[1.0] >= fails[1.9] >= fails[3.0]
+    assert fails[3.0] / M < 0.01
+
+
+def test_haar_orthogonal(orc):
+    for d in (8, 64):
+        P = orc.haar(d, 77)
+        assert np.abs(P.T @ P - np.eye(d)).max() < 1e-12
+        assert np.abs(P @ P.T - np.eye(d)).max() < 1e-12
+
+
+@pytest.mark.parametrize("d,B", [(2, 2), (3, 2), (3, 3), (4, 2), (4, 3)])
+def test_ext_code_matches_exhaustive_search(orc, d, B):
+    rng = np.random.default_rng(100 * d + B)
+    for _ in range(40):
+        x = rng.standard_normal(d); x /= np.linalg.norm(x)
+        u, xi = orc.encode_ext(x, B)
+        _, best = orc.ext_exhaustive(x, B)
+        assert abs(xi - best) <= 1e-12
+        half = 1 << (B - 1)
+        assert np.array_equal(u >= half, x >= 0)            # top bit = sign bit
+        assert u.max() < (1 << B)
+
+
+def test_ext_one_bit_reduces_to_sign_code(orc):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(32); x /= np.linalg.norm(x)
+    u, xi = orc.encode_ext(x, 1)
+    bits, xi1 = orc.encode_sign(x)
+    assert np.array_equal(u, bits) and abs(xi - xi1) < 1e-15
+
+
+# ---- query quantisation (Algorithm 2, query quantisation) ------------------------------------------
+
+def test_query_quantizer_invariants(orc):
+    rng = np.random.default_rng(2)
+    for bq in (1, 2, 4, 8):
+        for _ in range(50):
+            q = rng.standard_normal(64).astype(np.float32)
+            q /= np.float32(np.linalg.norm(q))
+            u, vl, dl, su = orc.quantize_query_f32(q, bq)
+            assert u.max() <= (1 << bq) - 1 and su == int(u.astype(np.int64).sum())
+            assert vl == q.min()
+            qbar = np.float64(vl) + np.float64(dl) * u
+            assert np.abs(qbar - q).max() <= 0.5 * np.float64(dl) * (1 + 1e-5) + 1e-7
+    u, vl, dl, su = orc.quantize_query_f32(np.full(16, 0.25, np.float32), 4)
+    assert dl == 1.0 and su == 0 and not u.any()
+
+
+def test_popcount_identity_on_trace(orc):
+    """sum_i (2 b_i - 1) qbar_i = Delta (2 sum b_i u_i - S_u) + v_l (2 popcount(b) - d), the
+    identity that turns the estimator's inner product into bit counts (Section 4.2)."""
+    X, Q, _ = small_data(N=600, D=32, cluster_dims=6)
+    ix = orc.Index.build(X, d=32, B=1, nlist=4)
+    code, off = ix.get("code"), ix.get("off")
+    qs, qprime, u, ids, cand = ix.pair_trace(Q[1], 2)
+    b = code[off[2]:off[3]].astype(np.int64)
+    ip = (b * u).sum(1)
+    pc = b.sum(1)
+    assert np.array_equal(ip, cand["ip"].astype(np.int64)) and np.array_equal(pc, cand["pc"])
+    qbar = np.float64(qs["vl"]) + np.float64(qs["delta"]) * u
+    lhs = ((2 * b - 1) * qbar).sum(1)
+    rhs = qs["delta"] * (2 * ip - qs["su"]) + qs["vl"] * (2 * pc - 32)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+# ---- k-means (Algorithm 1, IVF step) ------------------------------------------------------------
+
+def test_kmeans_fixed_point(orc):
+    rng = np.random.default_rng(4)
+    P = np.concatenate([rng.standard_normal((200, 3)) + 6 * rng.standard_normal(3) for _ in range(5)])
+    C, a = orc.kmeans(P, 5, seed=99, iters=100)
+    d2 = ((P[:, None, :] - C[None]) ** 2).sum(-1)
+    assert np.array_equal(a, np.argmin(d2, axis=1))
+    for j in range(5):
+        assert (a == j).any()
+        assert np.allclose(C[j], P[a == j].mean(0), rtol=1e-12, atol=1e-12)
+
+
+# ---- the search (Algorithm 2) --------------------------------------------------------------------
+
+def test_exact_ivf_all_lists_is_bruteforce(orc):
+    X, Q, _ = small_data(N=1500, D=32, cluster_dims=6)
+    ix = orc.Index.build(X, d=8, B=1, nlist=10)
+    gt, gd = orc.bruteforce(X, Q, 10)
+    ids, dd = ix.search_many(Q, 10, 10, mode=orc.EXACT_IVF)
+    assert np.array_equal(ids, gt) and np.allclose(dd, gd, rtol=0, atol=0)
+
+
+def test_bruteforce_matches_numpy(orc):
+    X, Q, _ = small_data(N=700, D=24, cluster_dims=4)
+    ids, dd = orc.bruteforce(X, Q, 7)
+    D2 = ((X[None].astype(np.float64) - Q[:, None].astype(np.float64)) ** 2).sum(-1)
+    ref = np.argsort(D2, axis=1, kind="stable")[:, :7]
+    assert np.array_equal(ids, ref)
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_alg2_without_pruning_equals_exact_ivf(orc, B):
+    X, Q, _ = small_data(N=2000, D=32, cluster_dims=6)
+    ix = orc.Index.build(X, d=16, B=B, nlist=12)
+    loose = orc.params(eps0=1e9, m=1e9)
+    for qi in range(Q.shape[0]):
+        a, ad = ix.search(Q[qi], 10, 4, mode=orc.ALG2, prm=loose)
+        e, ed = ix.search(Q[qi], 10, 4, mode=orc.EXACT_IVF)
+        assert np.array_equal(a, e) and np.array_equal(ad, ed)
+
+
+@pytest.mark.parametrize("B,stage2", [(1, True), (1, False), (4, True)])
+def test_alg2_equals_exact_ivf_when_no_bound_fails(orc, B, stage2):
+    """Whenever no applied bound fails, the multi-stage search returns the exact top-k of the probed
+    lists, whatever tau's history (Algorithm 2 with Eq 4-7)."""
+    X, Q, _ = small_data(N=3000, D=48)
+    ix = orc.Index.build(X, d=16, B=B, nlist=16)
+    prm = orc.params(verify=True, stage2=stage2)
+    clean = 0
+    for qi in range(Q.shape[0]):
+        a, ad, cnt = ix.search(Q[qi], 10, 6, mode=orc.ALG2, prm=prm, counters=True)
+        e, ed = ix.search(Q[qi], 10, 6, mode=orc.EXACT_IVF)
+        assert cnt["pass2"] <= cnt["pass_ext"] <= cnt["pass1"] <= cnt["scanned"]
+        bad = cnt["viol1"] + (cnt["viol_ext"] if B > 1 else 0) + (cnt["viol2"] if stage2 else 0)
+        if bad == 0:
+            clean += 1
+            assert np.array_equal(a, e) and np.array_equal(ad, ed)
+        else:  # any returned id is still a genuine candidate with its exact distance
+            ok = a >= 0
+            assert np.all(np.isin(a[ok], ix.get("lid")))
+            assert np.all(ad[ok] >= ed[ok] - 1e-9)
+    assert clean >= Q.shape[0] // 4
+
+
+def test_pruning_saves_exact_distances(orc):
+    X, Q, _ = small_data(N=4000, D=64, cluster_dims=8)
+    ix = orc.Index.build(X, d=32, B=1, nlist=16)
+    tot = {"scanned": 0, "pass1": 0, "pass2": 0}
+    for qi in range(Q.shape[0]):
+        _, _, c = ix.search(Q[qi], 10, 6, counters=True)
+        for k in tot:
+            tot[k] += c[k]
+    assert tot["pass1"] < 0.6 * tot["scanned"]             # stage 1 prunes (Algorithm 2, first test)
+    assert tot["pass2"] < 0.5 * tot["pass1"]               # stage 2 prunes further (Eq 7)
+    for qi in range(3):                                    # MRQ without stage 2: pass2 == pass_ext
+        _, _, c = ix.search(Q[qi], 10, 6, counters=True, prm=orc.params(stage2=False))
+        assert c["pass2"] == c["pass_ext"] == c["pass1"]
+
+
+def test_padding_when_fewer_candidates_than_k(orc):
+    X, Q, _ = small_data(N=200, D=16, cluster_dims=4)
+    ix = orc.Index.build(X, d=8, B=1, nlist=40)
+    lists, _ = ix.probe(Q[0], 1)
+    off = ix.get("off")
+    n = int(off[lists[0] + 1] - off[lists[0]])
+    ids, dd = ix.search(Q[0], n + 5, 1)
+    assert np.all(ids[n:] == -1) and np.all(np.isinf(dd[n:]))
+    assert np.all(ids[:n] >= 0)
+
+
+@pytest.mark.parametrize("B", [1, 4])
+def test_eq4_eq5_stage1_values_from_definitions(orc, B):
+    """Stage-1 values against Eq 4 and Eq 5 evaluated in the unrotated d-space: the quantised data
+    vector is xbar = P_r y/||y|| (y = 2b - 1 for the sign code, y = u - h for B bits), the quantised
+    query is P_r qbar' with qbar' = v_l + Delta u, and <xbar, x_b> is an explicit inner product."""
+    X, Q, _ = small_data(N=1200, D=40, cluster_dims=6)
+    d = 20
+    ix = orc.Index.build(X, d=d, B=B, nlist=5)
+    P, mu, Cc, Pr = ix.get("Pp"), ix.get("mu"), ix.get("C"), ix.get("Pr")
+    code, off = ix.get("code"), ix.get("off")
+    Xp = (X.astype(np.float64) - mu) @ P.T
+    eps0, m = 1.9, 3.0
+    prm = orc.params(eps0=eps0, m=m)
+    h = ((1 << B) - 1) / 2
+    for qi in range(3):
+        qp = (Q[qi].astype(np.float64) - mu) @ P.T
+        for j in range(ix.nlist):
+            qs, qprime, u, ids, cand = ix.pair_trace(Q[qi], j, prm)
+            c = Cc[j]
+            n_q = np.linalg.norm(qp[:d] - c)
+            assert np.allclose(qprime, Pr.T @ (qp[:d] - c) / n_q, rtol=0, atol=1e-12)
+            qbar = Pr @ (np.float64(qs["vl"]) + np.float64(qs["delta"]) * u)   # back in d-space
+            cw = code[off[j]:off[j + 1]].astype(np.float64)
+            xd = Xp[ids, :d]
+            n_x = np.linalg.norm(xd - c, axis=1)
+            xb = (xd - c) / n_x[:, None]
+            C1 = n_x ** 2 + n_q ** 2 + (Xp[ids, d:] ** 2).sum(1) + (qp[d:] ** 2).sum()
+            sig = math.sqrt((ix.get("lam")[d:] * qp[d:] ** 2).sum())
+            for yv, key in (((cw >= (1 << (B - 1))) * 2.0 - 1.0, "1"), (cw - h, "B")):
+                xbar = (yv @ Pr.T) / np.linalg.norm(yv, axis=1, keepdims=True)
+                align = (xbar * xb).sum(1)                                   # <xbar, x_b>
+                est = (xbar @ qbar) / align
+                dis = C1 - 2 * n_x * n_q * est                               # Eq 4
+                eb = 2 * n_x * n_q * np.sqrt(1 - align ** 2) / align * eps0 / math.sqrt(d - 1)
+                lb = dis - eb - 2 * m * sig
+                assert np.allclose(cand["dis" + key], dis, rtol=1e-9, atol=1e-9)
+                assert np.allclose(cand["eb" + key], eb, rtol=1e-8, atol=1e-9)
+                assert np.allclose(cand["lb" + key], lb, rtol=1e-9, atol=1e-9)
