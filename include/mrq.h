@@ -1,0 +1,177 @@
+/*
+ * mrq.h — C ABI of the MI355X (gfx950) MRQ search library.
+ *
+ * MRQ ("Quantization Meets Projection", arXiv 2411.06158) answers approximate k-NN queries under
+ * squared Euclidean distance (Section 2.1) with an IVF index over PCA-projected vectors whose leading
+ * d_r dimensions carry RaBitQ-style codes (Section 4, Algorithm 1) and a three-stage query
+ * (Algorithm 2 with Eq 4-7): a bit-code estimate with error bounds, the projected distance, then the
+ * exact distance for the survivors.
+ *
+ * Conventions for every entry point:
+ *   - Vectors are row-major FP32 (row stride = D floats).  X, Q and the output buffers may be device
+ *     pointers (e.g. torch's data_ptr() of a CUDA tensor) or ordinary host pointers; the kind is
+ *     detected per call.  The caller owns them.  The library owns the index and all its device
+ *     memory.
+ *   - A `stream` of NULL means the legacy default stream.  Calls are asynchronous on `stream` unless
+ *     documented otherwise; device outputs are valid once the stream has been synchronised.  Host
+ *     outputs are complete when the call returns.
+ *   - Distances are squared L2 (Eq 1), ascending; ties are broken by the smaller id.  When fewer
+ *     than k candidates exist the tail of a result row is padded with id = -1, dist = +inf.
+ *   - Every call returns an mrq_status; the message of the last failure on the calling thread is
+ *     available from mrq_last_error().  No exception crosses the ABI.
+ *   - Calls that use the same index from several host threads must not overlap (the index holds the
+ *     search workspace); different indexes are independent.
+ *
+ * On-disk formats (little-endian) written by mrq_save / mrq_export:
+ *   "MRQX0001" export layout, field by field:
+ *     char magic[8]; int64 N; int32 D, d, B, nlist;
+ *     f32 mu[D]; f32 Pp[D*D] (row i = i-th principal axis, eigenvalues descending);
+ *     f64 lambda[D]; f32 Pr[d*d] (row-major, x' = Pr^T (x_d - c)/||x_d - c||);
+ *     f32 C[nlist*d]; i64 off[nlist+1]; i64 ids[N] (list order, ascending id inside a list);
+ *     u8 code[N*d] (per leading dim the level index u in [0, 2^B), top bit = sign bit);
+ *     f32 xd[N*d]; f32 nx[N], tx[N], ax[N], xi1[N], xiB[N], yn[N]   (all in list order)
+ *   where nx = ||x_d - c||, tx = ||x_r||^2, ax = ||x - mu||^2, xi1 = <xbar_1bit, x_b>,
+ *   xiB = <xbar_Bbit, x_b>, yn = ||u - (2^B - 1)/2||.
+ */
+#ifndef MRQ_H
+#define MRQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrq_index mrq_index;   /* opaque, library-owned */
+typedef struct mrq_server mrq_server; /* opaque, library-owned */
+typedef void *mrq_stream;             /* a hipStream_t */
+
+typedef enum {
+    MRQ_OK = 0,
+    MRQ_EINVAL = 1,  /* an argument is out of range, a pointer is NULL or an input is not finite */
+    MRQ_ENOMEM = 2,  /* device or host allocation failed */
+    MRQ_EDEVICE = 3, /* a HIP runtime call failed */
+    MRQ_ESTATE = 4,  /* the object is not in a state that allows the call */
+    MRQ_EIO = 5      /* file could not be read / written or has the wrong format */
+} mrq_status;
+
+enum { MRQ_BATCHED = 0, MRQ_PER_QUERY = 1 };
+
+typedef struct {
+    uint64_t seed;        /* k-means initialisation and the random rotation P_r; default 4001 */
+    int32_t kmeans_iters; /* Lloyd iterations (stops early when no assignment changes); default 25 */
+    int32_t reserved[7];
+} mrq_build_opts;
+
+typedef struct {
+    int32_t mode;           /* MRQ_BATCHED (default) or MRQ_PER_QUERY (one query per pipeline pass) */
+    int32_t bq;             /* query code bits B_q in [1, 8]; default 4 (Algorithm 2, quantise q) */
+    float eps0;             /* Eq 5 confidence parameter; default 1.9; <= 0 selects the default */
+    float m;                /* Eq 6 / Chebyshev multiplier; eps_r = 2 m sigma; default 3 */
+    int32_t stage2;         /* 1 = use the Eq 7 projected-distance stage (MRQ+), 0 = plain MRQ; default 1 */
+    int32_t use_ext;        /* 1 = refine stage-1 survivors with the B-bit code when B > 1; default 1 */
+    int64_t *counters;      /* optional device or host int64[8]: scanned, pass1, pass_ext, pass2,
+                               seed_exact, items, 0, 0 (accumulated, not cleared) */
+    int32_t group;          /* queries per scan work item (0 = autotuned) */
+    int32_t reserved[5];
+} mrq_search_opts;
+
+/* Defaults for the option structs (pass NULL to any call to use them). */
+void mrq_build_opts_default(mrq_build_opts *o);
+void mrq_search_opts_default(mrq_search_opts *o);
+
+/*
+ * mrq_build — Algorithm 1 (Section 5.1): PCA of X (mean-centred, FP64 covariance), residual
+ * variances lambda_i, rotation x_p = P_p (x - mu), residual norms ||x_r||, IVF with nlist lists
+ * trained on the leading d_r coordinates x_d, and the per-vector code of (x_d - c)/||x_d - c|| under
+ * a random orthogonal P_r (Section 4.2) with B bits per leading dimension (B = 1: sign code; B > 1:
+ * extended code whose top bit is the sign bit), plus the normalisation factors ||x_d - c||,
+ * ||x_r||, <xbar, x_b>.  The original vectors are copied into the index for the exact stage.
+ *   X      N x D FP32, host or device, finite values only (checked: MRQ_EINVAL otherwise)
+ *   d_r    in [2, D];  bits B in [1, 8];  nlist in [1, N]
+ *   stream where the device work runs; the call synchronises it before returning
+ *   out    receives a new index on MRQ_OK (free with mrq_free); untouched on failure
+ */
+mrq_status mrq_build(const float *X, int64_t N, int32_t D, int32_t d_r, int32_t bits, int32_t nlist,
+                     const mrq_build_opts *opts, mrq_stream stream, mrq_index **out);
+
+/*
+ * mrq_search — Algorithm 2 with the Eq 7 stage for nq queries at once: project each query with
+ * P_p (Algorithm 2, first steps), compute sigma of Eq 6, rank the centroids by distance to q_d and
+ * take the nprobe nearest lists, quantise the normalised and rotated q_d per (query, list) pair,
+ * then for every candidate: estimate (Eq 4), prune with the bound of Eq 5 plus the residual bound
+ * (Eq 6), re-check with Eq 7, and compute the exact distance for the survivors.
+ *   Q      nq x D FP32 (host or device);  nq >= 1;  1 <= k <= 1024;  1 <= nprobe <= min(nlist, 1024)
+ *   ids    nq x k int64 output (host or device);  dists  nq x k FP32 output (host or device)
+ * The result of a query does not depend on the other queries of the batch nor on `mode`.
+ */
+mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe,
+                      int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
+
+/*
+ * mrq_search_mixed — as mrq_search, with a per-query k[i] and nprobe[i] (host or device int32
+ * arrays of nq entries) in one launch.  Results of query i are written at ids + out_off[i] and
+ * dists + out_off[i] (k[i] entries); out_off is an int64 array of nq entries (host or device).
+ */
+mrq_status mrq_search_mixed(const mrq_index *index, const float *Q, int64_t nq, const int32_t *k,
+                            const int32_t *nprobe, const int64_t *out_off, int64_t *ids, float *dists,
+                            const mrq_search_opts *opts, mrq_stream stream);
+
+/* Index shape: any pointer may be NULL. */
+mrq_status mrq_index_info(const mrq_index *index, int64_t *N, int32_t *D, int32_t *d_r, int32_t *bits,
+                          int32_t *nlist, int64_t *device_bytes);
+
+/* Write the index in the "MRQX0001" layout above (lossless for everything the search reads except
+ * the copy of the original vectors, which the caller keeps).  Synchronous. */
+mrq_status mrq_export(const mrq_index *index, const char *path);
+
+/* Persist / restore a complete index ("MRQS0001": the export layout followed by the original
+ * vectors in list order).  mrq_load allocates on the current device.  Synchronous. */
+mrq_status mrq_save(const mrq_index *index, const char *path);
+mrq_status mrq_load(const char *path, mrq_index **out);
+
+/* Release an index and all its device memory.  NULL is ignored. */
+void mrq_free(mrq_index *index);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mrq_last_error(void);
+
+/*
+ * Per-kernel device time of the last search calls on this index, measured with HIP events recorded
+ * on the search stream around each kernel.  names: a '\n'-separated list written into `names`
+ * (capacity `cap` bytes); ms[i] / launches[i] accumulate per kernel; returns the kernel count, or
+ * -1 on error.  mrq_timing_enable(index, 1) turns the events on (off by default), 0 off; reset
+ * clears the accumulators.
+ */
+int mrq_timing(const mrq_index *index, char *names, size_t cap, double *ms, int64_t *launches, int max);
+mrq_status mrq_timing_enable(mrq_index *index, int on, int reset);
+
+/*
+ * Serving (continuous batching).  A server owns a host thread that packs submitted requests into
+ * batches of at most max_slots queries, admits a request only when the worst-case device memory of
+ * its batch fits `mem_budget` bytes, runs batches on two streams so that a new batch starts while
+ * the previous one is still on the device, and hands back results through mrq_server_poll.
+ *   mrq_server_create: mem_budget 0 = no limit; max_slots in [1, 65536]
+ *   mrq_server_submit: q_host is D floats (copied); returns MRQ_EINVAL for bad k / nprobe and
+ *                      MRQ_ENOMEM only when the request could never fit the budget; otherwise it is
+ *                      queued until it can be admitted
+ *   mrq_server_poll:   copies up to max_done finished results (ids and dists rows of k_max entries,
+ *                      k_max = the largest k the server accepts = 1024 -> the caller passes rows of
+ *                      `row` entries) and returns how many were written, -1 on error
+ */
+mrq_status mrq_server_create(const mrq_index *index, size_t mem_budget, int32_t max_slots,
+                             const mrq_search_opts *opts, mrq_server **out);
+mrq_status mrq_server_submit(mrq_server *server, uint64_t req_id, const float *q_host, int32_t k,
+                             int32_t nprobe);
+int mrq_server_poll(mrq_server *server, uint64_t *req_ids, int32_t *ks, int64_t *ids, float *dists,
+                    int32_t row, int32_t max_done, double *latency_ms);
+/* Wait until every submitted request has finished (or timeout_ms elapsed); returns MRQ_ESTATE on
+ * timeout. */
+mrq_status mrq_server_drain(mrq_server *server, int64_t timeout_ms);
+void mrq_server_destroy(mrq_server *server);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRQ_H */

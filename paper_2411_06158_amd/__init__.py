@@ -1,0 +1,215 @@
+"""MRQ approximate k-NN search on MI355X (gfx950): ctypes binding of libmrq.so.
+
+The binding only marshals arguments: every step of index build and search runs in the library's
+HIP kernels.  Arrays may be numpy arrays (host) or torch tensors on the GPU (device); torch streams
+are passed through as hipStream_t.  The entry points keep the C names of include/mrq.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrq.so")
+
+MRQ_OK, MRQ_EINVAL, MRQ_ENOMEM, MRQ_EDEVICE, MRQ_ESTATE, MRQ_EIO = range(6)
+MRQ_BATCHED, MRQ_PER_QUERY = 0, 1
+
+EXPORTED = [
+    "mrq_build_opts_default", "mrq_search_opts_default", "mrq_build", "mrq_search", "mrq_search_mixed",
+    "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
+    "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
+    "mrq_server_destroy",
+]
+
+
+class MRQError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mrq status {status}: {msg}")
+        self.status = status
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("kmeans_iters", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class SearchOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("bq", C.c_int32), ("eps0", C.c_float), ("m", C.c_float),
+                ("stage2", C.c_int32), ("use_ext", C.c_int32), ("counters", C.c_void_p),
+                ("group", C.c_int32), ("reserved", C.c_int32 * 5)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmrq.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_06158_amd.build_lib.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.mrq_build_opts_default.argtypes = [C.POINTER(BuildOpts)]
+        L.mrq_search_opts_default.argtypes = [C.POINTER(SearchOpts)]
+        L.mrq_build.argtypes = [P, I64, I32, I32, I32, I32, C.POINTER(BuildOpts), P, C.POINTER(P)]
+        L.mrq_search.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
+        L.mrq_search_mixed.argtypes = [P, P, I64, P, P, P, P, P, C.POINTER(SearchOpts), P]
+        L.mrq_index_info.argtypes = [P, P, P, P, P, P, P]
+        L.mrq_export.argtypes = [P, C.c_char_p]
+        L.mrq_save.argtypes = [P, C.c_char_p]
+        L.mrq_load.argtypes = [C.c_char_p, C.POINTER(P)]
+        L.mrq_free.argtypes = [P]
+        L.mrq_free.restype = None
+        L.mrq_last_error.restype = C.c_char_p
+        L.mrq_timing.argtypes = [P, C.c_char_p, C.c_size_t, P, P, C.c_int]
+        L.mrq_timing.restype = C.c_int
+        L.mrq_timing_enable.argtypes = [P, C.c_int, C.c_int]
+        if hasattr(L, "mrq_server_create"):
+            L.mrq_server_create.argtypes = [P, C.c_size_t, I32, C.POINTER(SearchOpts), C.POINTER(P)]
+            L.mrq_server_submit.argtypes = [P, C.c_uint64, P, I32, I32]
+            L.mrq_server_poll.argtypes = [P, P, P, P, P, I32, I32, P]
+            L.mrq_server_poll.restype = C.c_int
+            L.mrq_server_drain.argtypes = [P, I64]
+            L.mrq_server_destroy.argtypes = [P]
+            L.mrq_server_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MRQ_OK:
+        raise MRQError(status, lib().mrq_last_error().decode(errors="replace"))
+
+
+def _ptr(a) -> int:
+    """Raw pointer of a numpy array or a torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return a.data_ptr()
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=True, counters=None,
+                group=0) -> SearchOpts:
+    o = SearchOpts()
+    lib().mrq_search_opts_default(C.byref(o))
+    o.mode, o.bq, o.eps0, o.m = int(mode), int(bq), float(eps0), float(m)
+    o.stage2, o.use_ext, o.group = int(bool(stage2)), int(bool(use_ext)), int(group)
+    o.counters = _ptr(counters) if counters is not None else None
+    return o
+
+
+class Index:
+    """An MRQ index living in GPU memory (owned by the library)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        N, D, d, B, L, nb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().mrq_index_info(self._h, C.byref(N), C.byref(D), C.byref(d), C.byref(B), C.byref(L),
+                                    C.byref(nb)))
+        self.N, self.D, self.d, self.B, self.nlist, self.device_bytes = (
+            N.value, D.value, d.value, B.value, L.value, nb.value)
+
+    @classmethod
+    def build(cls, X, d_r: int, bits: int, nlist: int, seed: int = 4001, kmeans_iters: int = 25,
+              stream=None) -> "Index":
+        o = BuildOpts()
+        lib().mrq_build_opts_default(C.byref(o))
+        o.seed, o.kmeans_iters = seed, kmeans_iters
+        h = C.c_void_p()
+        N, D = int(X.shape[0]), int(X.shape[1])
+        _check(lib().mrq_build(_ptr(X), N, D, d_r, bits, nlist, C.byref(o), _stream(stream), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        h = C.c_void_p()
+        _check(lib().mrq_load(path.encode(), C.byref(h)))
+        return cls(h)
+
+    def save(self, path: str):
+        _check(lib().mrq_save(self._h, path.encode()))
+
+    def export(self, path: str):
+        _check(lib().mrq_export(self._h, path.encode()))
+
+    def search(self, Q, k: int, nprobe: int, ids=None, dists=None, opts: Optional[SearchOpts] = None,
+               stream=None, **kw):
+        """Top-k ids (int64, -1 padded) and squared distances (float32, +inf padded) per query.
+
+        Q, ids and dists are all numpy (host) or all torch CUDA tensors (device); with device
+        tensors the call is asynchronous on `stream`."""
+        nq = int(Q.shape[0])
+        if ids is None or dists is None:
+            if isinstance(Q, np.ndarray):
+                ids = np.empty((nq, k), dtype=np.int64)
+                dists = np.empty((nq, k), dtype=np.float32)
+            else:
+                import torch
+                ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+                dists = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        o = opts if opts is not None else search_opts(**kw)
+        _check(lib().mrq_search(self._h, _ptr(Q), nq, k, nprobe, _ptr(ids), _ptr(dists), C.byref(o),
+                                _stream(stream)))
+        return ids, dists
+
+    def search_mixed(self, Q, k, nprobe, opts: Optional[SearchOpts] = None, stream=None, **kw):
+        """Per-query k[i] / nprobe[i]; returns (ids, dists, out_off) as flat host arrays."""
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        nprobe = np.ascontiguousarray(nprobe, dtype=np.int32)
+        off = np.zeros(len(k), dtype=np.int64)
+        off[1:] = np.cumsum(k[:-1].astype(np.int64))
+        tot = int(k.astype(np.int64).sum())
+        ids = np.empty(tot, dtype=np.int64)
+        dists = np.empty(tot, dtype=np.float32)
+        o = opts if opts is not None else search_opts(**kw)
+        _check(lib().mrq_search_mixed(self._h, _ptr(Q), len(k), _ptr(k), _ptr(nprobe), _ptr(off), _ptr(ids),
+                                      _ptr(dists), C.byref(o), _stream(stream)))
+        return ids, dists, off
+
+    def timing_enable(self, on: bool = True, reset: bool = True):
+        _check(lib().mrq_timing_enable(self._h, int(on), int(reset)))
+
+    def timing(self) -> dict:
+        buf = C.create_string_buffer(4096)
+        ms = (C.c_double * 64)()
+        n = (C.c_int64 * 64)()
+        cnt = lib().mrq_timing(self._h, buf, 4096, ms, n, 64)
+        names = buf.value.decode().split("\n")[:cnt]
+        return {nm: (ms[i], n[i]) for i, nm in enumerate(names)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mrq_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

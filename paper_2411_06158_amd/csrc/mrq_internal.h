@@ -1,0 +1,177 @@
+// Internal definitions shared by the host runtime and the HIP kernels of the MRQ library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mrq.h"
+
+namespace mrq {
+
+constexpr int kWave = 64;        // gfx950 wavefront width
+constexpr int kBlockVecs = 64;   // vectors per code block = one vector per lane
+constexpr int kPhases = 6;       // probe-rank phases: {0}, [1,4), [4,16), [16,64), [64,256), [256,1024)
+constexpr int kMaxK = 1024;
+constexpr int kMaxProbe = 1024;
+constexpr uint64_t kEmptyKey = ~0ull;
+
+// Per (query, list) pair: everything the stage-1 test needs besides the bit planes, read by the
+// scan through the scalar unit (12 dwords).
+struct PairRec {
+    int32_t q;       // query index in the batch
+    int32_t list;    // IVF list id
+    float Kr;        // ||q_d - c||^2 + ||q_r||^2 - eps_r  (query part of C1 minus the residual radius)
+    float two_nq;    // 2 ||q_d - c||
+    float vl;        // quantised query: lowest level
+    float delta;     // quantised query: level step
+    float su;        // sum of the query levels (exact integer)
+    float ebc;       // 2 ||q_d - c|| eps0 / sqrt(d - 1)
+    float tau;       // pruning threshold of the query for the current phase
+    float er;        // eps_r = 2 m sigma of the query (Eq 6)
+    float pad0, pad1;
+};
+static_assert(sizeof(PairRec) == 48, "PairRec layout");
+
+// Code words per row: the smallest instantiated width >= ceil(d / 32).
+int padded_words(int d);
+
+struct KernelTimer {
+    bool on = false;
+    std::vector<std::string> names;
+    std::vector<double> ms;
+    std::vector<int64_t> launches;
+    struct Pending { int slot; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int slot_of(const char* name);
+    void begin(hipStream_t s, const char* name, Pending* p);
+    void end(hipStream_t s, Pending* p);
+    void collect();   // synchronises on the recorded events and accumulates
+    ~KernelTimer();
+};
+
+struct Workspace {
+    // grow-only device scratch for one search call
+    void* base = nullptr;
+    size_t bytes = 0;
+};
+
+struct Index {
+    int64_t N = 0;
+    int32_t D = 0, d = 0, B = 1, nlist = 0;
+    int32_t W = 0, WP = 0;       // code words per row: needed / stored (padded)
+    int32_t d4 = 0, D4 = 0;      // d and D rounded up to a multiple of 4 (padded row strides)
+    int64_t Npad = 0;            // rows after padding every list to a multiple of 64
+    int device = 0;
+
+    // device arrays
+    float* mu = nullptr;         // D
+    float* Pp = nullptr;         // D x D, row i = axis i
+    float* PpLead = nullptr;     // d x D (rows 0..d-1 of Pp), contiguous
+    float* PpTail = nullptr;     // (D - d) x D
+    float* lamTail = nullptr;    // D - d
+    float* PrT = nullptr;        // d4 x d4: row j = column j of P_r (zero padded)
+    float* C = nullptr;          // nlist x d4 centroids (zero padded)
+    float* Cn2 = nullptr;        // nlist: ||c_j||^2
+    float* RC = nullptr;         // nlist x d4: P_r^T c_j
+    int64_t* list_off = nullptr; // nlist + 1 padded row offsets
+    int32_t* list_len = nullptr; // nlist real lengths
+    int32_t* list_nb = nullptr;  // nlist: 64-row blocks per list
+    int32_t* ids = nullptr;      // Npad, -1 on padding rows
+    uint32_t* code = nullptr;    // Npad x WP sign plane
+    uint32_t* ext = nullptr;     // Npad x (B - 1) x WP lower planes of the B-bit code
+    float* fA = nullptr;         // Npad: ||x_d - c||^2 + ||x_r||^2 (+inf on padding rows)
+    float* fF = nullptr;         // Npad: ||x_d - c|| / (sqrt(d) xi1)
+    float* fE = nullptr;         // Npad: ||x_d - c|| sqrt(1 - xi1^2) / xi1
+    float* fFB = nullptr;        // Npad: ||x_d - c|| / (2 ||y|| xiB)
+    float* fEB = nullptr;        // Npad: ||x_d - c|| sqrt(1 - xiB^2) / xiB
+    float* fSX = nullptr;        // Npad: 2 sum_i u_i - (2^B - 1) d
+    float* xd = nullptr;         // Npad x d4 leading coordinates of x_p
+    float* ax = nullptr;         // Npad: ||x - mu||^2
+    float* X = nullptr;          // Npad x D4 original vectors in list order
+    // export-only per-row summaries (list order)
+    float *nx = nullptr, *tx = nullptr, *xi1 = nullptr, *xiB = nullptr, *yn = nullptr;
+
+    // host copies
+    std::vector<double> lam64;
+    std::vector<int64_t> h_off_real;   // nlist + 1 unpadded offsets (export)
+    std::vector<int64_t> h_list_off;   // nlist + 1 padded offsets
+    int32_t max_list_len = 0;
+
+    std::vector<void*> allocations;
+    int64_t device_bytes = 0;
+
+    // search workspace (grow-only) and instrumentation
+    mutable Workspace ws;
+    mutable KernelTimer timer;
+    mutable std::mutex mu_ws;
+    int group_default = 32;
+
+    ~Index();
+};
+
+// ---- kernels (defined in mrq_search.hip and mrq_build.hip) --------------------------------------------------------
+struct SearchArgs {
+    const Index* ix;
+    const float* Q;        // device nq x D
+    int64_t nq;
+    const int32_t* kq;     // device nq
+    const int32_t* npq;    // device nq
+    const int64_t* slot_off;   // device nq + 1
+    const int64_t* pair_off;   // device nq + 1
+    const int64_t* out_off;    // device nq
+    int64_t total_slots, total_pairs;
+    int32_t np_max, k_max;
+    int32_t bq;
+    float eps0, m;
+    int32_t stage2, use_ext, group;
+    int64_t* ids;          // device output
+    float* dists;          // device output
+    int64_t* counters;     // device int64[8] or null
+};
+
+size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,
+                              int bq);
+hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
+
+// build-side launchers
+hipError_t launch_colmean(const float* X, int64_t N, int D, double* part, int nchunk, double* mu64,
+                          hipStream_t s);
+hipError_t launch_cov(const float* X, int64_t N, int D, const double* mu64, double* part, int nsplit,
+                      double* S, hipStream_t s);
+int cov_splits(int64_t N, int D);
+hipError_t launch_gemm_nt(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
+                          float* Cm, int64_t ldc, int64_t M, int N, int K, hipStream_t s);
+hipError_t launch_rownorms(const float* X, int64_t N, int D, const double* mu64, const float* xd,
+                           int d4, int d, double* ax64, double* tx64, hipStream_t s);
+hipError_t launch_kmeans_assign(const float* P, int64_t n, int ldp, int dim, const float* C, int ldc,
+                                const float* cn2, int k, const float* pn2, int32_t* assign, float* mind,
+                                hipStream_t s);
+hipError_t launch_kmeans_accum(const float* P, int64_t n, int ldp, int dim, const int32_t* assign,
+                               const int32_t* prev, double* sums, int32_t* cnt, int32_t* changed,
+                               hipStream_t s);
+hipError_t launch_kmeans_centroids(const double* sums, const int32_t* cnt, int k, int dim, float* C,
+                                   int ldc, float* cn2, hipStream_t s);
+hipError_t launch_sqnorms(const float* A, int64_t n, int lda, int dim, float* out, hipStream_t s);
+hipError_t launch_gather_layout(const Index& ix, const float* Xuser, const int32_t* perm,
+                                const float* xd_id, const double* ax64, const double* tx64, double* txr,
+                                int32_t* row_list, float* O, hipStream_t s);
+hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, const double* tx64_rows,
+                         hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_uniform_meta(int64_t nq, int k, int np, int32_t* kq, int32_t* npq, int64_t* slot_off,
+                               int64_t* pair_off, int64_t* out_off, hipStream_t s);
+hipError_t launch_gather_rows(const float* src, int64_t lds, const int32_t* idx, int64_t n, int dim,
+                              float* dst, int64_t ldd, hipStream_t s);
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_check_finite(const float* X, int64_t n, int32_t* bad, hipStream_t s);
+
+// host eigensolver (eigen_host.cpp): symmetric n x n (row-major) -> eigenvalues descending and
+// eigenvectors as rows, sign rule: largest-magnitude entry positive.
+void eigh_host(const double* A, int n, double* evals, double* evecs_rows);
+
+}  // namespace mrq

@@ -1,0 +1,1165 @@
+// Query-time kernels of the MRQ search path (Algorithm 2 with Eq 4-7 of arXiv 2411.06158), written
+// for gfx950: 64-wide wavefronts, one candidate vector per lane in the bit-code scan, per-(query, list)
+// query codes read through the scalar unit, survivors compacted by ballot into a per-wave LDS queue,
+// and per-query top-k kept in global memory as a sorted array of 64-bit (distance, id) keys updated
+// with atomicMin chains.
+//
+// Batch independence: every value a query's result depends on (projection, probe ranking, query
+// codes, stage values, exact distances, the pruning thresholds) is computed by a fixed sequence of
+// operations that depends only on that query, so a query returns bit-identical results alone, in any
+// batch, and on the per-query path.  The pruning threshold of a phase is the k-th best exact distance
+// after the previous phase (phases split the probe ranks at fixed boundaries), not a value that
+// depends on the timing of other work.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "mrq_internal.h"
+
+namespace mrq {
+
+// ------------------------------------------------------------------------------------------------
+// small helpers
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+    // xor butterfly: every lane ends with the same value (each step adds the same two operands)
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Read data that no kernel of the current launch writes through the constant address space, so a
+// wave-uniform address becomes a scalar load.
+__device__ __forceinline__ uint32_t const_load(const uint32_t* p) {
+    return *(const __attribute__((address_space(4))) uint32_t*)(p);
+}
+__device__ __forceinline__ PairRec const_load(const PairRec* p) {
+    const __attribute__((address_space(4))) uint32_t* w = (const __attribute__((address_space(4))) uint32_t*)(p);
+    uint32_t v[12];
+#pragma unroll
+    for (int i = 0; i < 12; i++) v[i] = w[i];
+    PairRec r;
+    __builtin_memcpy(&r, v, sizeof(r));
+    return r;
+}
+
+// Order-preserving map of a float onto uint32 (for keys that may be negative).
+__device__ __forceinline__ uint32_t ord_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Exact squared distance (Algorithm 2, exact stage) of two zero-padded rows of D4 floats: lane l
+// accumulates floats [4l, 4l+4) of every 256-float chunk in ascending order, then a butterfly sum.
+__device__ __forceinline__ float exact_dist_wave(const float* __restrict__ x, const float* __restrict__ q,
+                                                 int D4, int lane) {
+    float s = 0.f;
+    for (int i = lane * 4; i < D4; i += 256) {
+        float4 a = *reinterpret_cast<const float4*>(x + i);
+        float4 b = *reinterpret_cast<const float4*>(q + i);
+        float t;
+        t = a.x - b.x; s = fmaf(t, t, s);
+        t = a.y - b.y; s = fmaf(t, t, s);
+        t = a.z - b.z; s = fmaf(t, t, s);
+        t = a.w - b.w; s = fmaf(t, t, s);
+    }
+    return wave_sum(s);
+}
+
+// <x_d, q_d> of Eq 7 evaluated by one lane in ascending dimension order (rows zero padded to d4).
+__device__ __forceinline__ float dot_lane(const float* __restrict__ a, const float* __restrict__ b, int d4) {
+    float s = 0.f;
+    for (int i = 0; i < d4; i += 4) {
+        float4 x = *reinterpret_cast<const float4*>(a + i);
+        float4 y = *reinterpret_cast<const float4*>(b + i);
+        s = fmaf(x.x, y.x, s);
+        s = fmaf(x.y, y.y, s);
+        s = fmaf(x.z, y.z, s);
+        s = fmaf(x.w, y.w, s);
+    }
+    return s;
+}
+
+// Insert a (distance, id) key into a query's sorted k-slot array.  Each slot only ever decreases,
+// so the array stays sorted and any snapshot of slot k-1 bounds the final k-th distance from above.
+__device__ void topk_insert(unsigned long long* slots, int k, unsigned long long key) {
+    volatile unsigned long long* vs = slots;
+    if (key >= vs[k - 1]) return;
+    int lo = 0, hi = k - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (vs[mid] > key) hi = mid; else lo = mid + 1;
+    }
+    for (int i = lo; i < k; i++) {
+        unsigned long long old = atomicMin(slots + i, key);
+        if (old > key) key = old;
+        if (key == kEmptyKey) return;
+    }
+}
+
+__device__ __forceinline__ int phase_of(int r) {
+    if (r == 0) return 0;
+    int p = 1, bound = 4;
+    while (r >= bound) { p++; bound <<= 2; }
+    return p;
+}
+__host__ __device__ __forceinline__ int phase_lo(int p) { return p == 0 ? 0 : (1 << (2 * (p - 1))); }
+
+// ------------------------------------------------------------------------------------------------
+// fill helpers (kernels rather than memset nodes so the sequence can be captured in a graph)
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+static int fill_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+static hipError_t fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// Per-query metadata for a uniform (k, nprobe) batch.
+__global__ void k_uniform_meta(int64_t nq, int k, int np, int32_t* __restrict__ kq, int32_t* __restrict__ npq,
+                               int64_t* __restrict__ slot_off, int64_t* __restrict__ pair_off,
+                               int64_t* __restrict__ out_off) {
+    int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q > nq) return;
+    slot_off[q] = q * k;
+    pair_off[q] = q * np;
+    if (q < nq) {
+        kq[q] = k;
+        npq[q] = np;
+        out_off[q] = q * k;
+    }
+}
+hipError_t launch_uniform_meta(int64_t nq, int k, int np, int32_t* kq, int32_t* npq, int64_t* slot_off,
+                               int64_t* pair_off, int64_t* out_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_uniform_meta, dim3((unsigned)((nq + 256) / 256)), dim3(256), 0, s, nq, k, np, kq, npq,
+                       slot_off, pair_off, out_off);
+    return hipGetLastError();
+}
+
+// dst[i, :dim] = src[idx[i], :dim]
+__global__ void k_gather_rows(const float* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx,
+                              int64_t n, int dim, float* __restrict__ dst, int64_t ldd) {
+    const int64_t r = blockIdx.x * 4ll + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    const int64_t sr = idx[r];
+    for (int i = lane; i < dim; i += 64) dst[r * ldd + i] = src[sr * lds + i];
+}
+hipError_t launch_gather_rows(const float* src, int64_t lds, const int32_t* idx, int64_t n, int dim, float* dst,
+                              int64_t ldd, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, src, lds, idx, n, dim, dst, ldd);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// FP32 "NT" GEMM: C[m, n] = sum_k (A[m, k] - asub[k]) * B[n, k]; 64 x 64 tile per 256 threads, 4 x 4
+// outputs per thread, k in steps of 16 through LDS.  Each output is a sequential FMA chain over k in
+// ascending order, so its value depends only on its own row and column.
+// EPI 0: store;  EPI 1: C = max(0, rowv[m] + colv[n] - 2 acc)  (squared distances via norms)
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(const float* __restrict__ A, int64_t lda,
+                                                 const float* __restrict__ asub,
+                                                 const float* __restrict__ Bm, int64_t ldb,
+                                                 float* __restrict__ Cm, int64_t ldc, int64_t M, int N,
+                                                 int K, const float* __restrict__ rowv,
+                                                 const float* __restrict__ colv) {
+    __shared__ float As[16][68];
+    __shared__ float Bs[16][68];
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    const int n0 = blockIdx.y * 64;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = 0.f;
+    const int lr = t >> 2, lk = (t & 3) * 4;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int kk = k0 + lk + u;
+            int64_t mr = m0 + lr;
+            float av = 0.f;
+            if (mr < M && kk < K) {
+                av = A[mr * lda + kk];
+                if (asub) av -= asub[kk];
+            }
+            As[lk + u][lr] = av;
+            int nr = n0 + lr;
+            Bs[lk + u][lr] = (nr < N && kk < K) ? Bm[(int64_t)nr * ldb + kk] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+            float4 a = *reinterpret_cast<const float4*>(&As[kk][ty * 4]);
+            float4 b = *reinterpret_cast<const float4*>(&Bs[kk][tx * 4]);
+            float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        int64_t m = m0 + ty * 4 + i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            int n = n0 + tx * 4 + j;
+            if (n >= N) continue;
+            float v = acc[i][j];
+            if (EPI == 1) v = fmaxf(0.f, fmaf(-2.f, v, rowv[m] + colv[n]));
+            Cm[m * ldc + n] = v;
+        }
+    }
+}
+
+hipError_t launch_gemm_nt(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
+                          float* Cm, int64_t ldc, int64_t M, int N, int K, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_nt<0>, grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K,
+                       nullptr, nullptr);
+    return hipGetLastError();
+}
+static hipError_t launch_gemm_dist(const float* A, int64_t lda, const float* Bm, int64_t ldb, float* Cm,
+                                   int64_t ldc, int64_t M, int N, int K, const float* rowv,
+                                   const float* colv, hipStream_t s) {
+    dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, s, A, lda, nullptr, Bm, ldb, Cm, ldc, M, N, K,
+                       rowv, colv);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Exclusive prefix sum of an int32 array in one workgroup (1024 threads x 16 items per pass).
+
+__global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                   int64_t n) {
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t carry_s;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += 1024 * 16) {
+        int32_t v[16];
+        int32_t tot = 0;
+        const int64_t b0 = base + (int64_t)t * 16;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            int64_t idx = b0 + i;
+            v[i] = idx < n ? in[idx] : 0;
+            tot += v[i];
+        }
+        int32_t incl = tot;
+        for (int o = 1; o < 64; o <<= 1) {
+            int32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int32_t woff = 0;
+        for (int i = 0; i < w; i++) woff += wsum[i];
+        int32_t run = carry_s + woff + incl - tot;
+#pragma unroll
+        for (int i = 0; i < 16; i++) {
+            int64_t idx = b0 + i;
+            if (idx < n) out[idx] = run;
+            run += v[i];
+        }
+        __syncthreads();
+        if (t == 1023) carry_s = run;
+        __syncthreads();
+    }
+    if (t == 0) out[n] = carry_s;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Per-query statistics (Algorithm 2, first three steps; Eq 6):
+//   qpad = q (zero padded to D4), ||q_p||^2 = ||q - mu||^2, ||q_d||^2, ||q_r||^2 = ||q_p||^2 - ||q_d||^2,
+//   sigma^2 = sum_{i > d} lambda_i q_{p,i}^2,  eps_r = 2 m sigma.
+
+__global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q, int D, int D4,
+                                                    const float* __restrict__ mu,
+                                                    const float* __restrict__ qd, int d, int d4,
+                                                    const float* __restrict__ qtail,
+                                                    const float* __restrict__ lam_tail, float m,
+                                                    float* __restrict__ qpad, float* __restrict__ qn2,
+                                                    float* __restrict__ qd2, float* __restrict__ Tq,
+                                                    float* __restrict__ er) {
+    const int64_t q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const float* qr = Q + q * D;
+    float s = 0.f;
+    for (int i = lane; i < D4; i += 64) {
+        float v = i < D ? qr[i] : 0.f;
+        qpad[q * D4 + i] = v;
+        if (i < D) {
+            float c = v - mu[i];
+            s = fmaf(c, c, s);
+        }
+    }
+    s = wave_sum(s);
+    float sd = 0.f;
+    for (int i = lane; i < d; i += 64) {
+        float v = qd[q * d4 + i];
+        sd = fmaf(v, v, sd);
+    }
+    sd = wave_sum(sd);
+    float var = 0.f;
+    const int r = D - d;
+    for (int i = lane; i < r; i += 64) {
+        float v = qtail[q * (int64_t)r + i];
+        var = fmaf(lam_tail[i], v * v, var);
+    }
+    var = wave_sum(var);
+    if (lane == 0) {
+        qn2[q] = s;
+        qd2[q] = sd;
+        Tq[q] = r == 0 ? 0.f : fmaxf(0.f, s - sd);
+        er[q] = r == 0 ? 0.f : 2.f * m * sqrtf(var);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Probe selection (Algorithm 2, centroid ranking): the np nearest lists by g_j = ||q_d - c_j||^2,
+// ties -> smaller list id, nearest first.  Radix select of the np-th smallest key, collection of the
+// keys below it plus the first equal keys in id order, then a bitonic sort of (g, j).
+
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int nlist,
+                                               const int32_t* __restrict__ npq,
+                                               const int64_t* __restrict__ pair_off,
+                                               int32_t* __restrict__ pair_list,
+                                               int32_t* __restrict__ pair_q) {
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long sel[kMaxProbe];
+    __shared__ uint32_t s_prefix, s_kth;
+    __shared__ int s_nless, s_eqbase, s_wtot[4];
+    const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const float* g = G + (int64_t)q * nlist;
+    const int np = npq[q];
+    uint32_t prefix = 0, mask = 0, kth = (uint32_t)np;
+    for (int pass = 0; pass < 4; pass++) {
+        const int shift = 24 - 8 * pass;
+        hist[t] = 0;
+        __syncthreads();
+        for (int j = t; j < nlist; j += 256) {
+            uint32_t key = __float_as_uint(g[j]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t cum = 0;
+            for (int b = 0; b < 256; b++) {
+                if (cum + hist[b] >= kth) {
+                    s_prefix = prefix | ((uint32_t)b << shift);
+                    s_kth = kth - cum;
+                    break;
+                }
+                cum += hist[b];
+            }
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        kth = s_kth;
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    const uint32_t T = prefix;
+    const int nless = np - (int)kth;
+    if (t == 0) { s_nless = 0; s_eqbase = 0; }
+    __syncthreads();
+    for (int base = 0; base < nlist; base += 256) {
+        const int j = base + t;
+        const uint32_t key = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
+        const bool less = j < nlist && key < T;
+        const bool eq = j < nlist && key == T;
+        if (less) {
+            int p = atomicAdd(&s_nless, 1);
+            sel[p] = ((unsigned long long)key << 32) | (uint32_t)j;
+        }
+        unsigned long long bm = __ballot(eq);
+        int before = __popcll(bm & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wtot[w] = __popcll(bm);
+        __syncthreads();
+        int woff = 0;
+        for (int i = 0; i < w; i++) woff += s_wtot[i];
+        const int r = s_eqbase + woff + before;
+        if (eq && r < (int)kth) sel[nless + r] = ((unsigned long long)key << 32) | (uint32_t)j;
+        __syncthreads();
+        if (t == 0) s_eqbase += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
+        __syncthreads();
+    }
+    int P = 1;
+    while (P < np) P <<= 1;
+    for (int i = np + t; i < P; i += 256) sel[i] = kEmptyKey;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < P; i += 256) {
+                int ixj = i ^ stride;
+                if (ixj > i) {
+                    bool asc = (i & size) == 0;
+                    unsigned long long a = sel[i], b = sel[ixj];
+                    if ((a > b) == asc) { sel[i] = b; sel[ixj] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int64_t o = pair_off[q];
+    for (int r = t; r < np; r += 256) {
+        pair_list[o + r] = (int32_t)(sel[r] & 0xFFFFFFFFull);
+        pair_q[o + r] = q;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Pair bucketing by (phase, list) and per-pair query codes.
+
+__global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
+                             const int64_t* __restrict__ pair_off, int64_t npairs, int nlist,
+                             int32_t* __restrict__ cnt) {
+    int64_t pi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pi >= npairs) return;
+    const int q = pair_q[pi];
+    const int r = (int)(pi - pair_off[q]);
+    atomicAdd(&cnt[phase_of(r) * nlist + pair_list[pi]], 1);
+}
+
+// One wave per (query, list) pair (Algorithm 2: normalise, rotate and quantise q_d for list j):
+//   w = P_r^T q_d - P_r^T c_j,  n_q = ||w||,  q' = w / n_q,
+//   v_l = min q', Delta = (max q' - v_l) / (2^bq - 1), u_i = floor((q'_i - v_l) * (1/Delta) + 1/2)
+// (each step one IEEE-rounded FP32 operation, no contraction); bit plane b of u is written as d-bit
+// masks, together with the pair's scalars.
+__global__ __launch_bounds__(256) void k_pair_prep(
+    const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
+    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
+    const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
+    const float* __restrict__ Tq, const float* __restrict__ er, const int32_t* __restrict__ boff,
+    int32_t* __restrict__ fill,
+    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int32_t* __restrict__ pair_pos) {
+    const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
+    if (pi >= npairs) return;
+    const int lane = threadIdx.x & 63;
+    const int q = pair_q[pi];
+    const int j = pair_list[pi];
+    const int r = (int)(pi - pair_off[q]);
+    const int p = phase_of(r);
+    int pos = 0;
+    if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
+    pos = __shfl(pos, 0);
+    if (lane == 0) pair_pos[pi] = pos;
+    const int nh = (d + 63) / 64;  // dims per lane
+    float wv[24];                  // d <= 1536
+    float n2 = 0.f;
+    for (int h = 0; h < nh; h++) {
+        int i = lane + 64 * h;
+        float v = 0.f;
+        if (i < d) v = __fsub_rn(rq[(int64_t)q * d4 + i], RC[(int64_t)j * d4 + i]);
+        wv[h] = v;
+        n2 = fmaf(v, v, n2);
+    }
+    n2 = wave_sum(n2);
+    const float nq = sqrtf(n2);
+    float lo = FLT_MAX, hi = -FLT_MAX;
+    for (int h = 0; h < nh; h++) {
+        int i = lane + 64 * h;
+        float v = nq > 0.f ? __fdiv_rn(wv[h], nq) : 0.f;
+        wv[h] = v;
+        if (i < d) { lo = fminf(lo, v); hi = fmaxf(hi, v); }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    const int levels = (1 << bq) - 1;
+    float delta = 1.f;
+    int su = 0;
+    int uv[24];
+    if (hi > lo) {
+        delta = __fdiv_rn(__fsub_rn(hi, lo), (float)levels);
+        const float inv = __fdiv_rn(1.f, delta);
+        for (int h = 0; h < nh; h++) {
+            int i = lane + 64 * h;
+            int u = 0;
+            if (i < d) {
+                float tt = __fadd_rn(__fmul_rn(__fsub_rn(wv[h], lo), inv), 0.5f);
+                u = (int)floorf(tt);
+                u = u < 0 ? 0 : (u > levels ? levels : u);
+            }
+            uv[h] = u;
+            su += u;
+        }
+    } else {
+        for (int h = 0; h < nh; h++) uv[h] = 0;
+    }
+    su = wave_sum_i(su);
+    uint32_t* pl = planes + (int64_t)pos * bq * WP;
+    for (int b = 0; b < bq; b++) {
+        for (int h = 0; h < (WP + 1) / 2; h++) {
+            unsigned long long bm = __ballot(h < nh && ((uv[h < nh ? h : 0] >> b) & 1));
+            if (lane == 0) {
+                if (2 * h < WP) pl[b * WP + 2 * h] = (uint32_t)bm;
+                if (2 * h + 1 < WP) pl[b * WP + 2 * h + 1] = (uint32_t)(bm >> 32);
+            }
+        }
+    }
+    if (lane == 0) {
+        PairRec R;
+        R.q = q;
+        R.list = j;
+        R.Kr = (n2 + Tq[q]) - er[q];
+        R.two_nq = 2.f * nq;
+        R.vl = lo;
+        R.delta = delta;
+        R.su = (float)su;
+        R.ebc = 2.f * nq * eps0 / sqrtf((float)(d - 1));
+        R.tau = INFINITY;
+        R.er = er[q];
+        R.pad0 = 0.f;
+        R.pad1 = 0.f;
+        if (!(hi > lo)) { R.vl = nq > 0.f ? lo : 0.f; }
+        recs[pos] = R;
+    }
+}
+
+__global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_nb, int nlist,
+                        int G, int n, int32_t* __restrict__ items) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int c = cnt[t];
+    int j = t % nlist;
+    items[t] = c == 0 ? 0 : list_nb[j] * ((c + G - 1) / G);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Stage 1 (Eq 4 with the Eq 5 and Eq 6 bounds) for the candidate held by this lane against one pair:
+//   ip = sum_b 2^b popcount(code & U_b),   I = Delta (2 ip - S_u) + v_l (2 popcount(code) - d)
+//      = sqrt(d) <xbar_b, qbar_b>,
+//   dis' = (A_x + K) - 2 n_q F_x I,   LB = dis' - ebc E_x - eps_r  (evaluated as (A_x + Kr) - ...).
+
+template <int WP, int BQT>
+__device__ __forceinline__ float stage1_lb(const uint32_t (&c)[WP], int pc, float A, float F, float E,
+                                           const PairRec& R, const uint32_t* __restrict__ U, int bq, int d) {
+    const int nb = BQT > 0 ? BQT : bq;
+    int ip = 0;
+#pragma unroll
+    for (int b = 0; b < (BQT > 0 ? BQT : 8); b++) {
+        if (BQT == 0 && b >= nb) break;
+        int acc = 0;
+#pragma unroll
+        for (int w = 0; w < WP; w++) acc += __builtin_popcount(c[w] & U[b * WP + w]);
+        ip += acc << b;
+    }
+    const float J1 = (float)(2 * ip - (int)R.su);
+    const float J2 = (float)(2 * pc - d);
+    const float I = fmaf(R.delta, J1, R.vl * J2);
+    return fmaf(-R.ebc, E, fmaf(-(R.two_nq * F), I, A + R.Kr));
+}
+
+// B-bit refinement of a stage-1 survivor (extended code, top plane = sign plane):
+//   ipB = sum_{a, b} 2^(a + b) popcount(X_a & U_b),
+//   I_B = Delta (2 ipB - (2^B - 1) S_u) + v_l SX_x = 2 <y, qbar'>,
+//   dis_B = (A_x + K) - 2 n_q FB_x I_B,   LB_B = dis_B - ebc EB_x - eps_r.
+__device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const uint32_t* __restrict__ extp,
+                                        int B, int WP, float A, float FB, float EB, float SX, const PairRec& R,
+                                        const uint32_t* __restrict__ U, int bq) {
+    long long ip = 0;
+    for (int a = 0; a < B; a++) {
+        const uint32_t* X = a == B - 1 ? sign : extp + a * WP;
+        for (int b = 0; b < bq; b++) {
+            int acc = 0;
+            for (int w = 0; w < WP; w++) acc += __builtin_popcount(X[w] & U[b * WP + w]);
+            ip += (long long)acc << (a + b);
+        }
+    }
+    const float J1 = (float)(2 * ip - (long long)((1 << B) - 1) * (long long)R.su);
+    const float I = fmaf(R.delta, J1, R.vl * SX);
+    return fmaf(-R.ebc, EB, fmaf(-(R.two_nq * FB), I, A + R.Kr));
+}
+
+struct ScanCtx {
+    const PairRec* recs;
+    const uint32_t* planes;
+    const int32_t* boff;
+    const int32_t* ioff;
+    const int64_t* list_off;
+    const int32_t* list_nb;
+    const uint32_t* code;
+    const uint32_t* ext;
+    const float *fA, *fF, *fE, *fFB, *fEB, *fSX;
+    const float* xd;
+    const float* ax;
+    const float* X;
+    const int32_t* ids;
+    const float* qd;
+    const float* qpad;
+    const float* qn2;
+    const int32_t* kq;
+    const int64_t* slot_off;
+    unsigned long long* slots;
+    int32_t* wcount;
+    int64_t* counters;
+    int nlist, d, d4, D4, B, bq, G, stage2, use_ext, phase;
+};
+
+// Survivor queue of one wave: (row, record position) pairs in LDS.
+struct Surv { int32_t row, pos; };
+
+// Ext refinement, Eq 7 re-check and exact distance for up to 64 queued survivors (one per lane),
+// then the exact stage wave-cooperatively for each remaining survivor and the top-k insert.
+template <int WP>
+__device__ void flush_queue(const ScanCtx& c, Surv* qu, int n, int lane, long long* cnt_ext,
+                            long long* cnt2) {
+    int row = 0, q = 0;
+    bool pass = lane < n;
+    float tau = 0.f, er = 0.f;
+    if (pass) {
+        row = qu[lane].row;
+        const int pos = qu[lane].pos;
+        const PairRec R = c.recs[pos];
+        q = R.q;
+        tau = R.tau;
+        er = R.er;
+        if (c.B > 1 && c.use_ext) {
+            const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
+            float lb = ext_lb(c.code + (int64_t)row * WP, c.ext + (int64_t)row * (c.B - 1) * WP, c.B, WP,
+                              c.fA[row], c.fFB[row], c.fEB[row], c.fSX[row], R, U, c.bq);
+            pass = lb < tau;
+        }
+    }
+    *cnt_ext += __popcll(__ballot(pass));
+    if (pass && c.stage2) {
+        float dot = dot_lane(c.xd + (int64_t)row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+        float diso = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]);
+        pass = diso - er < tau;
+    }
+    unsigned long long m2 = __ballot(pass);
+    *cnt2 += __popcll(m2);
+    while (m2) {
+        const int s = __ffsll((long long)m2) - 1;
+        m2 &= m2 - 1;
+        const int rs = __shfl(row, s);
+        const int qs = __shfl(q, s);
+        float dist = exact_dist_wave(c.X + (int64_t)rs * c.D4, c.qpad + (int64_t)qs * c.D4, c.D4, lane);
+        if (lane == 0) {
+            unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+            topk_insert(c.slots + c.slot_off[qs], c.kq[qs], key);
+        }
+    }
+}
+
+// Persistent list-major scan of one phase.  A work item is (list j, 64-row block, chunk of up to G
+// pair records of list j); a wave loads its block's codes and factors once and tests them against
+// every pair of the chunk, the pair's scalars and bit planes arriving through scalar loads.
+template <int WP, int BQT>
+__global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
+    __shared__ Surv queue[4][128];
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    Surv* qu = queue[wv];
+    const int p = c.phase;
+    const int* ioff = c.ioff + p * c.nlist;
+    const int base_item = ioff[0];
+    const int total = ioff[c.nlist] - base_item;
+    int qn = 0;
+    long long n1 = 0, next = 0, n2 = 0, nscan = 0;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(c.wcount + p, 1);
+        it = uniform(__shfl(it, 0));
+        if (it >= total) break;
+        const int git = base_item + it;
+        int lo = 0, hi = c.nlist - 1;  // last list j with ioff[j] <= git
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (ioff[mid] <= git) lo = mid; else hi = mid - 1;
+        }
+        const int j = uniform(lo);
+        const int local = git - ioff[j];
+        const int nb = c.list_nb[j];
+        const int blk = local % nb, ch = local / nb;
+        const int pbeg = c.boff[p * c.nlist + j] + ch * c.G;
+        const int pend0 = c.boff[p * c.nlist + j + 1];
+        const int pend = pbeg + c.G < pend0 ? pbeg + c.G : pend0;
+        const int64_t row = c.list_off[j] + (int64_t)blk * 64 + lane;
+        uint32_t cw[WP];
+#pragma unroll
+        for (int w = 0; w < WP; w++) cw[w] = c.code[row * WP + w];
+        int pc = 0;
+#pragma unroll
+        for (int w = 0; w < WP; w++) pc += __builtin_popcount(cw[w]);
+        const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
+        constexpr int NBQ = BQT > 0 ? BQT : 8;
+        const int bq = BQT > 0 ? BQT : c.bq;
+        const int64_t pstride = (int64_t)bq * WP;
+        // pair records and planes are read-only during the scan: scalar loads
+        for (int pos = pbeg; pos < pend; pos++) {
+            const PairRec R = const_load(c.recs + pos);
+            uint32_t U[NBQ * WP];
+#pragma unroll
+            for (int t = 0; t < NBQ * WP; t++) U[t] = t < bq * WP ? const_load(c.planes + pos * pstride + t) : 0u;
+            const float lb = stage1_lb<WP, BQT>(cw, pc, A, F, E, R, U, bq, c.d);
+            const unsigned long long m = __ballot(lb < R.tau);
+            nscan += 64;
+            if (m) {
+                const int before = __popcll(m & ((1ull << lane) - 1ull));
+                if ((m >> lane) & 1ull) qu[qn + before] = Surv{(int32_t)row, pos};
+                const int add = __popcll(m);
+                n1 += add;
+                qn += add;
+                if (qn >= 64) {
+                    __threadfence_block();
+                    flush_queue<WP>(c, qu, 64, lane, &next, &n2);
+                    const int rest = qn - 64;
+                    Surv tmp;
+                    if (lane < rest) tmp = qu[64 + lane];
+                    __threadfence_block();
+                    if (lane < rest) qu[lane] = tmp;
+                    __threadfence_block();
+                    qn = rest;
+                }
+            }
+        }
+    }
+    if (qn > 0) {
+        __threadfence_block();
+        flush_queue<WP>(c, qu, qn, lane, &next, &n2);
+    }
+    if (c.counters && lane == 0) {
+        atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
+        atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
+        atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
+        atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)n2);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Seed pass: each query's nearest list (probe rank 0) processed by one wave in increasing order of
+// the stage-1 estimate.  The first k candidates fill the result queue (their exact distances set
+// tau), the rest are tested against the running tau exactly as in Algorithm 2.  After this pass every
+// query with k candidates in its nearest list has a finite threshold for the batched phases.
+
+constexpr int kSeedChunk = 1024;
+
+// sort 64 keys held one per lane, ascending (bitonic network over shuffles)
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
+    for (int size = 2; size <= 64; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            unsigned long long o = __shfl_xor(v, stride);
+            bool up = (lane & size) == 0;
+            bool lower = (lane & stride) == 0;
+            unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (lower == up) ? mn : mx;
+        }
+    }
+    return v;
+}
+
+template <int WP, int BQT>
+__global__ __launch_bounds__(64) void k_seed(ScanCtx c, const int64_t* __restrict__ pair_off,
+                                             const int32_t* __restrict__ pair_pos,
+                                             const int32_t* __restrict__ list_len) {
+    __shared__ unsigned long long keys[kSeedChunk];
+    __shared__ float lbs[kSeedChunk];
+    __shared__ unsigned long long tk[2][kMaxK];
+    __shared__ unsigned long long nk[64];
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int pos0 = pair_pos[pair_off[q]];
+    const PairRec R = c.recs[pos0];
+    const uint32_t* U = c.planes + (int64_t)pos0 * (BQT > 0 ? BQT : c.bq) * WP;
+    const int j = R.list;
+    const int n = list_len[j];
+    const int64_t base = c.list_off[j];
+    const int k = c.kq[q];
+    const float er = R.er;
+    int cur = 0, have = 0;
+    float tau = INFINITY;
+    long long nscan = 0, n1 = 0, next = 0, n2 = 0;
+    for (int cs = 0; cs < n; cs += kSeedChunk) {
+        const int m = n - cs < kSeedChunk ? n - cs : kSeedChunk;
+        int P = 64;
+        while (P < m) P <<= 1;
+        for (int idx = lane; idx < P; idx += 64) {
+            if (idx < m) {
+                const int64_t row = base + cs + idx;
+                uint32_t cw[WP];
+                int pc = 0;
+#pragma unroll
+                for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
+                // the estimate itself (LB + radii) orders the walk; LB decides
+                const float lb = stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
+                const float dis = lb + R.ebc * c.fE[row] + er;
+                keys[idx] = ((unsigned long long)ord_bits(dis) << 32) | (uint32_t)idx;
+                lbs[idx] = lb;
+            } else {
+                keys[idx] = kEmptyKey;
+            }
+        }
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = lane; i < P; i += 64) {
+                    int ixj = i ^ stride;
+                    if (ixj > i) {
+                        bool asc = (i & size) == 0;
+                        unsigned long long a = keys[i], b = keys[ixj];
+                        if ((a > b) == asc) { keys[i] = b; keys[ixj] = a; }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        nscan += m;
+        int at = 0;
+        while (at < m) {
+            int bs = m - at < 64 ? m - at : 64;
+            if (have < k && k - have < bs) bs = k - have;
+            bool pass = false;
+            int64_t row = 0;
+            if (lane < bs) {
+                const int idx = (int)(keys[at + lane] & 0xFFFFFFFFull);
+                row = base + cs + idx;
+                pass = lbs[idx] < tau;
+            }
+            n1 += __popcll(__ballot(pass));
+            if (pass && c.B > 1 && c.use_ext) {
+                const uint32_t* Ub = U;
+                float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row],
+                                  c.fFB[row], c.fEB[row], c.fSX[row], R, Ub, c.bq);
+                pass = lb < tau;
+            }
+            next += __popcll(__ballot(pass));
+            if (pass && c.stage2) {
+                float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+                float diso = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]);
+                pass = diso - er < tau;
+            }
+            unsigned long long m2 = __ballot(pass);
+            n2 += __popcll(m2);
+            unsigned long long mine = kEmptyKey;
+            while (m2) {
+                const int s = __ffsll((long long)m2) - 1;
+                m2 &= m2 - 1;
+                const int64_t rs = __shfl(row, s);
+                float dist = exact_dist_wave(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane);
+                if (lane == s) mine = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+            }
+            // merge the new keys into the sorted queue tk[cur][0..have)
+            unsigned long long sv = wave_sort64(mine, lane);
+            const int mnew = __popcll(__ballot(sv != kEmptyKey));
+            if (mnew > 0) {
+                nk[lane] = sv;
+                __syncthreads();
+                unsigned long long* src = tk[cur];
+                unsigned long long* dst = tk[cur ^ 1];
+                for (int i = lane; i < have; i += 64) {  // existing element: rank among new keys
+                    unsigned long long e = src[i];
+                    int lo = 0, hi = mnew;
+                    while (lo < hi) { int mid = (lo + hi) >> 1; if (nk[mid] < e) lo = mid + 1; else hi = mid; }
+                    int dp = i + lo;
+                    if (dp < k) dst[dp] = e;
+                }
+                if (lane < mnew) {
+                    unsigned long long e = sv;
+                    int lo = 0, hi = have;
+                    while (lo < hi) { int mid = (lo + hi) >> 1; if (src[mid] < e) lo = mid + 1; else hi = mid; }
+                    int dp = lane + lo;
+                    if (dp < k) dst[dp] = e;
+                }
+                __syncthreads();
+                cur ^= 1;
+                have = have + mnew < k ? have + mnew : k;
+                if (have == k) tau = __uint_as_float((uint32_t)(tk[cur][k - 1] >> 32));
+            }
+            at += bs;
+        }
+        __syncthreads();
+    }
+    unsigned long long* out = c.slots + c.slot_off[q];
+    for (int i = lane; i < k; i += 64) out[i] = i < have ? tk[cur][i] : kEmptyKey;
+    if (c.counters && lane == 0) {
+        atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
+        atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
+        atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
+        atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)n2);
+        atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)n2);
+    }
+}
+
+// Threshold of a phase: the k-th best exact distance held after the previous phases, written into
+// every pair record of the phase.
+__global__ void k_tau_snap(const unsigned long long* __restrict__ slots, const int64_t* __restrict__ slot_off,
+                           const int32_t* __restrict__ kq, const int32_t* __restrict__ boff, int nlist, int phase,
+                           int64_t npairs, PairRec* __restrict__ recs) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t pos = boff[phase * nlist] + i;
+    if (i >= npairs || pos >= boff[(phase + 1) * nlist]) return;
+    const int q = recs[pos].q;
+    const unsigned long long v = slots[slot_off[q] + kq[q] - 1];
+    recs[pos].tau = v == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(v >> 32));
+}
+
+__global__ void k_finalize(const unsigned long long* __restrict__ slots, const int64_t* __restrict__ slot_off,
+                           const int32_t* __restrict__ kq, const int64_t* __restrict__ out_off,
+                           int64_t* __restrict__ ids, float* __restrict__ dists) {
+    const int64_t q = blockIdx.x;
+    const int k = kq[q];
+    const unsigned long long* s = slots + slot_off[q];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        unsigned long long v = s[i];
+        int64_t o = out_off[q] + i;
+        if (v == kEmptyKey) {
+            ids[o] = -1;
+            dists[o] = INFINITY;
+        } else {
+            ids[o] = (int64_t)(uint32_t)(v & 0xFFFFFFFFull);
+            dists[o] = __uint_as_float((uint32_t)(v >> 32));
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side: workspace layout and the launch sequence
+
+namespace {
+struct Carve {
+    char* p;
+    size_t used = 0;
+    template <class T>
+    T* take(int64_t n) {
+        size_t b = ((size_t)(n > 0 ? n : 1) * sizeof(T) + 255) & ~(size_t)255;
+        T* r = reinterpret_cast<T*>(p ? p + used : nullptr);
+        used += b;
+        return r;
+    }
+};
+
+struct WsPtrs {
+    float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcount;
+    PairRec* recs;
+    uint32_t* planes;
+    unsigned long long* slots;
+};
+
+WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
+             size_t* used) {
+    Carve c{reinterpret_cast<char*>(base)};
+    WsPtrs w;
+    const int64_t P = (int64_t)kPhases * ix.nlist;
+    w.qd = c.take<float>(nq * ix.d4);
+    w.qtail = c.take<float>(nq * (int64_t)(ix.D - ix.d));
+    w.qpad = c.take<float>(nq * ix.D4);
+    w.rq = c.take<float>(nq * ix.d4);
+    w.qn2 = c.take<float>(nq);
+    w.qd2 = c.take<float>(nq);
+    w.Tq = c.take<float>(nq);
+    w.er = c.take<float>(nq);
+    w.G = c.take<float>(nq * (int64_t)ix.nlist);
+    w.pair_list = c.take<int32_t>(total_pairs);
+    w.pair_q = c.take<int32_t>(total_pairs);
+    w.pair_pos = c.take<int32_t>(total_pairs);
+    w.cnt = c.take<int32_t>(P);
+    w.boff = c.take<int32_t>(P + 1);
+    w.fill = c.take<int32_t>(P);
+    w.items = c.take<int32_t>(P);
+    w.ioff = c.take<int32_t>(P + 1);
+    w.wcount = c.take<int32_t>(kPhases);
+    w.recs = c.take<PairRec>(total_pairs);
+    w.planes = c.take<uint32_t>(total_pairs * bq * ix.WP);
+    w.slots = c.take<unsigned long long>(total_slots);
+    *used = c.used;
+    return w;
+}
+
+struct Timed {
+    KernelTimer* t;
+    hipStream_t s;
+    KernelTimer::Pending p;
+    Timed(KernelTimer* tm, hipStream_t st, const char* name) : t(tm), s(st) {
+        p.slot = -1;
+        if (t && t->on) t->begin(s, name, &p);
+    }
+    ~Timed() {
+        if (t && t->on && p.slot >= 0) t->end(s, &p);
+    }
+};
+}  // namespace
+
+size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq) {
+    size_t used = 0;
+    carve(nullptr, ix, nq, total_slots, total_pairs, bq, &used);
+    return used;
+}
+
+template <int WP, int BQT>
+static void launch_scan_phase(const ScanCtx& c, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_scan<WP, BQT>), dim3(grid), dim3(256), 0, s, c);
+}
+template <int WP, int BQT>
+static void launch_seed(const ScanCtx& c, int64_t nq, const int64_t* pair_off, const int32_t* pair_pos,
+                        const int32_t* list_len, hipStream_t s) {
+    hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64), 0, s, c, pair_off, pair_pos, list_len);
+}
+
+template <int WP>
+static void dispatch_bq(const ScanCtx& c, bool seed, int grid, int64_t nq, const int64_t* pair_off,
+                        const int32_t* pair_pos, const int32_t* list_len, hipStream_t s) {
+    if (c.bq == 4) {
+        if (seed) launch_seed<WP, 4>(c, nq, pair_off, pair_pos, list_len, s);
+        else launch_scan_phase<WP, 4>(c, grid, s);
+    } else {
+        if (seed) launch_seed<WP, 0>(c, nq, pair_off, pair_pos, list_len, s);
+        else launch_scan_phase<WP, 0>(c, grid, s);
+    }
+}
+
+static void dispatch(const ScanCtx& c, int WP, bool seed, int grid, int64_t nq, const int64_t* pair_off,
+                     const int32_t* pair_pos, const int32_t* list_len, hipStream_t s) {
+    switch (WP) {
+        case 1: dispatch_bq<1>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 2: dispatch_bq<2>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 4: dispatch_bq<4>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 8: dispatch_bq<8>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 16: dispatch_bq<16>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 32: dispatch_bq<32>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        default: dispatch_bq<48>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+    }
+}
+
+int padded_words(int d) {
+    const int W = (d + 31) / 32;
+    const int opts[] = {1, 2, 4, 8, 16, 32, 48};
+    for (int o : opts)
+        if (o >= W) return o;
+    return -1;
+}
+
+#define HIP_TRY(x)                              \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
+    const Index& ix = *a.ix;
+    size_t used = 0;
+    WsPtrs w = carve(ws, ix, a.nq, a.total_slots, a.total_pairs, a.bq, &used);
+    if (used > ws_bytes) return hipErrorOutOfMemory;
+    KernelTimer* tm = &ix.timer;
+    const int64_t nq = a.nq;
+    const int d = ix.d, d4 = ix.d4, D = ix.D, D4 = ix.D4, nlist = ix.nlist;
+    const int64_t P = (int64_t)kPhases * nlist;
+
+    {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
+        Timed t(tm, s, "project");
+        HIP_TRY(launch_fill_f32(w.qd, 0.f, nq * d4, s));
+        HIP_TRY(launch_gemm_nt(a.Q, D, ix.mu, ix.PpLead, D, w.qd, d4, nq, d, D, s));
+        if (D > d) HIP_TRY(launch_gemm_nt(a.Q, D, ix.mu, ix.PpTail, D, w.qtail, D - d, nq, D - d, D, s));
+        hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4,
+                           w.qtail, ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(launch_gemm_nt(w.qd, d4, nullptr, ix.PrT, d4, w.rq, d4, nq, d, d, s));
+    }
+    {   // centroid ranking
+        Timed t(tm, s, "probe");
+        HIP_TRY(launch_gemm_dist(w.qd, d4, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, s));
+        hipLaunchKernelGGL(k_select, dim3((unsigned)nq), dim3(256), 0, s, w.G, nlist, a.npq, a.pair_off,
+                           w.pair_list, w.pair_q);
+        HIP_TRY(hipGetLastError());
+    }
+    {   // per-pair query codes, grouped by (phase, list)
+        Timed t(tm, s, "pair_prep");
+        HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
+        HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
+        HIP_TRY(launch_fill_i32(w.wcount, 0, kPhases, s));
+        hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
+                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, P);
+        hipLaunchKernelGGL(k_pair_prep, dim3((unsigned)((a.total_pairs + 3) / 4)), dim3(256), 0, s,
+                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.rq, ix.RC, d, d4,
+                           ix.WP, a.bq, a.eps0, w.Tq, w.er, w.boff, w.fill, w.recs, w.planes, w.pair_pos);
+        hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
+                           nlist, a.group, (int)P, w.items);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, P);
+        HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
+        HIP_TRY(hipGetLastError());
+    }
+    ScanCtx c;
+    c.recs = w.recs; c.planes = w.planes; c.boff = w.boff; c.ioff = w.ioff;
+    c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.code = ix.code; c.ext = ix.ext;
+    c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
+    c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2;
+    c.kq = a.kq; c.slot_off = a.slot_off; c.slots = w.slots; c.wcount = w.wcount;
+    c.counters = a.counters; c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq;
+    c.G = a.group; c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0;
+    {
+        Timed t(tm, s, "seed");
+        dispatch(c, ix.WP, true, 0, nq, a.pair_off, w.pair_pos, ix.list_len, s);
+        HIP_TRY(hipGetLastError());
+    }
+    for (int p = 1; p < kPhases; p++) {
+        if (a.np_max <= phase_lo(p)) break;
+        c.phase = p;
+        {
+            Timed t(tm, s, "tau");
+            hipLaunchKernelGGL(k_tau_snap, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
+                               w.slots, a.slot_off, a.kq, w.boff, nlist, p, a.total_pairs, w.recs);
+        }
+        Timed t(tm, s, "scan");
+        dispatch(c, ix.WP, false, 2048, nq, a.pair_off, w.pair_pos, ix.list_len, s);
+        HIP_TRY(hipGetLastError());
+    }
+    {
+        Timed t(tm, s, "finalize");
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)nq), dim3(64), 0, s, w.slots, a.slot_off, a.kq,
+                           a.out_off, a.ids, a.dists);
+        HIP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
+}  // namespace mrq

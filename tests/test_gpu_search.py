@@ -1,0 +1,241 @@
+"""GPU parity of the MRQ search path with the CPU oracle (needs an MI355X).
+
+The device index is exported and the oracle imports it, re-deriving every per-vector quantity in
+FP64 from the original vectors; the device results are then compared with the oracle's plain
+definition of the result (EXACT-IVF over the probed lists) under the rules in tests/parity.py.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import torch  # noqa: E402
+
+import oracle  # noqa: E402
+import paper_2411_06158_amd as mrq  # noqa: E402
+from paper_2411_06158_amd import synth  # noqa: E402
+from parity import check_rows  # noqa: E402
+
+
+def _mk(name, N, nq, d, B, nlist, spec_override=None):
+    X, Q, spec = synth.workload(name, N=N, nq=nq, cache=False)
+    Xd = torch.from_numpy(X).cuda()
+    ix = mrq.Index.build(Xd, d_r=d, bits=B, nlist=nlist)
+    tmp = tempfile.mkdtemp()
+    path = os.path.join(tmp, "ix.mrqx")
+    ix.export(path)
+    orc = oracle.Index.load_export(path, X)
+    return dict(X=X, Q=Q, Xd=Xd, Qd=torch.from_numpy(Q).cuda(), ix=ix, orc=orc, d=d, B=B, nlist=nlist)
+
+
+@pytest.fixture(scope="module")
+def small():
+    print("\n[gpu] build small: N=20000 D=128 d=32 B=1 nlist=64", flush=True)
+    return _mk("small", 20000, 100, 32, 1, 64)
+
+
+@pytest.fixture(scope="module")
+def small_ext():
+    print("\n[gpu] build small ext: N=12000 D=128 d=64 B=4 nlist=48", flush=True)
+    return _mk("small", 12000, 60, 64, 4, 48)
+
+
+def _search(env, k, nprobe, **kw):
+    ids, dists = env["ix"].search(env["Qd"], k, nprobe, **kw)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), dists.cpu().numpy()
+
+
+def _assert_parity(env, ids, dists, k, nprobe, prm=None, max_excused=0.1):
+    prm = prm or oracle.params()
+    st = check_rows(env["orc"], env["X"], env["Q"], ids, dists, k, nprobe, prm)
+    print(f"[gpu] parity k={k} nprobe={nprobe}: {dict((a, b) for a, b in st.items() if a != 'failures')}",
+          flush=True)
+    assert not st["failures"], st["failures"][:5]
+    excused = st["risk_excused"] + st["tie_excused"] + st["probe_tie"]
+    assert excused <= max_excused * st["queries"]
+
+
+# ---- build parity -------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["small", "small_ext"])
+def test_build_matches_oracle(which, request):
+    env = request.getfixturevalue(which)
+    path = os.path.join(tempfile.mkdtemp(), "raw.mrqx")
+    env["ix"].export(path)
+    raw = oracle.Index.load_export(path)        # the device's own stored summaries
+    orc = env["orc"]                             # the same index re-derived in FP64
+    for name, tol in (("nx", 2e-5), ("tx", 2e-5), ("ax", 2e-6), ("xi1", 2e-5), ("xiB", 2e-5), ("yn", 1e-6)):
+        a, b = raw.get(name), orc.get(name)
+        scale = np.maximum(np.abs(b), 1e-3 * np.abs(b).max())
+        err = np.abs(a - b) / scale
+        assert err.max() <= tol, (name, float(err.max()))
+    # sign bits: every disagreement with the FP64 rotated residual sits at a near-zero coordinate
+    d = env["d"]
+    Pr, Cc, off, lid, code = orc.get("Pr"), orc.get("C"), orc.get("off"), orc.get("lid"), orc.get("code")
+    xd = orc.get("xd")
+    B = env["B"]
+    lists = np.searchsorted(off, np.arange(orc.N), side="right") - 1
+    o = xd - Cc[lists]
+    xp = (o @ Pr) / np.linalg.norm(o, axis=1, keepdims=True)
+    sign = (code >> (B - 1)) & 1
+    flips = sign != (xp >= 0)
+    assert np.all(np.abs(xp[flips]) < 1e-5), np.abs(xp[flips]).max()
+    if B > 1:  # the B-bit code reaches the best cosine up to FP32 input noise
+        for r in range(0, orc.N, max(1, orc.N // 300)):
+            _, best = oracle.encode_ext(xp[r], B)
+            assert orc.get("xiB")[r] >= best - 1e-5
+
+
+# ---- search parity --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,nprobe", [(10, 8), (1, 4), (50, 16), (10, 64)])
+def test_search_matches_oracle(small, k, nprobe):
+    ids, dists = _search(small, k, nprobe)
+    _assert_parity(small, ids, dists, k, nprobe)
+
+
+def test_search_ext_bits_matches_oracle(small_ext):
+    ids, dists = _search(small_ext, 10, 8)
+    _assert_parity(small_ext, ids, dists, 10, 8)
+    ids2, dists2 = _search(small_ext, 10, 8, use_ext=False)
+    _assert_parity(small_ext, ids2, dists2, 10, 8, prm=oracle.params(use_ext=False))
+
+
+def test_plain_mrq_without_stage2(small):
+    ids, dists = _search(small, 10, 8, stage2=False)
+    _assert_parity(small, ids, dists, 10, 8, prm=oracle.params(stage2=False))
+
+
+def test_all_lists_is_exact_knn(small):
+    n = 40
+    gt, gd = oracle.bruteforce(small["X"], small["Q"][:n], 10)
+    ids, dists = small["ix"].search(small["Qd"][:n].contiguous(), 10, small["nlist"])
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    agree = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids, gt)])
+    assert agree >= 0.99
+
+
+def test_recall_against_ground_truth(small):
+    gt, _ = oracle.bruteforce(small["X"], small["Q"], 10)
+    ids, _ = _search(small, 10, 8)
+    rec = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids, gt)])
+    print(f"[gpu] recall@10 nprobe=8: {rec:.4f}", flush=True)
+    assert rec >= 0.95
+
+
+# ---- batch independence and the per-query path -----------------------------------------------------
+
+def test_per_query_path_bit_identical(small):
+    ids, dists = _search(small, 10, 8)
+    ids1, dists1 = _search(small, 10, 8, mode=mrq.MRQ_PER_QUERY)
+    assert np.array_equal(ids, ids1) and np.array_equal(dists.view(np.uint32), dists1.view(np.uint32))
+
+
+def test_result_independent_of_batch(small):
+    ids, dists = _search(small, 10, 8)
+    sel = [3, 17, 42, 99]
+    sub = small["Qd"][sel].contiguous()
+    ids2, dists2 = small["ix"].search(sub, 10, 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids[sel], ids2.cpu().numpy())
+    assert np.array_equal(dists[sel].view(np.uint32), dists2.cpu().numpy().view(np.uint32))
+    big = torch.cat([small["Qd"]] * 5)
+    ids3, dists3 = small["ix"].search(big, 10, 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(np.concatenate([ids] * 5), ids3.cpu().numpy())
+
+
+def test_host_buffers(small):
+    ids, dists = small["ix"].search(small["Q"][:7].copy(), 10, 8)
+    ref, refd = _search(small, 10, 8)
+    assert np.array_equal(ids, ref[:7]) and np.array_equal(dists, refd[:7])
+
+
+def test_mixed_k_nprobe(small):
+    rng = np.random.default_rng(0)
+    n = small["Q"].shape[0]
+    ks = rng.integers(1, 40, n).astype(np.int32)
+    nps = rng.integers(1, 20, n).astype(np.int32)
+    ids, dists, off = small["ix"].search_mixed(small["Qd"], ks, nps)
+    rows_i = [ids[off[i]:off[i] + ks[i]] for i in range(n)]
+    rows_d = [dists[off[i]:off[i] + ks[i]] for i in range(n)]
+    for i in range(0, n, 9):  # each row equals the uniform search with that (k, nprobe)
+        a, b = small["ix"].search(small["Qd"][i:i + 1].contiguous(), int(ks[i]), int(nps[i]))
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy()[0], rows_i[i])
+        assert np.array_equal(b.cpu().numpy()[0].view(np.uint32), rows_d[i].view(np.uint32))
+    st = check_rows(small["orc"], small["X"], small["Q"], rows_i, rows_d, None, None, oracle.params(),
+                    ks=ks, nprobes=nps)
+    assert not st["failures"], st["failures"][:5]
+
+
+def test_counters_monotone(small):
+    cnt = np.zeros(8, dtype=np.int64)
+    small["ix"].search(small["Q"][:20].copy(), 10, 8, counters=cnt)
+    scanned, p1, pext, p2 = cnt[:4]
+    assert scanned > 0 and scanned >= p1 >= pext >= p2 > 0
+
+
+# ---- edge cases -----------------------------------------------------------------------------------
+
+def test_padding_when_k_exceeds_candidates():
+    X, Q, _ = synth.workload("small", N=300, nq=5, cache=False)
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=16, bits=1, nlist=40)
+    ids, dists = ix.search(torch.from_numpy(Q).cuda(), 64, 1)
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    path = os.path.join(tempfile.mkdtemp(), "p.mrqx")
+    ix.export(path)
+    orc = oracle.Index.load_export(path, X)
+    for i in range(5):
+        lists, _ = orc.probe(Q[i], 1)
+        off = orc.get("off")
+        n = int(off[lists[0] + 1] - off[lists[0]])
+        assert np.all(ids[i, :n] >= 0) and np.all(ids[i, n:] == -1) and np.all(np.isinf(dists[i, n:]))
+        assert set(ids[i, :n].tolist()) == set(orc.get("lid")[off[lists[0]]:off[lists[0] + 1]].tolist())
+
+
+def test_full_dimension_rabitq_mode():
+    """d_r = D: no residual terms (the IVF + RaBitQ special case)."""
+    X, Q, _ = synth.workload("small", N=8000, nq=30, cache=False)
+    env = dict(X=X, Q=Q, Qd=torch.from_numpy(Q).cuda(), nlist=32)
+    env["ix"] = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=128, bits=1, nlist=32)
+    path = os.path.join(tempfile.mkdtemp(), "f.mrqx")
+    env["ix"].export(path)
+    env["orc"] = oracle.Index.load_export(path, X)
+    assert np.abs(oracle.Index.load_export(path).get("tx")).max() == 0
+    ids, dists = _search(env, 10, 6)
+    _assert_parity(env, ids, dists, 10, 6)
+
+
+def test_invalid_arguments_rejected(small):
+    with pytest.raises(mrq.MRQError) as e:
+        small["ix"].search(small["Qd"], 0, 8)
+    assert e.value.status == mrq.MRQ_EINVAL
+    with pytest.raises(mrq.MRQError):
+        small["ix"].search(small["Qd"], 10, small["nlist"] + 1)
+    bad = small["X"][:500].copy()
+    bad[7, 3] = np.nan
+    with pytest.raises(mrq.MRQError) as e:
+        mrq.Index.build(torch.from_numpy(bad).cuda(), d_r=16, bits=1, nlist=4)
+    assert e.value.status == mrq.MRQ_EINVAL
+
+
+def test_save_load_roundtrip(small):
+    path = os.path.join(tempfile.mkdtemp(), "s.mrqs")
+    small["ix"].save(path)
+    ix2 = mrq.Index.load(path)
+    a, b = _search(small, 10, 8)
+    c, d = ix2.search(small["Qd"], 10, 8)
+    torch.cuda.synchronize()
+    assert np.array_equal(a, c.cpu().numpy()) and np.array_equal(b, d.cpu().numpy())
