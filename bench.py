@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched MRQ search on one MI355X.
+
+Metric: queries per second of the batched search at the smallest nprobe whose recall@10 against
+exact brute-force ground truth is >= 0.95, on the GIST-shaped synthetic workload (N = 1,000,000,
+D = 960, 10,000 queries, nlist = 4,096, d_r = 128, 1-bit codes, k = 10).  A step is one batched
+search of all queries (projection, probe, query codes, seed pass, phased scans, top-k) with the
+index and the queries resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock: 39.3 T lane-ops/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def ground_truth(torch, Xd, Qd, k, extra=32, chunk=1024):
+    """Exact top-k (ties -> smaller id): FP32 distance tiles on the GPU pick k + extra candidates,
+    which are re-scored in FP64."""
+    xn = (Xd * Xd).sum(1)
+    out = []
+    for s in range(0, Qd.shape[0], chunk):
+        q = Qd[s:s + chunk]
+        d = xn[None, :] - 2.0 * (q @ Xd.T)
+        cand = torch.topk(d, k + extra, dim=1, largest=False).indices
+        cand, _ = torch.sort(cand, dim=1)
+        dd = ((Xd[cand].double() - q.double()[:, None, :]) ** 2).sum(-1)
+        order = torch.argsort(dd, dim=1, stable=True)
+        out.append(torch.gather(cand, 1, order)[:, :k])
+        del d, dd
+    return torch.cat(out).cpu().numpy()
+
+
+def recall(ids, gt, k):
+    import numpy as np
+    hit = 0
+    for a, b in zip(ids[:, :k], gt[:, :k]):
+        hit += len(set(a.tolist()) & set(b.tolist()))
+    return hit / (gt.shape[0] * k)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gist1m")
+    ap.add_argument("--N", type=int, default=None)
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--nlist", type=int, default=4096)
+    ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--bits", type=int, default=1)
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (0 = smallest reaching the recall)")
+    ap.add_argument("--target-recall", type=float, default=0.95)
+    ap.add_argument("--per-query", type=int, default=200, help="queries timed on the per-query path")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline time budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="skip GT/sweep/baselines (profiler runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this search path runs on a single MI355X "
+              "and reports single-GPU throughput; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2411_06158_amd as mrq
+    from paper_2411_06158_amd import synth
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    X, Q, spec = synth.workload(args.workload, N=args.N, nq=args.nq)
+    N, D = X.shape
+    nq = Q.shape[0]
+    log(f"data {N}x{D}, {nq} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    ix = mrq.Index.build(Xd, d_r=args.d, bits=args.bits, nlist=args.nlist)
+    build_s = time.time() - t1
+    log(f"build {build_s:.1f}s, index {ix.device_bytes / 2**30:.2f} GiB")
+
+    k = args.k
+    ids_buf = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
+
+    def run(nprobe, counters=None, mode=mrq.MRQ_BATCHED, Qs=None, ib=None, db=None):
+        o = mrq.search_opts(mode=mode, counters=counters)
+        Qs = Qd if Qs is None else Qs
+        return ix.search(Qs, k, nprobe, ids=ids_buf if ib is None else ib, dists=d_buf if db is None else db,
+                         opts=o)
+
+    chosen, rec_at = args.nprobe, None
+    sweep = []
+    if not args.profile_only:
+        t2 = time.time()
+        gt = ground_truth(torch, Xd, Qd, k)
+        log(f"ground truth {time.time() - t2:.1f}s")
+        cands = [args.nprobe] if args.nprobe else [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+        for npb in cands:
+            if npb > args.nlist:
+                break
+            run(npb)
+            torch.cuda.synchronize()
+            r = recall(ids_buf.cpu().numpy(), gt, k)
+            sweep.append((npb, r))
+            log(f"nprobe {npb}: recall@{k} {r:.4f}")
+            chosen, rec_at = npb, r
+            if r >= args.target_recall:
+                break
+    if not chosen:
+        chosen = 64
+
+    # timed region: W warm-up steps, then K steps with per-kernel HIP events and device counters
+    for _ in range(args.warmup):
+        run(chosen)
+    torch.cuda.synchronize()
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    ix.timing_enable(True, reset=True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        run(chosen, counters=cnt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    ix.timing_enable(False, reset=False)
+    kt = ix.timing()
+    cnt = cnt.cpu().numpy() / args.steps
+    qps = nq * args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"batched: {qps:,.0f} QPS, {ms_step:.2f} ms/step at nprobe {chosen}")
+    log("kernel ms/step: " + ", ".join(f"{n}={v[0] / args.steps:.3f}" for n, v in kt.items()))
+
+    # roofline of the dominant kernel (the phased list-major scan)
+    d, B, bq = args.d, args.bits, 4
+    W = (d + 31) // 32
+    scan_ms, scan_launches = kt.get("scan", (0.0, 0))
+    scanned, p1, pext, p2 = (float(x) for x in cnt[:4])
+    pairs_scan = nq * (chosen - 1)
+    rec_bytes = d / 8 + 12
+    alg_bytes = (scanned * rec_bytes + (p1 * ((B - 1) * d / 8 + 8) if B > 1 else 0.0)
+                 + pext * (4 * d + 4) + p2 * 4 * D + pairs_scan * (48 + bq * d / 8))
+    alg_ops = scanned * (2 * bq * W + 16)
+    per_launch_ms = scan_ms / max(scan_launches, 1)
+    launches_per_step = scan_launches / args.steps
+    bytes_per_launch = alg_bytes / max(launches_per_step, 1)
+    ops_per_launch = alg_ops / max(launches_per_step, 1)
+    gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    tops = ops_per_launch / (per_launch_ms * 1e-3) / 1e12 if per_launch_ms > 0 else 0.0
+    frac_hbm, frac_alu = gbs / HBM_PEAK_GBS, tops / VALU_PEAK_TOPS
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TOP/s",
+                "frac": round(frac_alu, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(frac_hbm, 4)}
+    roof.update({"kernel": "k_scan (phased list-major bit-code scan)", "traffic": None,
+                 "effective_pair_GBs": round(gbs, 1), "valu_TOPs": round(tops, 3),
+                 "launch_ms": round(per_launch_ms, 4), "launches_per_step": launches_per_step})
+
+    out_extra = {}
+    if not args.profile_only:
+        # the plain per-query GPU path at the same nprobe
+        npq = min(args.per_query, nq)
+        Qs = Qd[:npq].contiguous()
+        ib = torch.empty((npq, k), dtype=torch.int64, device=dev)
+        db = torch.empty((npq, k), dtype=torch.float32, device=dev)
+        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
+        torch.cuda.synchronize()
+        pq_qps = npq / (time.perf_counter() - tp)
+        same = bool(torch.equal(ib, ids_buf[:npq]))
+        log(f"per-query path: {pq_qps:,.0f} QPS (ids identical to batched: {same})")
+        out_extra.update({"per_query_qps": round(pq_qps, 1), "speedup_vs_per_query": round(qps / pq_qps, 1),
+                          "per_query_matches_batched": same})
+
+    cpu = None
+    if not args.profile_only and not args.no_cpu_baseline:
+        import oracle
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "bench.mrqx")
+            ix.export(path)
+            orc = oracle.Index.load_export(path).attach(X)
+            prm = oracle.params()
+            n, tc = 0, time.perf_counter()
+            while n < nq and time.perf_counter() - tc < args.cpu_seconds:
+                orc.search(Q[n], k, chosen, mode=oracle.ALG2, prm=prm)
+                n += 1
+            el = time.perf_counter() - tc
+            cpu = {"value": round(n / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                   "sample": f"first {n} queries, single-threaded FP64 Algorithm 2 on the exported index, "
+                             f"nprobe {chosen}, k {k}"}
+            log(f"cpu oracle: {cpu['value']} QPS over {n} queries")
+
+    res = {
+        "metric": "QPS at recall@10=0.95 (1 GPU, batched vs per-query); scan HBM GB/s vs peak",
+        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} d_r={args.d} "
+                               f"bits={args.bits} k={k}",
+                   "N": N, "D": D, "nq": nq, "nlist": args.nlist, "d_r": args.d, "bits": args.bits, "k": k,
+                   "nprobe": chosen, "recall_at_10": None if rec_at is None else round(rec_at, 4),
+                   "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "build_s": round(build_s, 2),
+        "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in kt.items()},
+        "pass_rates": {"stage1": round(p1 / max(scanned, 1), 5), "stage2_exact": round(p2 / max(scanned, 1), 6),
+                       "seed_scanned_per_query": round(float(cnt[4]) / nq, 1),
+                       "scanned_per_query": round(scanned / nq, 1)},
+        "nprobe_sweep": sweep,
+    }
+    res.update(out_extra)
+    print(json.dumps(res), flush=True)
+    ix.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -71,8 +71,10 @@ typedef struct {
     float m;                /* Eq 6 / Chebyshev multiplier; eps_r = 2 m sigma; default 3 */
     int32_t stage2;         /* 1 = use the Eq 7 projected-distance stage (MRQ+), 0 = plain MRQ; default 1 */
     int32_t use_ext;        /* 1 = refine stage-1 survivors with the B-bit code when B > 1; default 1 */
-    int64_t *counters;      /* optional device or host int64[8]: scanned, pass1, pass_ext, pass2,
-                               seed_exact, items, 0, 0 (accumulated, not cleared) */
+    int64_t *counters;      /* optional device or host int64[8], accumulated (not cleared):
+                               [0..3] batched scan: candidates scanned, stage-1 survivors, B-bit
+                               survivors, exact distances; [4..7] the same for the seed pass over
+                               each query's nearest list */
     int32_t group;          /* queries per scan work item (0 = autotuned) */
     int32_t reserved[5];
 } mrq_search_opts;

@@ -70,6 +70,7 @@ def lib():
                                 C.c_int32]
         L.orc_import.restype = P
         L.orc_import.argtypes = [C.c_char_p, P, C.c_int64, C.c_int32]
+        L.orc_attach.argtypes = [P, P, C.c_int64, C.c_int32]
         L.orc_free.argtypes = [P]
         L.orc_info.argtypes = [P, P, P, P, P, P]
         L.orc_get.argtypes = [P, C.c_char_p, P]
@@ -200,6 +201,14 @@ class Index:
         else:
             h = lib().orc_import(path.encode(), None, 0, 0)
         return cls(h, X)
+
+    def attach(self, X):
+        """Use the stored per-vector summaries of an export, with X for the exact distances."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        if lib().orc_attach(self._h, _p(X), X.shape[0], X.shape[1]) != 0:
+            raise ValueError("shape of X does not match the index")
+        self._X = X
+        return self
 
     def __del__(self):
         try:

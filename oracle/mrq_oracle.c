@@ -585,6 +585,13 @@ orc_index *orc_import(const char *path, const float *X, int64_t Nx, int32_t Dx) 
     return ix;
 }
 
+/* Give an index imported without X the caller-owned original vectors (exact distances only). */
+int orc_attach(orc_index *ix, const float *X, int64_t N, int32_t D) {
+    if (!ix || N != ix->N || D != ix->D) return -1;
+    ix->X = X;
+    return 0;
+}
+
 int orc_info(const orc_index *ix, int64_t *N, int32_t *D, int32_t *d, int32_t *B, int32_t *nlist) {
     if (!ix) return -1;
     *N = ix->N; *D = ix->D; *d = ix->d; *B = ix->B; *nlist = ix->nlist;

@@ -62,6 +62,7 @@ int orc_kmeans(const double *P, int64_t n, int dim, int k, uint64_t seed, int it
 orc_index *orc_build(const float *X, int64_t N, int32_t D, int32_t d, int32_t B, int32_t nlist,
                      uint64_t seed, int32_t kmeans_iters);
 orc_index *orc_import(const char *path, const float *X, int64_t N, int32_t D);
+int orc_attach(orc_index *ix, const float *X, int64_t N, int32_t D);
 void orc_free(orc_index *ix);
 int orc_info(const orc_index *ix, int64_t *N, int32_t *D, int32_t *d, int32_t *B, int32_t *nlist);
 int orc_get(const orc_index *ix, const char *name, void *out);

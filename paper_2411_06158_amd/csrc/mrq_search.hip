@@ -921,11 +921,10 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c, const int64_t* __restric
     unsigned long long* out = c.slots + c.slot_off[q];
     for (int i = lane; i < k; i += 64) out[i] = i < have ? tk[cur][i] : kEmptyKey;
     if (c.counters && lane == 0) {
-        atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
-        atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
-        atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
-        atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)n2);
-        atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)n2);
+        atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)nscan);
+        atomicAdd((unsigned long long*)&c.counters[5], (unsigned long long)n1);
+        atomicAdd((unsigned long long*)&c.counters[6], (unsigned long long)next);
+        atomicAdd((unsigned long long*)&c.counters[7], (unsigned long long)n2);
     }
 }
 

@@ -124,23 +124,40 @@ def build_model(spec: MixtureSpec) -> MixtureModel:
 
 
 def sample(model: MixtureModel, n: int, draw_seed: int, chunk: int = 65536) -> np.ndarray:
-    """n points of the mixture as a C-contiguous float32 array (n x D)."""
+    """n points of the mixture as a C-contiguous float32 array (n x D).
+
+    Rows are drawn in fixed chunks of 65,536, each from its own seeded stream, so the result does
+    not depend on how many threads produce it."""
     spec = model.spec
-    rng = np.random.default_rng([spec.model_seed, 0xD7A1, draw_seed])
-    comp = rng.choice(spec.n_comp, size=n, p=model.weights)
+    chunk = 65536
     out = np.empty((n, spec.D), dtype=np.float32)
     centres32 = model.centres.astype(np.float32)
     mixT = np.ascontiguousarray(model.mix.T)
-    for s in range(0, n, chunk):
+
+    def one(ci: int):
+        s = ci * chunk
         e = min(n, s + chunk)
+        rng = np.random.default_rng([spec.model_seed, 0xD7A1, draw_seed, ci])
+        comp = rng.choice(spec.n_comp, size=e - s, p=model.weights)
         z = rng.standard_normal((e - s, spec.D), dtype=np.float32)
         blk = z @ mixT
-        blk += centres32[comp[s:e]]
+        blk += centres32[comp]
         if spec.normalize:
-            nrm = np.sqrt(np.einsum("ij,ij->i", blk.astype(np.float64), blk.astype(np.float64)))
+            b64 = blk.astype(np.float64)
+            nrm = np.sqrt(np.einsum("ij,ij->i", b64, b64))
             nrm[nrm == 0] = 1.0
-            blk = (blk / nrm[:, None]).astype(np.float32)
+            blk = (b64 / nrm[:, None]).astype(np.float32)
         out[s:e] = blk
+
+    nchunks = (n + chunk - 1) // chunk
+    if nchunks <= 1:
+        for ci in range(nchunks):
+            one(ci)
+    else:
+        import concurrent.futures as cf
+        workers = max(1, min(16, os.cpu_count() or 1))
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(nchunks)))
     return out
 
 

@@ -182,8 +182,9 @@ def test_mixed_k_nprobe(small):
 def test_counters_monotone(small):
     cnt = np.zeros(8, dtype=np.int64)
     small["ix"].search(small["Q"][:20].copy(), 10, 8, counters=cnt)
-    scanned, p1, pext, p2 = cnt[:4]
-    assert scanned > 0 and scanned >= p1 >= pext >= p2 > 0
+    for part in (cnt[:4], cnt[4:]):
+        scanned, p1, pext, p2 = part
+        assert scanned > 0 and scanned >= p1 >= pext >= p2 > 0
 
 
 # ---- edge cases -----------------------------------------------------------------------------------
