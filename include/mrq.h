@@ -150,17 +150,27 @@ int mrq_timing(const mrq_index *index, char *names, size_t cap, double *ms, int6
 mrq_status mrq_timing_enable(mrq_index *index, int on, int reset);
 
 /*
- * Serving (continuous batching).  A server owns a host thread that packs submitted requests into
- * batches of at most max_slots queries, admits a request only when the worst-case device memory of
- * its batch fits `mem_budget` bytes, runs batches on two streams so that a new batch starts while
- * the previous one is still on the device, and hands back results through mrq_server_poll.
- *   mrq_server_create: mem_budget 0 = no limit; max_slots in [1, 65536]
- *   mrq_server_submit: q_host is D floats (copied); returns MRQ_EINVAL for bad k / nprobe and
- *                      MRQ_ENOMEM only when the request could never fit the budget; otherwise it is
- *                      queued until it can be admitted
- *   mrq_server_poll:   copies up to max_done finished results (ids and dists rows of k_max entries,
- *                      k_max = the largest k the server accepts = 1024 -> the caller passes rows of
- *                      `row` entries) and returns how many were written, -1 on error
+ * Serving (continuous batching) of mrq_search for requests that arrive one at a time.  A server owns a
+ * host thread and two batch slots (each with its own stream, pinned staging buffers and device
+ * workspace).  Submitted requests wait in arrival order; whenever a slot is free the thread admits
+ * the waiting requests (up to max_slots per batch) whose batch still fits the device-memory budget
+ * left by the other slot, copies them to the device, runs one mixed-k / nprobe batched search and
+ * copies the results back on the slot's stream, so a new batch is packed and launched while the
+ * previous one is still on the device.  A request's result is the same as mrq_search's for that query
+ * alone (search results do not depend on the batch).
+ *   mrq_server_create:  mem_budget = device bytes both slots may use together (0 = no limit);
+ *                       max_slots in [1, 65536] queries per batch; opts as for mrq_search (mode and
+ *                       counters are ignored); the index must outlive the server
+ *   mrq_server_submit:  q_host = D floats (copied before return); MRQ_EINVAL for a bad k or nprobe,
+ *                       MRQ_ENOMEM when one such request alone would exceed the budget; otherwise the
+ *                       request is queued until it can be admitted
+ *   mrq_server_poll:    moves up to max_done finished requests out: req_ids[i], ks[i] (may be NULL),
+ *                       ids / dists rows of stride `row` (>= the request's k), latency_ms[i] = arrival
+ *                       to completion (may be NULL; -1 if the batch failed, its row is -1 / +inf);
+ *                       returns the number written, or -1 on bad arguments
+ *   mrq_server_drain:   waits until every submitted request has finished; MRQ_ESTATE on timeout
+ *   mrq_server_destroy: stops the thread after the batches in flight and frees the server
+ * The submit / poll / drain calls are thread-safe.
  */
 mrq_status mrq_server_create(const mrq_index *index, size_t mem_budget, int32_t max_slots,
                              const mrq_search_opts *opts, mrq_server **out);
@@ -168,8 +178,6 @@ mrq_status mrq_server_submit(mrq_server *server, uint64_t req_id, const float *q
                              int32_t nprobe);
 int mrq_server_poll(mrq_server *server, uint64_t *req_ids, int32_t *ks, int64_t *ids, float *dists,
                     int32_t row, int32_t max_done, double *latency_ms);
-/* Wait until every submitted request has finished (or timeout_ms elapsed); returns MRQ_ESTATE on
- * timeout. */
 mrq_status mrq_server_drain(mrq_server *server, int64_t timeout_ms);
 void mrq_server_destroy(mrq_server *server);
 

@@ -15,11 +15,6 @@
 
 #include "mrq_internal.h"
 
-struct mrq_index : mrq::Index {
-    hipEvent_t ws_event = nullptr;  // last use of the default search workspace
-    bool ws_event_recorded = false;
-};
-
 namespace mrq {
 
 namespace {
@@ -550,7 +545,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         *d_s = d_dev ? nullptr : c.take<float>(out_total);
         *cnt_s = cnt_host ? c.take<int64_t>(8) : nullptr;
         *sw = base ? base + c.used : nullptr;
-        *used = c.used + search_workspace_bytes(*ix, nq_run, slots_run, pairs_run, o.bq);
+        *used = c.used + search_workspace_bytes(*ix, nq_run, slots_run, pairs_run, o.bq, np_max);
     };
     int32_t *kq, *npq;
     int64_t *so, *po, *oo, *ids_s, *cnt_s;

@@ -14,7 +14,7 @@ namespace mrq {
 
 constexpr int kWave = 64;        // gfx950 wavefront width
 constexpr int kBlockVecs = 64;   // vectors per code block = one vector per lane
-constexpr int kPhases = 6;       // probe-rank phases: {0}, [1,4), [4,16), [16,64), [64,256), [256,1024)
+constexpr int kPhases = 11;      // probe-rank phases: {0}, [1,2), [2,4), [4,8), ..., [512,1024)
 constexpr int kMaxK = 1024;
 constexpr int kMaxProbe = 1024;
 constexpr uint64_t kEmptyKey = ~0ull;
@@ -132,10 +132,11 @@ struct SearchArgs {
     int64_t* ids;          // device output
     float* dists;          // device output
     int64_t* counters;     // device int64[8] or null
+    bool timed = true;     // record per-kernel events when the index timer is on
 };
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,
-                              int bq);
+                              int bq, int np_max);
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
 
 // build-side launchers
@@ -175,3 +176,9 @@ hipError_t launch_check_finite(const float* X, int64_t n, int32_t* bad, hipStrea
 void eigh_host(const double* A, int n, double* evals, double* evecs_rows);
 
 }  // namespace mrq
+
+// The opaque handle of the C ABI.
+struct mrq_index : mrq::Index {
+    hipEvent_t ws_event = nullptr;  // last use of the default search workspace
+    bool ws_event_recorded = false;
+};

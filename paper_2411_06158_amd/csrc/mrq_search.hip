@@ -64,29 +64,69 @@ __device__ __forceinline__ uint32_t ord_bits(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Exact squared distance (Algorithm 2, exact stage) of two zero-padded rows of D4 floats: lane l
-// accumulates floats [4l, 4l+4) of every 256-float chunk in ascending order, then a butterfly sum.
-__device__ __forceinline__ float exact_dist_wave(const float* __restrict__ x, const float* __restrict__ q,
-                                                 int D4, int lane) {
+// Exact squared distance (Algorithm 2, exact stage) of two zero-padded rows of D4 floats, computed
+// by a group of 16 lanes: lane l of the group accumulates the float4 chunks l, l + 16, l + 32, ... in
+// ascending order, then a butterfly over the group.  A wave evaluates four pairs at once; the value of
+// a pair depends only on its two rows.
+__device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, const float* __restrict__ q,
+                                                  int D4, int l16) {
+    const int nc = D4 >> 2;  // float4 chunks per row
+    const float4* __restrict__ xa = reinterpret_cast<const float4*>(x);
+    const float4* __restrict__ qa = reinterpret_cast<const float4*>(q);
     float s = 0.f;
-    for (int i = lane * 4; i < D4; i += 256) {
-        float4 a = *reinterpret_cast<const float4*>(x + i);
-        float4 b = *reinterpret_cast<const float4*>(q + i);
-        float t;
-        t = a.x - b.x; s = fmaf(t, t, s);
-        t = a.y - b.y; s = fmaf(t, t, s);
-        t = a.z - b.z; s = fmaf(t, t, s);
-        t = a.w - b.w; s = fmaf(t, t, s);
+    for (int base = 0; base < nc; base += 128) {  // 8 chunks per lane in flight per round
+        float4 a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int ci = base + 16 * u + l16;
+            a[u] = ci < nc ? xa[ci] : make_float4(0.f, 0.f, 0.f, 0.f);
+            b[u] = ci < nc ? qa[ci] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            if (base + 16 * u + l16 >= nc) break;
+            float t;
+            t = a[u].x - b[u].x; s = fmaf(t, t, s);
+            t = a[u].y - b[u].y; s = fmaf(t, t, s);
+            t = a[u].z - b[u].z; s = fmaf(t, t, s);
+            t = a[u].w - b[u].w; s = fmaf(t, t, s);
+        }
     }
-    return wave_sum(s);
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    return s;
 }
 
-// <x_d, q_d> of Eq 7 evaluated by one lane in ascending dimension order (rows zero padded to d4).
+// <x_d, q_d> of Eq 7 evaluated by one lane in ascending dimension order (rows zero padded to d4);
+// every stage-2 value of the search is computed this way.  dot_lane keeps four float4 of each row in
+// flight per round; dot_lane_small is the low-register form with the same operation order.
 __device__ __forceinline__ float dot_lane(const float* __restrict__ a, const float* __restrict__ b, int d4) {
+    const int nc = d4 >> 2;
+    const float4* __restrict__ xa = reinterpret_cast<const float4*>(a);
+    const float4* __restrict__ ya = reinterpret_cast<const float4*>(b);
+    float s = 0.f;
+    for (int base = 0; base < nc; base += 4) {
+        float4 x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            x[u] = base + u < nc ? xa[base + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            y[u] = base + u < nc ? ya[base + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (base + u >= nc) break;
+            s = fmaf(x[u].x, y[u].x, s);
+            s = fmaf(x[u].y, y[u].y, s);
+            s = fmaf(x[u].z, y[u].z, s);
+            s = fmaf(x[u].w, y[u].w, s);
+        }
+    }
+    return s;
+}
+__device__ __forceinline__ float dot_lane_small(const float* __restrict__ a, const float* __restrict__ b, int d4) {
     float s = 0.f;
     for (int i = 0; i < d4; i += 4) {
-        float4 x = *reinterpret_cast<const float4*>(a + i);
-        float4 y = *reinterpret_cast<const float4*>(b + i);
+        const float4 x = *reinterpret_cast<const float4*>(a + i);
+        const float4 y = *reinterpret_cast<const float4*>(b + i);
         s = fmaf(x.x, y.x, s);
         s = fmaf(x.y, y.y, s);
         s = fmaf(x.z, y.z, s);
@@ -95,30 +135,40 @@ __device__ __forceinline__ float dot_lane(const float* __restrict__ a, const flo
     return s;
 }
 
-// Insert a (distance, id) key into a query's sorted k-slot array.  Each slot only ever decreases,
-// so the array stays sorted and any snapshot of slot k-1 bounds the final k-th distance from above.
+// Take up to four set lanes of *mask (lowest first) and give each 16-lane group one of them: returns
+// the source lane of this lane's group, or -1.
+__device__ __forceinline__ int take4(unsigned long long* mask, int lane) {
+    int src = -1;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const int s = *mask ? __ffsll((long long)*mask) - 1 : -1;
+        if (s >= 0) *mask &= *mask - 1;
+        if ((lane >> 4) == g) src = s;
+    }
+    return src;
+}
+
+// Insert a (distance, id) key into a query's sorted k-slot array.  Each slot only ever decreases
+// (atomicMin), so the array stays sorted and the final content is the k smallest keys inserted,
+// whatever the order of the inserts.
 __device__ void topk_insert(unsigned long long* slots, int k, unsigned long long key) {
     volatile unsigned long long* vs = slots;
     if (key >= vs[k - 1]) return;
     int lo = 0, hi = k - 1;
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (vs[mid] > key) hi = mid; else lo = mid + 1;
     }
     for (int i = lo; i < k; i++) {
-        unsigned long long old = atomicMin(slots + i, key);
+        const unsigned long long old = atomicMin(slots + i, key);
         if (old > key) key = old;
         if (key == kEmptyKey) return;
     }
 }
 
-__device__ __forceinline__ int phase_of(int r) {
-    if (r == 0) return 0;
-    int p = 1, bound = 4;
-    while (r >= bound) { p++; bound <<= 2; }
-    return p;
-}
-__host__ __device__ __forceinline__ int phase_lo(int p) { return p == 0 ? 0 : (1 << (2 * (p - 1))); }
+// Probe-rank phases: rank 0 (the seed pass), then [1, 2), [2, 4), [4, 8), ... [512, 1024).
+__device__ __forceinline__ int phase_of(int r) { return r == 0 ? 0 : 32 - __clz(r); }
+__host__ __device__ __forceinline__ int phase_lo(int p) { return p == 0 ? 0 : (1 << (p - 1)); }
 
 // ------------------------------------------------------------------------------------------------
 // fill helpers (kernels rather than memset nodes so the sequence can be captured in a graph)
@@ -474,6 +524,7 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
 //   v_l = min q', Delta = (max q' - v_l) / (2^bq - 1), u_i = floor((q'_i - v_l) * (1/Delta) + 1/2)
 // (each step one IEEE-rounded FP32 operation, no contraction); bit plane b of u is written as d-bit
 // masks, together with the pair's scalars.
+template <int NH>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
     const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
@@ -492,9 +543,10 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
     pos = __shfl(pos, 0);
     if (lane == 0) pair_pos[pi] = pos;
-    const int nh = (d + 63) / 64;  // dims per lane
-    float wv[24];                  // d <= 1536
+    constexpr int nh = NH;  // dims per lane (lane l holds dims l, l + 64, ...)
+    float wv[NH];
     float n2 = 0.f;
+#pragma unroll
     for (int h = 0; h < nh; h++) {
         int i = lane + 64 * h;
         float v = 0.f;
@@ -505,6 +557,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     n2 = wave_sum(n2);
     const float nq = sqrtf(n2);
     float lo = FLT_MAX, hi = -FLT_MAX;
+#pragma unroll
     for (int h = 0; h < nh; h++) {
         int i = lane + 64 * h;
         float v = nq > 0.f ? __fdiv_rn(wv[h], nq) : 0.f;
@@ -516,10 +569,11 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     const int levels = (1 << bq) - 1;
     float delta = 1.f;
     int su = 0;
-    int uv[24];
+    int uv[NH];
     if (hi > lo) {
         delta = __fdiv_rn(__fsub_rn(hi, lo), (float)levels);
         const float inv = __fdiv_rn(1.f, delta);
+#pragma unroll
         for (int h = 0; h < nh; h++) {
             int i = lane + 64 * h;
             int u = 0;
@@ -532,18 +586,21 @@ __global__ __launch_bounds__(256) void k_pair_prep(
             su += u;
         }
     } else {
+#pragma unroll
         for (int h = 0; h < nh; h++) uv[h] = 0;
     }
     su = wave_sum_i(su);
     uint32_t* pl = planes + (int64_t)pos * bq * WP;
     for (int b = 0; b < bq; b++) {
-        for (int h = 0; h < (WP + 1) / 2; h++) {
-            unsigned long long bm = __ballot(h < nh && ((uv[h < nh ? h : 0] >> b) & 1));
+#pragma unroll
+        for (int h = 0; h < (NH > 0 ? NH : 1); h++) {
+            unsigned long long bm = __ballot(((uv[h] >> b) & 1) != 0);
             if (lane == 0) {
                 if (2 * h < WP) pl[b * WP + 2 * h] = (uint32_t)bm;
                 if (2 * h + 1 < WP) pl[b * WP + 2 * h + 1] = (uint32_t)(bm >> 32);
             }
         }
+        for (int w = 2 * NH + lane; w < WP; w += 64) pl[b * WP + w] = 0u;  // words beyond the last lane dim
     }
     if (lane == 0) {
         PairRec R;
@@ -626,6 +683,7 @@ struct ScanCtx {
     const int32_t* ioff;
     const int64_t* list_off;
     const int32_t* list_nb;
+    const int32_t* list_len;
     const uint32_t* code;
     const uint32_t* ext;
     const float *fA, *fF, *fE, *fFB, *fEB, *fSX;
@@ -636,93 +694,114 @@ struct ScanCtx {
     const float* qd;
     const float* qpad;
     const float* qn2;
+    const float* er;
     const int32_t* kq;
+    const int32_t* npq;
     const int64_t* slot_off;
+    const int64_t* pair_off;
+    const int32_t* pair_pos;
     unsigned long long* slots;
-    int32_t* wcount;
+    int2* surv1;         // stage-1 survivors of the current phase: (row, pair record position)
+    int2* surv2;         // stage-2 survivors of the current phase: (row, query)
+    int32_t* cnt;        // [0] stage-1 survivors appended, [1] stage-2 survivors appended
     int64_t* counters;
-    int nlist, d, d4, D4, B, bq, G, stage2, use_ext, phase;
+    int nlist, d, d4, D4, B, bq, G, stage2, use_ext, phase, k_max, cap;
 };
 
-// Survivor queue of one wave: (row, record position) pairs in LDS.
-struct Surv { int32_t row, pos; };
+__device__ __forceinline__ float ord_to_float(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
 
-// Ext refinement, Eq 7 re-check and exact distance for up to 64 queued survivors (one per lane),
-// then the exact stage wave-cooperatively for each remaining survivor and the top-k insert.
+// ------------------------------------------------------------------------------------------------
+// Batched stage-1 scan of one phase (list-major, persistent).  A work item is (list j, 64-row block,
+// chunk of up to GT pair records of list j in this phase): the wave loads its block's codes and
+// factors once and tests them against every pair of the chunk, each pair's scalars and bit planes
+// arriving through scalar loads.  Survivors (LB < the phase threshold of their query) are appended to
+// the phase's survivor buffer with one atomic per item.  Every decision of a phase uses the fixed
+// phase threshold, so the set of candidates that reach each stage does not depend on the order in
+// which they are processed.
+
+// Stages after stage 1 for the survivors of one wave, processed in place (used when the survivor
+// buffer is full): B-bit refinement and Eq 7 re-check per lane, exact distances four at a time.
+// Low-register form of exact_dist_group with the same operation order (hence the same results), for
+// the rarely taken in-place path of the scan kernel.
+__device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
+                                                        int D4, int l16) {
+    float s = 0.f;
+    for (int ci = l16; ci < (D4 >> 2); ci += 16) {
+        const float4 a = reinterpret_cast<const float4*>(x)[ci];
+        const float4 b = reinterpret_cast<const float4*>(q)[ci];
+        float t;
+        t = a.x - b.x; s = fmaf(t, t, s);
+        t = a.y - b.y; s = fmaf(t, t, s);
+        t = a.z - b.z; s = fmaf(t, t, s);
+        t = a.w - b.w; s = fmaf(t, t, s);
+    }
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
 template <int WP>
-__device__ void flush_queue(const ScanCtx& c, Surv* qu, int n, int lane, long long* cnt_ext,
-                            long long* cnt2) {
-    int row = 0, q = 0;
-    bool pass = lane < n;
+__device__ void finish_inline(const ScanCtx& c, bool pass, int64_t row, int pos, int lane) {
+    int q = 0;
     float tau = 0.f, er = 0.f;
     if (pass) {
-        row = qu[lane].row;
-        const int pos = qu[lane].pos;
         const PairRec R = c.recs[pos];
         q = R.q;
         tau = R.tau;
         er = R.er;
         if (c.B > 1 && c.use_ext) {
             const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
-            float lb = ext_lb(c.code + (int64_t)row * WP, c.ext + (int64_t)row * (c.B - 1) * WP, c.B, WP,
-                              c.fA[row], c.fFB[row], c.fEB[row], c.fSX[row], R, U, c.bq);
-            pass = lb < tau;
+            pass = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
+                          c.fEB[row], c.fSX[row], R, U, c.bq) < tau;
+        }
+        if (pass && c.stage2) {
+            const float dot = dot_lane_small(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < tau;
         }
     }
-    *cnt_ext += __popcll(__ballot(pass));
-    if (pass && c.stage2) {
-        float dot = dot_lane(c.xd + (int64_t)row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-        float diso = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]);
-        pass = diso - er < tau;
-    }
     unsigned long long m2 = __ballot(pass);
-    *cnt2 += __popcll(m2);
     while (m2) {
-        const int s = __ffsll((long long)m2) - 1;
-        m2 &= m2 - 1;
-        const int rs = __shfl(row, s);
-        const int qs = __shfl(q, s);
-        float dist = exact_dist_wave(c.X + (int64_t)rs * c.D4, c.qpad + (int64_t)qs * c.D4, c.D4, lane);
-        if (lane == 0) {
-            unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+        const int src = take4(&m2, lane);
+        const int64_t rs = __shfl(row, src < 0 ? 0 : src);
+        const int qs = __shfl(q, src < 0 ? 0 : src);
+        const float dist = exact_dist_group_small(c.X + rs * c.D4, c.qpad + (int64_t)qs * c.D4, c.D4, lane & 15);
+        if (src >= 0 && (lane & 15) == 0) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
             topk_insert(c.slots + c.slot_off[qs], c.kq[qs], key);
         }
     }
 }
 
-// Persistent list-major scan of one phase.  A work item is (list j, 64-row block, chunk of up to G
-// pair records of list j); a wave loads its block's codes and factors once and tests them against
-// every pair of the chunk, the pair's scalars and bit planes arriving through scalar loads.
-template <int WP, int BQT>
+template <int WP, int BQT, int GT>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
-    __shared__ Surv queue[4][128];
+    __shared__ unsigned long long sh_mask[4][GT];
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
-    Surv* qu = queue[wv];
     const int p = c.phase;
     const int* ioff = c.ioff + p * c.nlist;
-    const int base_item = ioff[0];
-    const int total = ioff[c.nlist] - base_item;
-    int qn = 0;
-    long long n1 = 0, next = 0, n2 = 0, nscan = 0;
-    for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(c.wcount + p, 1);
-        it = uniform(__shfl(it, 0));
-        if (it >= total) break;
+    const int base_item = (int)const_load((const uint32_t*)ioff);
+    const int total = (int)const_load((const uint32_t*)ioff + c.nlist) - base_item;
+    constexpr int NBQ = BQT > 0 ? BQT : 8;
+    const int bq = BQT > 0 ? BQT : c.bq;
+    const int64_t pstride = (int64_t)bq * WP;
+    long long nscan = 0, n1 = 0;
+    // items are dealt to the waves round-robin: neighbouring waves take neighbouring blocks of a list
+    const int nwaves = gridDim.x * 4;
+    for (int it = blockIdx.x * 4 + wv; it < total; it += nwaves) {
         const int git = base_item + it;
         int lo = 0, hi = c.nlist - 1;  // last list j with ioff[j] <= git
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (ioff[mid] <= git) lo = mid; else hi = mid - 1;
+            if ((int)const_load((const uint32_t*)ioff + mid) <= git) lo = mid; else hi = mid - 1;
         }
         const int j = uniform(lo);
-        const int local = git - ioff[j];
+        const int local = git - (int)const_load((const uint32_t*)ioff + j);
         const int nb = c.list_nb[j];
         const int blk = local % nb, ch = local / nb;
-        const int pbeg = c.boff[p * c.nlist + j] + ch * c.G;
+        const int pbeg = c.boff[p * c.nlist + j] + ch * GT;
         const int pend0 = c.boff[p * c.nlist + j + 1];
-        const int pend = pbeg + c.G < pend0 ? pbeg + c.G : pend0;
+        const int ng = uniform(pbeg + GT < pend0 ? GT : pend0 - pbeg);
         const int64_t row = c.list_off[j] + (int64_t)blk * 64 + lane;
         uint32_t cw[WP];
 #pragma unroll
@@ -731,57 +810,126 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 #pragma unroll
         for (int w = 0; w < WP; w++) pc += __builtin_popcount(cw[w]);
         const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
-        constexpr int NBQ = BQT > 0 ? BQT : 8;
-        const int bq = BQT > 0 ? BQT : c.bq;
-        const int64_t pstride = (int64_t)bq * WP;
-        // pair records and planes are read-only during the scan: scalar loads
-        for (int pos = pbeg; pos < pend; pos++) {
-            const PairRec R = const_load(c.recs + pos);
-            uint32_t U[NBQ * WP];
+        int nsurv = 0;
 #pragma unroll
-            for (int t = 0; t < NBQ * WP; t++) U[t] = t < bq * WP ? const_load(c.planes + pos * pstride + t) : 0u;
-            const float lb = stage1_lb<WP, BQT>(cw, pc, A, F, E, R, U, bq, c.d);
-            const unsigned long long m = __ballot(lb < R.tau);
-            nscan += 64;
-            if (m) {
-                const int before = __popcll(m & ((1ull << lane) - 1ull));
-                if ((m >> lane) & 1ull) qu[qn + before] = Surv{(int32_t)row, pos};
-                const int add = __popcll(m);
-                n1 += add;
-                qn += add;
-                if (qn >= 64) {
-                    __threadfence_block();
-                    flush_queue<WP>(c, qu, 64, lane, &next, &n2);
-                    const int rest = qn - 64;
-                    Surv tmp;
-                    if (lane < rest) tmp = qu[64 + lane];
-                    __threadfence_block();
-                    if (lane < rest) qu[lane] = tmp;
-                    __threadfence_block();
-                    qn = rest;
+        for (int g = 0; g < GT; g++) {
+            if (g < ng) {
+                const int pos = pbeg + g;
+                const PairRec R = const_load(c.recs + pos);
+                uint32_t U[NBQ * WP];
+#pragma unroll
+                for (int t = 0; t < NBQ * WP; t++) U[t] = t < bq * WP ? const_load(c.planes + pos * pstride + t) : 0u;
+                const float lb = stage1_lb<WP, BQT>(cw, pc, A, F, E, R, U, bq, c.d);
+                const unsigned long long m = __ballot(lb < R.tau);
+                if (lane == 0) sh_mask[wv][g] = m;
+                nsurv += __popcll(m);
+            }
+        }
+        nscan += 64ll * ng;
+        n1 += nsurv;
+        if (nsurv == 0) continue;
+        __threadfence_block();
+        int base = 0;
+        if (lane == 0) base = atomicAdd(c.cnt, nsurv);
+        base = uniform(__shfl(base, 0));
+        int off = base;
+#pragma unroll
+        for (int g = 0; g < GT; g++) {
+            if (g < ng) {
+                const unsigned long long m = sh_mask[wv][g];
+                if (m) {
+                    const bool mine = (m >> lane) & 1ull;
+                    if (off + __popcll(m) <= c.cap) {
+                        if (mine) c.surv1[off + __popcll(m & ((1ull << lane) - 1ull))] = make_int2((int)row, pbeg + g);
+                    } else {
+                        finish_inline<WP>(c, mine, row, pbeg + g, lane);
+                    }
+                    off += __popcll(m);
                 }
             }
         }
-    }
-    if (qn > 0) {
         __threadfence_block();
-        flush_queue<WP>(c, qu, qn, lane, &next, &n2);
     }
-    if (c.counters && lane == 0) {
+    if (c.counters && lane == 0) {  // nscan and n1 are wave-uniform
         atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
         atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
+    }
+}
+
+// Stage-1 survivors -> B-bit refinement and Eq 7 re-check, one survivor per lane, grid-stride over the
+// phase's survivor buffer.
+template <int WP>
+__global__ __launch_bounds__(256) void k_stage2(ScanCtx c) {
+    const int lane = lane_id();
+    const int n = min(c.cnt[0], c.cap);
+    long long next = 0, n2 = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < n; i0 += stride) {
+        const int64_t i = i0 + lane;
+        bool pass = i < n;
+        int64_t row = 0;
+        int q = 0;
+        float tau = 0.f, er = 0.f;
+        if (pass) {
+            const int2 e = c.surv1[i];
+            row = e.x;
+            const PairRec R = c.recs[e.y];
+            q = R.q;
+            tau = R.tau;
+            er = R.er;
+            if (c.B > 1 && c.use_ext) {
+                const uint32_t* U = c.planes + (int64_t)e.y * c.bq * WP;
+                pass = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
+                              c.fEB[row], c.fSX[row], R, U, c.bq) < tau;
+            }
+        }
+        next += __popcll(__ballot(pass));
+        if (pass && c.stage2) {
+            const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < tau;
+        }
+        const unsigned long long m = __ballot(pass);
+        if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(c.cnt + 1, __popcll(m));
+            base = __shfl(base, 0);
+            if ((m >> lane) & 1ull) c.surv2[base + __popcll(m & ((1ull << lane) - 1ull))] = make_int2((int)row, q);
+            n2 += __popcll(m);
+        }
+    }
+    if (c.counters && lane == 0) {  // next and n2 are wave-uniform
         atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
         atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)n2);
     }
 }
 
-// ------------------------------------------------------------------------------------------------
-// Seed pass: each query's nearest list (probe rank 0) processed by one wave in increasing order of
-// the stage-1 estimate.  The first k candidates fill the result queue (their exact distances set
-// tau), the rest are tested against the running tau exactly as in Algorithm 2.  After this pass every
-// query with k candidates in its nearest list has a finite threshold for the batched phases.
+// Stage-2 survivors -> exact distances (16 lanes each, four per wave) and the result queues.
+__global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
+    const int lane = lane_id();
+    const int n = c.cnt[1];
+    const int64_t groups = (int64_t)gridDim.x * 16;  // 16-lane groups in the grid
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; i - (lane >> 4) < n; i += groups) {
+        const bool valid = i < n;
+        const int2 e = c.surv2[valid ? i : 0];
+        const float dist = exact_dist_group(c.X + (int64_t)e.x * c.D4, c.qpad + (int64_t)e.y * c.D4, c.D4, lane & 15);
+        if (valid && (lane & 15) == 0) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[e.x];
+            topk_insert(c.slots + c.slot_off[e.y], c.kq[e.y], key);
+        }
+    }
+}
 
-constexpr int kSeedChunk = 1024;
+// Query-major passes.  One wave owns one query: it holds the query's result queue in LDS (loaded from
+// and written back to the global slots), sorts a chunk of candidates by (lower bound, row) and walks
+// them in that order exactly as Algorithm 2 treats a candidate - stage-1 bound, B-bit refinement,
+// Eq 7 re-check, exact distance, queue update - with the threshold tau of the queue updated after
+// every batch of 64.  Because the chunk is sorted by lower bound, the walk stops at the first
+// candidate whose bound reaches tau.
+// The seed pass runs it over each query's nearest list (probe rank 0), so that the first batched phase
+// starts from a finite threshold.
+
+enum { PASS_SEED = 0 };
+constexpr int kChunk = 512;
 
 // sort 64 keys held one per lane, ascending (bitonic network over shuffles)
 __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
@@ -797,129 +945,173 @@ __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, 
     return v;
 }
 
-template <int WP, int BQT>
-__global__ __launch_bounds__(64) void k_seed(ScanCtx c, const int64_t* __restrict__ pair_off,
-                                             const int32_t* __restrict__ pair_pos,
-                                             const int32_t* __restrict__ list_len) {
-    __shared__ unsigned long long keys[kSeedChunk];
-    __shared__ float lbs[kSeedChunk];
-    __shared__ unsigned long long tk[2][kMaxK];
-    __shared__ unsigned long long nk[64];
-    const int q = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int pos0 = pair_pos[pair_off[q]];
-    const PairRec R = c.recs[pos0];
-    const uint32_t* U = c.planes + (int64_t)pos0 * (BQT > 0 ? BQT : c.bq) * WP;
-    const int j = R.list;
-    const int n = list_len[j];
-    const int64_t base = c.list_off[j];
-    const int k = c.kq[q];
-    const float er = R.er;
-    int cur = 0, have = 0;
-    float tau = INFINITY;
-    long long nscan = 0, n1 = 0, next = 0, n2 = 0;
-    for (int cs = 0; cs < n; cs += kSeedChunk) {
-        const int m = n - cs < kSeedChunk ? n - cs : kSeedChunk;
-        int P = 64;
-        while (P < m) P <<= 1;
-        for (int idx = lane; idx < P; idx += 64) {
-            if (idx < m) {
-                const int64_t row = base + cs + idx;
-                uint32_t cw[WP];
-                int pc = 0;
-#pragma unroll
-                for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
-                // the estimate itself (LB + radii) orders the walk; LB decides
-                const float lb = stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
-                const float dis = lb + R.ebc * c.fE[row] + er;
-                keys[idx] = ((unsigned long long)ord_bits(dis) << 32) | (uint32_t)idx;
-                lbs[idx] = lb;
-            } else {
-                keys[idx] = kEmptyKey;
+struct QueryState {
+    unsigned long long* tk[2];
+    int cur, have, k;
+    float tau;
+};
+
+// Sort keys/vals[0, P) ascending by key (one wave, LDS).
+__device__ void sort_chunk(unsigned long long* keys, int32_t* vals, int P, int lane) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = lane; i < P; i += 64) {
+                const int ixj = i ^ stride;
+                if (ixj > i) {
+                    const bool asc = (i & size) == 0;
+                    const unsigned long long a = keys[i], b = keys[ixj];
+                    if ((a > b) == asc) {
+                        keys[i] = b;
+                        keys[ixj] = a;
+                        const int32_t t = vals[i];
+                        vals[i] = vals[ixj];
+                        vals[ixj] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Walk m sorted candidates (key = ord(lb) << 32 | row, val = pair record position).
+template <int WP>
+__device__ void walk_chunk(const ScanCtx& c, int q, float er, const unsigned long long* keys,
+                           const int32_t* vals, int m, QueryState& st, unsigned long long* nk, int lane,
+                           long long* n1, long long* next, long long* n2) {
+    int at = 0;
+    while (at < m) {
+        const float lb0 = ord_to_float((uint32_t)(keys[at] >> 32));
+        if (!(lb0 < st.tau)) break;  // every later candidate has a bound >= tau
+        int bs = m - at < 64 ? m - at : 64;
+        if (st.have < st.k && st.k - st.have < bs) bs = st.k - st.have;
+        bool pass = false;
+        int64_t row = 0;
+        int pos = 0;
+        if (lane < bs) {
+            const unsigned long long key = keys[at + lane];
+            row = (int64_t)(uint32_t)(key & 0xFFFFFFFFull);
+            pos = vals[at + lane];
+            pass = ord_to_float((uint32_t)(key >> 32)) < st.tau;
+        }
+        *n1 += __popcll(__ballot(pass));
+        if (pass && c.B > 1 && c.use_ext) {
+            const PairRec R = c.recs[pos];
+            const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
+            const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
+                                    c.fEB[row], c.fSX[row], R, U, c.bq);
+            pass = lb < st.tau;
+        }
+        *next += __popcll(__ballot(pass));
+        if (pass && c.stage2) {
+            const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < st.tau;
+        }
+        unsigned long long m2 = __ballot(pass);
+        *n2 += __popcll(m2);
+        unsigned long long mine = kEmptyKey;
+        while (m2) {
+            const int src = take4(&m2, lane);
+            const int64_t rs = __shfl(row, src < 0 ? 0 : src);
+            const float dist = exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+            for (int g = 0; g < 4; g++) {
+                const int sg = __shfl(src, g * 16);
+                const unsigned long long kg = __shfl(key, g * 16);
+                if (sg >= 0 && lane == sg) mine = kg;
             }
         }
-        __syncthreads();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        // merge the new keys into the sorted queue
+        const unsigned long long sv = wave_sort64(mine, lane);
+        const int mnew = __popcll(__ballot(sv != kEmptyKey));
+        if (mnew > 0) {
+            nk[lane] = sv;
+            __syncthreads();
+            const unsigned long long* src = st.tk[st.cur];
+            unsigned long long* dst = st.tk[st.cur ^ 1];
+            for (int i = lane; i < st.have; i += 64) {  // existing key: rank among the new keys
+                const unsigned long long e = src[i];
+                int lo = 0, hi = mnew;
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (nk[mid] < e) lo = mid + 1; else hi = mid; }
+                if (i + lo < st.k) dst[i + lo] = e;
+            }
+            if (lane < mnew) {
+                int lo = 0, hi = st.have;
+                while (lo < hi) { int mid = (lo + hi) >> 1; if (src[mid] < sv) lo = mid + 1; else hi = mid; }
+                if (lane + lo < st.k) dst[lane + lo] = sv;
+            }
+            __syncthreads();
+            st.cur ^= 1;
+            st.have = st.have + mnew < st.k ? st.have + mnew : st.k;
+            if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.tk[st.cur][st.k - 1] >> 32));
+        }
+        at += bs;
+    }
+}
+
+template <int WP, int BQT>
+__global__ __launch_bounds__(64) void k_query_pass(ScanCtx c, int mode, int r_lo, int r_hi) {
+    __shared__ unsigned long long keys[kChunk];
+    __shared__ int32_t vals[kChunk];
+    __shared__ unsigned long long nk[64];
+    extern __shared__ unsigned long long tk_dyn[];  // 2 x k_max keys
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int np = c.npq[q];
+    QueryState st;
+    st.tk[0] = tk_dyn;
+    st.tk[1] = tk_dyn + c.k_max;
+    st.cur = 0;
+    st.k = c.kq[q];
+    unsigned long long* slots = c.slots + c.slot_off[q];
+    int have = 0;
+    for (int i = lane; i < st.k; i += 64) {
+        const unsigned long long v = slots[i];
+        st.tk[0][i] = v;
+        have += v != kEmptyKey;
+    }
+    st.have = wave_sum_i(have);
+    __syncthreads();
+    st.tau = st.have == st.k ? __uint_as_float((uint32_t)(st.tk[0][st.k - 1] >> 32)) : INFINITY;
+    const float er = c.er[q];
+    long long nscan = 0, n1 = 0, next = 0, n2 = 0;
+    {
+        const int rhi = r_hi < np ? r_hi : np;
+        for (int r = r_lo; r < rhi; r++) {
+            const int pos = c.pair_pos[c.pair_off[q] + r];
+            const PairRec R = c.recs[pos];
+            const uint32_t* U = c.planes + (int64_t)pos * (BQT > 0 ? BQT : c.bq) * WP;
+            const int j = R.list;
+            const int n = c.list_len[j];
+            const int64_t base = c.list_off[j];
+            for (int cs = 0; cs < n; cs += kChunk) {
+                const int m = n - cs < kChunk ? n - cs : kChunk;
+                int P = 64;
+                while (P < m) P <<= 1;
                 for (int i = lane; i < P; i += 64) {
-                    int ixj = i ^ stride;
-                    if (ixj > i) {
-                        bool asc = (i & size) == 0;
-                        unsigned long long a = keys[i], b = keys[ixj];
-                        if ((a > b) == asc) { keys[i] = b; keys[ixj] = a; }
+                    if (i < m) {
+                        const int64_t row = base + cs + i;
+                        uint32_t cw[WP];
+                        int pc = 0;
+#pragma unroll
+                        for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
+                        const float lb = stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
+                        keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)row;
+                        vals[i] = pos;
+                    } else {
+                        keys[i] = kEmptyKey;
+                        vals[i] = 0;
                     }
                 }
                 __syncthreads();
+                nscan += m;
+                sort_chunk(keys, vals, P, lane);
+                walk_chunk<WP>(c, q, er, keys, vals, m, st, nk, lane, &n1, &next, &n2);
+                __syncthreads();
             }
         }
-        nscan += m;
-        int at = 0;
-        while (at < m) {
-            int bs = m - at < 64 ? m - at : 64;
-            if (have < k && k - have < bs) bs = k - have;
-            bool pass = false;
-            int64_t row = 0;
-            if (lane < bs) {
-                const int idx = (int)(keys[at + lane] & 0xFFFFFFFFull);
-                row = base + cs + idx;
-                pass = lbs[idx] < tau;
-            }
-            n1 += __popcll(__ballot(pass));
-            if (pass && c.B > 1 && c.use_ext) {
-                const uint32_t* Ub = U;
-                float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row],
-                                  c.fFB[row], c.fEB[row], c.fSX[row], R, Ub, c.bq);
-                pass = lb < tau;
-            }
-            next += __popcll(__ballot(pass));
-            if (pass && c.stage2) {
-                float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-                float diso = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]);
-                pass = diso - er < tau;
-            }
-            unsigned long long m2 = __ballot(pass);
-            n2 += __popcll(m2);
-            unsigned long long mine = kEmptyKey;
-            while (m2) {
-                const int s = __ffsll((long long)m2) - 1;
-                m2 &= m2 - 1;
-                const int64_t rs = __shfl(row, s);
-                float dist = exact_dist_wave(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane);
-                if (lane == s) mine = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
-            }
-            // merge the new keys into the sorted queue tk[cur][0..have)
-            unsigned long long sv = wave_sort64(mine, lane);
-            const int mnew = __popcll(__ballot(sv != kEmptyKey));
-            if (mnew > 0) {
-                nk[lane] = sv;
-                __syncthreads();
-                unsigned long long* src = tk[cur];
-                unsigned long long* dst = tk[cur ^ 1];
-                for (int i = lane; i < have; i += 64) {  // existing element: rank among new keys
-                    unsigned long long e = src[i];
-                    int lo = 0, hi = mnew;
-                    while (lo < hi) { int mid = (lo + hi) >> 1; if (nk[mid] < e) lo = mid + 1; else hi = mid; }
-                    int dp = i + lo;
-                    if (dp < k) dst[dp] = e;
-                }
-                if (lane < mnew) {
-                    unsigned long long e = sv;
-                    int lo = 0, hi = have;
-                    while (lo < hi) { int mid = (lo + hi) >> 1; if (src[mid] < e) lo = mid + 1; else hi = mid; }
-                    int dp = lane + lo;
-                    if (dp < k) dst[dp] = e;
-                }
-                __syncthreads();
-                cur ^= 1;
-                have = have + mnew < k ? have + mnew : k;
-                if (have == k) tau = __uint_as_float((uint32_t)(tk[cur][k - 1] >> 32));
-            }
-            at += bs;
-        }
-        __syncthreads();
     }
-    unsigned long long* out = c.slots + c.slot_off[q];
-    for (int i = lane; i < k; i += 64) out[i] = i < have ? tk[cur][i] : kEmptyKey;
+    for (int i = lane; i < st.k; i += 64) slots[i] = i < st.have ? st.tk[st.cur][i] : kEmptyKey;
     if (c.counters && lane == 0) {
         atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)nscan);
         atomicAdd((unsigned long long*)&c.counters[5], (unsigned long long)n1);
@@ -978,14 +1170,25 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
-    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcount;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *scnt;
     PairRec* recs;
     uint32_t* planes;
     unsigned long long* slots;
+    int2 *surv1, *surv2;
 };
 
+// Survivor buffer capacity of a phase (entries): half of the candidates the search can scan, within
+// [2^16, 2^27]; survivors beyond it are finished inside the scan kernel with the same decisions.
+int64_t surv_capacity(const Index& ix, int64_t total_pairs) {
+    const int64_t avg = (ix.N + ix.nlist - 1) / ix.nlist;
+    int64_t want = total_pairs * avg / 2;
+    if (want < ((int64_t)1 << 16)) want = (int64_t)1 << 16;
+    if (want > ((int64_t)1 << 27)) want = (int64_t)1 << 27;
+    return want;
+}
+
 WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
-             size_t* used) {
+             int np_max, size_t* used) {
     Carve c{reinterpret_cast<char*>(base)};
     WsPtrs w;
     const int64_t P = (int64_t)kPhases * ix.nlist;
@@ -1006,10 +1209,13 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.fill = c.take<int32_t>(P);
     w.items = c.take<int32_t>(P);
     w.ioff = c.take<int32_t>(P + 1);
-    w.wcount = c.take<int32_t>(kPhases);
     w.recs = c.take<PairRec>(total_pairs);
     w.planes = c.take<uint32_t>(total_pairs * bq * ix.WP);
     w.slots = c.take<unsigned long long>(total_slots);
+    w.scnt = c.take<int32_t>(2 * kPhases);
+    const int64_t cap = surv_capacity(ix, total_pairs);
+    w.surv1 = c.take<int2>(cap);
+    w.surv2 = c.take<int2>(cap);
     *used = c.used;
     return w;
 }
@@ -1028,44 +1234,42 @@ struct Timed {
 };
 }  // namespace
 
-size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq) {
+size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
+                              int np_max) {
     size_t used = 0;
-    carve(nullptr, ix, nq, total_slots, total_pairs, bq, &used);
+    carve(nullptr, ix, nq, total_slots, total_pairs, bq, np_max, &used);
     return used;
 }
 
 template <int WP, int BQT>
-static void launch_scan_phase(const ScanCtx& c, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_scan<WP, BQT>), dim3(grid), dim3(256), 0, s, c);
-}
-template <int WP, int BQT>
-static void launch_seed(const ScanCtx& c, int64_t nq, const int64_t* pair_off, const int32_t* pair_pos,
-                        const int32_t* list_len, hipStream_t s) {
-    hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64), 0, s, c, pair_off, pair_pos, list_len);
-}
-
-template <int WP>
-static void dispatch_bq(const ScanCtx& c, bool seed, int grid, int64_t nq, const int64_t* pair_off,
-                        const int32_t* pair_pos, const int32_t* list_len, hipStream_t s) {
-    if (c.bq == 4) {
-        if (seed) launch_seed<WP, 4>(c, nq, pair_off, pair_pos, list_len, s);
-        else launch_scan_phase<WP, 4>(c, grid, s);
+static void launch_phase_kernels(const ScanCtx& c, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
+    if (which == 0) {
+        if (c.G <= 16) hipLaunchKernelGGL((k_scan<WP, BQT, 16>), dim3(2048), dim3(256), 0, s, c);
+        else hipLaunchKernelGGL((k_scan<WP, BQT, 32>), dim3(2048), dim3(256), 0, s, c);
+    } else if (which == 2) {
+        hipLaunchKernelGGL((k_stage2<WP>), dim3(2048), dim3(256), 0, s, c);
     } else {
-        if (seed) launch_seed<WP, 0>(c, nq, pair_off, pair_pos, list_len, s);
-        else launch_scan_phase<WP, 0>(c, grid, s);
+        hipLaunchKernelGGL((k_query_pass<WP, BQT>), dim3((unsigned)nq), dim3(64),
+                           sizeof(unsigned long long) * 2 * c.k_max, s, c, mode, r_lo, r_hi);
     }
 }
 
-static void dispatch(const ScanCtx& c, int WP, bool seed, int grid, int64_t nq, const int64_t* pair_off,
-                     const int32_t* pair_pos, const int32_t* list_len, hipStream_t s) {
+template <int WP>
+static void dispatch_bq(const ScanCtx& c, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
+    if (c.bq == 4) launch_phase_kernels<WP, 4>(c, which, mode, r_lo, r_hi, nq, s);
+    else launch_phase_kernels<WP, 0>(c, which, mode, r_lo, r_hi, nq, s);
+}
+
+// which = 0: batched stage-1 scan; which = 1: query pass in `mode` over probe ranks [r_lo, r_hi)
+static void dispatch(const ScanCtx& c, int WP, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
     switch (WP) {
-        case 1: dispatch_bq<1>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        case 2: dispatch_bq<2>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        case 4: dispatch_bq<4>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        case 8: dispatch_bq<8>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        case 16: dispatch_bq<16>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        case 32: dispatch_bq<32>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
-        default: dispatch_bq<48>(c, seed, grid, nq, pair_off, pair_pos, list_len, s); break;
+        case 1: dispatch_bq<1>(c, which, mode, r_lo, r_hi, nq, s); break;
+        case 2: dispatch_bq<2>(c, which, mode, r_lo, r_hi, nq, s); break;
+        case 4: dispatch_bq<4>(c, which, mode, r_lo, r_hi, nq, s); break;
+        case 8: dispatch_bq<8>(c, which, mode, r_lo, r_hi, nq, s); break;
+        case 16: dispatch_bq<16>(c, which, mode, r_lo, r_hi, nq, s); break;
+        case 32: dispatch_bq<32>(c, which, mode, r_lo, r_hi, nq, s); break;
+        default: dispatch_bq<48>(c, which, mode, r_lo, r_hi, nq, s); break;
     }
 }
 
@@ -1086,9 +1290,9 @@ int padded_words(int d) {
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
     const Index& ix = *a.ix;
     size_t used = 0;
-    WsPtrs w = carve(ws, ix, a.nq, a.total_slots, a.total_pairs, a.bq, &used);
+    WsPtrs w = carve(ws, ix, a.nq, a.total_slots, a.total_pairs, a.bq, a.np_max, &used);
     if (used > ws_bytes) return hipErrorOutOfMemory;
-    KernelTimer* tm = &ix.timer;
+    KernelTimer* tm = a.timed ? &ix.timer : nullptr;
     const int64_t nq = a.nq;
     const int d = ix.d, d4 = ix.d4, D = ix.D, D4 = ix.D4, nlist = ix.nlist;
     const int64_t P = (int64_t)kPhases * nlist;
@@ -1114,43 +1318,68 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
-        HIP_TRY(launch_fill_i32(w.wcount, 0, kPhases, s));
+        HIP_TRY(launch_fill_i32(w.scnt, 0, 2 * kPhases, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, P);
-        hipLaunchKernelGGL(k_pair_prep, dim3((unsigned)((a.total_pairs + 3) / 4)), dim3(256), 0, s,
-                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.rq, ix.RC, d, d4,
-                           ix.WP, a.bq, a.eps0, w.Tq, w.er, w.boff, w.fill, w.recs, w.planes, w.pair_pos);
+        const int nh = (d + 63) / 64;
+        const dim3 gp((unsigned)((a.total_pairs + 3) / 4));
+#define PREP(NHV)                                                                                          \
+    hipLaunchKernelGGL(k_pair_prep<NHV>, gp, dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, \
+                       nlist, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.boff, w.fill, w.recs,      \
+                       w.planes, w.pair_pos)
+        if (nh <= 1) PREP(1);
+        else if (nh <= 2) PREP(2);
+        else if (nh <= 4) PREP(4);
+        else if (nh <= 8) PREP(8);
+        else if (nh <= 16) PREP(16);
+        else PREP(24);
+#undef PREP
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
-                           nlist, a.group, (int)P, w.items);
+                           nlist, a.group <= 16 ? 16 : 32, (int)P, w.items);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, P);
         HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
         HIP_TRY(hipGetLastError());
     }
     ScanCtx c;
     c.recs = w.recs; c.planes = w.planes; c.boff = w.boff; c.ioff = w.ioff;
-    c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.code = ix.code; c.ext = ix.ext;
+    c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.list_len = ix.list_len; c.code = ix.code; c.ext = ix.ext;
     c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
-    c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2;
-    c.kq = a.kq; c.slot_off = a.slot_off; c.slots = w.slots; c.wcount = w.wcount;
-    c.counters = a.counters; c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq;
-    c.G = a.group; c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0;
+    c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
+    c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
+    c.slots = w.slots; c.surv1 = w.surv1; c.surv2 = w.surv2; c.cnt = w.scnt; c.counters = a.counters;
+    c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = a.group <= 16 ? 16 : 32;
+    c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
+    c.cap = (int)surv_capacity(ix, a.total_pairs);
     {
         Timed t(tm, s, "seed");
-        dispatch(c, ix.WP, true, 0, nq, a.pair_off, w.pair_pos, ix.list_len, s);
+        dispatch(c, ix.WP, 1, PASS_SEED, 0, 1, nq, s);
         HIP_TRY(hipGetLastError());
     }
     for (int p = 1; p < kPhases; p++) {
         if (a.np_max <= phase_lo(p)) break;
         c.phase = p;
+        c.cnt = w.scnt + 2 * p;
         {
             Timed t(tm, s, "tau");
             hipLaunchKernelGGL(k_tau_snap, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                                w.slots, a.slot_off, a.kq, w.boff, nlist, p, a.total_pairs, w.recs);
         }
-        Timed t(tm, s, "scan");
-        dispatch(c, ix.WP, false, 2048, nq, a.pair_off, w.pair_pos, ix.list_len, s);
-        HIP_TRY(hipGetLastError());
+        {
+            Timed t(tm, s, "scan");
+            dispatch(c, ix.WP, 0, 0, 0, 0, nq, s);
+            HIP_TRY(hipGetLastError());
+        }
+        {
+            Timed t(tm, s, "stage2");
+            dispatch(c, ix.WP, 2, 0, 0, 0, nq, s);
+            HIP_TRY(hipGetLastError());
+        }
+        {
+            Timed t(tm, s, "exact");
+            hipLaunchKernelGGL(k_exact, dim3(2048), dim3(256), 0, s, c);
+            HIP_TRY(hipGetLastError());
+        }
     }
     {
         Timed t(tm, s, "finalize");

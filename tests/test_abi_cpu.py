@@ -1,0 +1,87 @@
+"""The C ABI library loads without a GPU, exports every entry point include/mrq.h declares, and
+rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+import tempfile
+
+import numpy as np
+import pytest
+
+import paper_2411_06158_amd as mrq
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mrq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrq_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("mrq_build", "mrq_search", "mrq_search_mixed", "mrq_export", "mrq_save", "mrq_load", "mrq_free",
+                 "mrq_last_error", "mrq_server_create", "mrq_server_submit", "mrq_server_poll"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mrq.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(mrq.EXPORTED) == declared_functions()
+
+
+def test_option_defaults():
+    b = mrq.BuildOpts()
+    mrq.lib().mrq_build_opts_default(C.byref(b))
+    assert b.seed == 4001 and b.kmeans_iters == 25
+    s = mrq.SearchOpts()
+    mrq.lib().mrq_search_opts_default(C.byref(s))
+    assert (s.mode, s.bq, s.stage2, s.use_ext, s.group) == (0, 4, 1, 1, 0)
+    assert abs(s.eps0 - 1.9) < 1e-6 and s.m == 3.0
+
+
+def _build(X, N, D, d, B, nlist):
+    h = C.c_void_p()
+    st = mrq.lib().mrq_build(None if X is None else X.ctypes.data, N, D, d, B, nlist, None, None, C.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("N,D,d,B,nlist,msg", [
+    (0, 8, 4, 1, 1, "N"), (100, 1, 1, 1, 1, "D"), (100, 8, 9, 1, 4, "d_r"), (100, 8, 1, 1, 4, "d_r"),
+    (100, 8, 4, 0, 4, "bits"), (100, 8, 4, 9, 4, "bits"), (100, 8, 4, 1, 0, "nlist"), (100, 8, 4, 1, 101, "nlist"),
+])
+def test_build_rejects_bad_arguments(N, D, d, B, nlist, msg):
+    X = np.zeros((max(N, 1), D), np.float32)
+    st, h = _build(X, N, D, d, B, nlist)
+    assert st == mrq.MRQ_EINVAL and not h.value
+    assert msg in mrq.lib().mrq_last_error().decode()
+
+
+def test_null_pointers_rejected():
+    st, _ = _build(None, 10, 4, 2, 1, 1)
+    assert st == mrq.MRQ_EINVAL
+    ids = np.zeros(10, np.int64)
+    dd = np.zeros(10, np.float32)
+    q = np.zeros(4, np.float32)
+    assert mrq.lib().mrq_search(None, q.ctypes.data, 1, 10, 1, ids.ctypes.data, dd.ctypes.data, None, None) == mrq.MRQ_EINVAL
+    assert mrq.lib().mrq_export(None, b"/tmp/x") == mrq.MRQ_EINVAL
+    srv = C.c_void_p()
+    assert mrq.lib().mrq_server_create(None, 0, 8, None, C.byref(srv)) == mrq.MRQ_EINVAL
+    assert mrq.lib().mrq_server_poll(None, None, None, None, None, 1, 1, None) == -1
+    mrq.lib().mrq_free(None)  # ignored
+
+
+def test_load_rejects_missing_and_corrupt_files():
+    h = C.c_void_p()
+    assert mrq.lib().mrq_load(b"/nonexistent/index.mrqs", C.byref(h)) == mrq.MRQ_EIO
+    with tempfile.NamedTemporaryFile(suffix=".mrqs", delete=False) as f:
+        f.write(b"NOTANIDX" + b"\0" * 64)
+        path = f.name
+    try:
+        assert mrq.lib().mrq_load(path.encode(), C.byref(h)) == mrq.MRQ_EIO
+        assert "MRQS0001" in mrq.lib().mrq_last_error().decode()
+    finally:
+        os.unlink(path)
