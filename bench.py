@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+SEARCH_SOURCES = ["paper_2411_06158_amd/csrc/mrq_search.hip", "paper_2411_06158_amd/csrc/mrq_internal.h"]
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock: 39.3 T lane-ops/s
 
 
@@ -42,6 +43,28 @@ def ground_truth(torch, Xd, Qd, k, extra=32, chunk=1024):
         out.append(torch.gather(cand, 1, order)[:, :k])
         del d, dd
     return torch.cat(out).cpu().numpy()
+
+
+def counter_traffic(tag, kernel):
+    """HBM bytes per launch of `kernel` on workload `tag` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summaries under profiles/, or None when there is none or the search sources have changed
+    since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in SEARCH_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    src = h.hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{tag}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-record:"):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if kv.get("workload") == tag and kv.get("kernel") == kernel and kv.get("source") == src:
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def recall(ids, gt, k):
@@ -195,7 +218,13 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(fh, 4)}
-        roof.update({"kernel": dom, "traffic": None, "launch_ms": round(r["launch_ms"], 4),
+        tag = f"{args.workload}_d{args.d}_b{args.bits}_np{chosen}_k{k}"
+        kname = {"scan": "k_scan", "stage2": "k_stage2", "exact": "k_exact"}[dom]
+        traffic = counter_traffic(tag, kname)
+        roof.update({"kernel": kname, "traffic": None if traffic is None else round(traffic),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "algorithmic_bytes_per_launch": round(r["bytes_per_launch"]),
+                     "launch_ms": round(r["launch_ms"], 4),
                      "per_kernel": {n: {"ms_per_step": round(v["ms_per_step"], 4), "GB/s": round(v["gbs"], 1),
                                         "TOP/s": round(v["tops"], 3)} for n, v in rows.items()}})
     else:
