@@ -75,8 +75,10 @@ typedef struct {
                                [0..3] batched scan: candidates scanned, stage-1 survivors, B-bit
                                survivors, exact distances; [4..7] the same for the seed pass over
                                each query's nearest list */
-    int32_t group;          /* queries per scan work item (0 = autotuned) */
-    int32_t reserved[5];
+    int32_t group;          /* queries per scan work item: 16, 32 or 64 (0 = the index default) */
+    int32_t exact_cap;      /* exact-stage buffer entries per phase (0 = automatic); candidates beyond
+                               it are finished inside the scan; results do not depend on it */
+    int32_t reserved[4];
 } mrq_search_opts;
 
 /* Defaults for the option structs (pass NULL to any call to use them). */

@@ -39,7 +39,8 @@ class BuildOpts(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("bq", C.c_int32), ("eps0", C.c_float), ("m", C.c_float),
                 ("stage2", C.c_int32), ("use_ext", C.c_int32), ("counters", C.c_void_p),
-                ("group", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("group", C.c_int32), ("exact_cap", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 _lib = None
@@ -115,11 +116,12 @@ def _stream(stream) -> Optional[int]:
 
 
 def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=True, counters=None,
-                group=0) -> SearchOpts:
+                group=0, exact_cap=0) -> SearchOpts:
     o = SearchOpts()
     lib().mrq_search_opts_default(C.byref(o))
     o.mode, o.bq, o.eps0, o.m = int(mode), int(bq), float(eps0), float(m)
     o.stage2, o.use_ext, o.group = int(bool(stage2)), int(bool(use_ext)), int(group)
+    o.exact_cap = int(exact_cap)
     o.counters = _ptr(counters) if counters is not None else None
     return o
 

@@ -177,6 +177,8 @@ void check_args_build(const float* X, int64_t N, int32_t D, int32_t d, int32_t B
     if (d > 1536) throw Fail(MRQ_EINVAL, "d_r above 1536 is not supported");
     if (B < 1 || B > 8) throw Fail(MRQ_EINVAL, "bits must be in [1, 8]");
     if (nlist < 1 || nlist > N) throw Fail(MRQ_EINVAL, "nlist must be in [1, N]");
+    if (N + 64 * (int64_t)nlist >= (int64_t)0x7fffffff)
+        throw Fail(MRQ_EINVAL, "N + 64 nlist must be below 2^31 - 1 (rows are addressed with int32)");
 }
 
 }  // namespace
@@ -486,6 +488,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     resolve_opts(opts_in, &o);
     if (o.bq < 1 || o.bq > 8) throw Fail(MRQ_EINVAL, "bq must be in [1, 8]");
     if (o.mode != MRQ_BATCHED && o.mode != MRQ_PER_QUERY) throw Fail(MRQ_EINVAL, "unknown mode");
+    if (o.group < 0 || o.group > 64) throw Fail(MRQ_EINVAL, "group must be in [0, 64]");
+    if (o.exact_cap < 0) throw Fail(MRQ_EINVAL, "exact_cap must be >= 0");
     const int np_cap = std::min(ix->nlist, kMaxProbe);
 
     // per-query k / nprobe on the host (mixed batches)
@@ -600,6 +604,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.stage2 = o.stage2;
     a.use_ext = o.use_ext;
     a.group = o.group > 0 ? o.group : ix->group_default;
+    a.exact_cap = o.exact_cap;
     a.counters = cnt_d;
     if (!per_query) {
         if (uniform_kq) hip_check(launch_uniform_meta(nq, k_u, np_u, kq, npq, so, po, oo, s), "meta");

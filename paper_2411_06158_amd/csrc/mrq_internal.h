@@ -19,11 +19,9 @@ constexpr int kMaxK = 1024;
 constexpr int kMaxProbe = 1024;
 constexpr uint64_t kEmptyKey = ~0ull;
 
-// Per (query, list) pair: everything the stage-1 test needs besides the bit planes, read by the
-// scan through the scalar unit (12 dwords).
+// Per (query, list) pair: everything the stage-1, B-bit and Eq 7 tests need besides the query codes
+// (12 dwords; the first eight are the test scalars).
 struct PairRec {
-    int32_t q;       // query index in the batch
-    int32_t list;    // IVF list id
     float Kr;        // ||q_d - c||^2 + ||q_r||^2 - eps_r  (query part of C1 minus the residual radius)
     float two_nq;    // 2 ||q_d - c||
     float vl;        // quantised query: lowest level
@@ -32,7 +30,10 @@ struct PairRec {
     float ebc;       // 2 ||q_d - c|| eps0 / sqrt(d - 1)
     float tau;       // pruning threshold of the query for the current phase
     float er;        // eps_r = 2 m sigma of the query (Eq 6)
-    float pad0, pad1;
+    int32_t q;       // query index in the batch
+    int32_t list;    // IVF list id
+    float qn2;       // ||q - mu||^2 = ||q_p||^2 (Eq 7)
+    float pad;
 };
 static_assert(sizeof(PairRec) == 48, "PairRec layout");
 
@@ -129,6 +130,7 @@ struct SearchArgs {
     int32_t bq;
     float eps0, m;
     int32_t stage2, use_ext, group;
+    int64_t exact_cap = 0;  // exact-stage buffer entries per phase (0 = automatic)
     int64_t* ids;          // device output
     float* dists;          // device output
     int64_t* counters;     // device int64[8] or null

@@ -12,6 +12,7 @@
 // depends on the timing of other work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -96,41 +97,29 @@ __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, c
     return s;
 }
 
-// <x_d, q_d> of Eq 7 evaluated by one lane in ascending dimension order (rows zero padded to d4);
-// every stage-2 value of the search is computed this way.  dot_lane keeps four float4 of each row in
-// flight per round; dot_lane_small is the low-register form with the same operation order.
+// <x_d, q_d> of Eq 7 (rows zero padded to d4) as one chain of fused multiply-adds, in the order in which
+// the scan's FP32 matrix-core tiles accumulate it: for each 16-dimension slice t, element e of each lane
+// group's float4, then lane group g = 0..3, i.e. dimension 16t + 4g + e.  A v_mfma_f32_16x16x4_f32 chain
+// rounds every element of its tile in exactly this sequence, so the seed pass (which calls this) and the
+// scan give every (query, vector) pair the same stage-2 value.
 __device__ __forceinline__ float dot_lane(const float* __restrict__ a, const float* __restrict__ b, int d4) {
-    const int nc = d4 >> 2;
-    const float4* __restrict__ xa = reinterpret_cast<const float4*>(a);
-    const float4* __restrict__ ya = reinterpret_cast<const float4*>(b);
     float s = 0.f;
-    for (int base = 0; base < nc; base += 4) {
+    for (int t = 0; t < d4; t += 16) {
         float4 x[4], y[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            x[u] = base + u < nc ? xa[base + u] : make_float4(0.f, 0.f, 0.f, 0.f);
-            y[u] = base + u < nc ? ya[base + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int g = 0; g < 4; g++) {
+            const bool in = t + 4 * g < d4;
+            x[g] = in ? *reinterpret_cast<const float4*>(a + t + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
+            y[g] = in ? *reinterpret_cast<const float4*>(b + t + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            if (base + u >= nc) break;
-            s = fmaf(x[u].x, y[u].x, s);
-            s = fmaf(x[u].y, y[u].y, s);
-            s = fmaf(x[u].z, y[u].z, s);
-            s = fmaf(x[u].w, y[u].w, s);
-        }
-    }
-    return s;
-}
-__device__ __forceinline__ float dot_lane_small(const float* __restrict__ a, const float* __restrict__ b, int d4) {
-    float s = 0.f;
-    for (int i = 0; i < d4; i += 4) {
-        const float4 x = *reinterpret_cast<const float4*>(a + i);
-        const float4 y = *reinterpret_cast<const float4*>(b + i);
-        s = fmaf(x.x, y.x, s);
-        s = fmaf(x.y, y.y, s);
-        s = fmaf(x.z, y.z, s);
-        s = fmaf(x.w, y.w, s);
+        for (int g = 0; g < 4; g++) if (t + 4 * g < d4) s = fmaf(x[g].x, y[g].x, s);
+#pragma unroll
+        for (int g = 0; g < 4; g++) if (t + 4 * g < d4) s = fmaf(x[g].y, y[g].y, s);
+#pragma unroll
+        for (int g = 0; g < 4; g++) if (t + 4 * g < d4) s = fmaf(x[g].z, y[g].z, s);
+#pragma unroll
+        for (int g = 0; g < 4; g++) if (t + 4 * g < d4) s = fmaf(x[g].w, y[g].w, s);
     }
     return s;
 }
@@ -529,9 +518,10 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
     const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
     const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
-    const float* __restrict__ Tq, const float* __restrict__ er, const int32_t* __restrict__ boff,
-    int32_t* __restrict__ fill,
-    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int32_t* __restrict__ pair_pos) {
+    const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
+    const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
+    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int8_t* __restrict__ qu8,
+    int32_t* __restrict__ pair_pos) {
     const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
     if (pi >= npairs) return;
     const int lane = threadIdx.x & 63;
@@ -590,6 +580,15 @@ __global__ __launch_bounds__(256) void k_pair_prep(
         for (int h = 0; h < nh; h++) uv[h] = 0;
     }
     su = wave_sum_i(su);
+    {   // levels as signed bytes for the i8 matrix-core scan (u - 128 when bq = 8), zero beyond d
+        int8_t* qbyte = qu8 + (int64_t)pos * KP;
+        const int ob = bq == 8 ? 128 : 0;
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int i = lane + 64 * h;
+            if (i < KP) qbyte[i] = (int8_t)(i < d ? uv[h] - ob : 0);
+        }
+    }
     uint32_t* pl = planes + (int64_t)pos * bq * WP;
     for (int b = 0; b < bq; b++) {
 #pragma unroll
@@ -614,8 +613,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(
         R.ebc = 2.f * nq * eps0 / sqrtf((float)(d - 1));
         R.tau = INFINITY;
         R.er = er[q];
-        R.pad0 = 0.f;
-        R.pad1 = 0.f;
+        R.qn2 = qn2[q];
+        R.pad = 0.f;
         if (!(hi > lo)) { R.vl = nq > 0.f ? lo : 0.f; }
         recs[pos] = R;
     }
@@ -630,12 +629,46 @@ __global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restri
     items[t] = c == 0 ? 0 : list_nb[j] * ((c + G - 1) / G);
 }
 
-// ------------------------------------------------------------------------------------------------
-// Stage 1 (Eq 4 with the Eq 5 and Eq 6 bounds) for the candidate held by this lane against one pair:
-//   ip = sum_b 2^b popcount(code & U_b),   I = Delta (2 ip - S_u) + v_l (2 popcount(code) - d)
-//      = sqrt(d) <xbar_b, qbar_b>,
-//   dis' = (A_x + K) - 2 n_q F_x I,   LB = dis' - ebc E_x - eps_r  (evaluated as (A_x + Kr) - ...).
+// Work-item descriptors of every phase: item ioff[t] + local of (phase, list) t = p nlist + j is block
+// local % nb of list j against the pair chunk local / nb (up to G pairs):
+//   {first row of the block, first pair record, number of pairs, list}.
+// One wave per (phase, list); items are written in ascending order, neighbouring blocks of a list next
+// to each other.
+__global__ __launch_bounds__(256) void k_item_desc(const int32_t* __restrict__ ioff, const int32_t* __restrict__ boff,
+                                                   const int32_t* __restrict__ list_nb,
+                                                   const int64_t* __restrict__ list_off, int nlist, int G,
+                                                   int64_t n, int4* __restrict__ desc) {
+    const int64_t t = blockIdx.x * 4ll + (threadIdx.x >> 6);
+    if (t >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int i0 = ioff[t], ni = ioff[t + 1] - i0;
+    if (ni == 0) return;
+    const int j = (int)(t % nlist);
+    const int nb = list_nb[j];
+    const int b0 = boff[t], b1 = boff[t + 1];
+    const int64_t r0 = list_off[j];
+    for (int local = lane; local < ni; local += 64) {
+        const int blk = local % nb, ch = local / nb;
+        const int pbeg = b0 + ch * G;
+        desc[i0 + local] = make_int4((int)(r0 + 64ll * blk), pbeg, min(G, b1 - pbeg), j);
+    }
+}
 
+// ------------------------------------------------------------------------------------------------
+// Stage 1 (Eq 4 with the Eq 5 and Eq 6 bounds) of one candidate against one pair, from the integer
+// inner product of the candidate's sign code b with the query levels u:
+//   ip = sum_i b_i u_i,   I = Delta (2 ip - S_u) + v_l (2 popcount(b) - d) = sqrt(d) <xbar_b, qbar_b>,
+//   dis' = (A_x + K) - 2 n_q F_x I,   LB = dis' - ebc E_x - eps_r  (evaluated as (A_x + Kr) - ...).
+__device__ __forceinline__ float stage1_from_ip(int ip, int pc, float A, float F, float E, const PairRec& R,
+                                                int d) {
+    const float J1 = (float)(2 * ip - (int)R.su);
+    const float J2 = (float)(2 * pc - d);
+    const float I = fmaf(R.delta, J1, R.vl * J2);
+    return fmaf(-R.ebc, E, fmaf(-(R.two_nq * F), I, A + R.Kr));
+}
+
+// The same with ip from the bit planes U_b of the query levels: ip = sum_b 2^b popcount(b & U_b)
+// (the seed pass, one candidate per lane).
 template <int WP, int BQT>
 __device__ __forceinline__ float stage1_lb(const uint32_t (&c)[WP], int pc, float A, float F, float E,
                                            const PairRec& R, const uint32_t* __restrict__ U, int bq, int d) {
@@ -649,16 +682,21 @@ __device__ __forceinline__ float stage1_lb(const uint32_t (&c)[WP], int pc, floa
         for (int w = 0; w < WP; w++) acc += __builtin_popcount(c[w] & U[b * WP + w]);
         ip += acc << b;
     }
-    const float J1 = (float)(2 * ip - (int)R.su);
-    const float J2 = (float)(2 * pc - d);
-    const float I = fmaf(R.delta, J1, R.vl * J2);
-    return fmaf(-R.ebc, E, fmaf(-(R.two_nq * F), I, A + R.Kr));
+    return stage1_from_ip(ip, pc, A, F, E, R, d);
 }
 
-// B-bit refinement of a stage-1 survivor (extended code, top plane = sign plane):
-//   ipB = sum_{a, b} 2^(a + b) popcount(X_a & U_b),
+// B-bit refinement of a stage-1 survivor (extended code whose top plane is the sign plane), from
+// ipB = sum_i ux_i u_i with ux the candidate's level indices:
 //   I_B = Delta (2 ipB - (2^B - 1) S_u) + v_l SX_x = 2 <y, qbar'>,
 //   dis_B = (A_x + K) - 2 n_q FB_x I_B,   LB_B = dis_B - ebc EB_x - eps_r.
+__device__ __forceinline__ float ext_from_ip(long long ip, int B, float A, float FB, float EB, float SX,
+                                             const PairRec& R) {
+    const float J1 = (float)(2 * ip - (long long)((1 << B) - 1) * (long long)R.su);
+    const float I = fmaf(R.delta, J1, R.vl * SX);
+    return fmaf(-R.ebc, EB, fmaf(-(R.two_nq * FB), I, A + R.Kr));
+}
+
+// The same with ipB = sum_{a, b} 2^(a + b) popcount(X_a & U_b) (the seed pass).
 __device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const uint32_t* __restrict__ extp,
                                         int B, int WP, float A, float FB, float EB, float SX, const PairRec& R,
                                         const uint32_t* __restrict__ U, int bq) {
@@ -671,16 +709,16 @@ __device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const
             ip += (long long)acc << (a + b);
         }
     }
-    const float J1 = (float)(2 * ip - (long long)((1 << B) - 1) * (long long)R.su);
-    const float I = fmaf(R.delta, J1, R.vl * SX);
-    return fmaf(-R.ebc, EB, fmaf(-(R.two_nq * FB), I, A + R.Kr));
+    return ext_from_ip(ip, B, A, FB, EB, SX, R);
 }
 
 struct ScanCtx {
     const PairRec* recs;
     const uint32_t* planes;
+    const int8_t* qu8;   // per pair: KP signed bytes u_i - ob (0 beyond d), i8 matrix-core operand
     const int32_t* boff;
     const int32_t* ioff;
+    const int4* desc;    // work-item descriptors of all phases (k_item_desc)
     const int64_t* list_off;
     const int32_t* list_nb;
     const int32_t* list_len;
@@ -701,11 +739,10 @@ struct ScanCtx {
     const int64_t* pair_off;
     const int32_t* pair_pos;
     unsigned long long* slots;
-    int2* surv1;         // stage-1 survivors of the current phase: (row, pair record position)
-    int2* surv2;         // stage-2 survivors of the current phase: (row, query)
-    int32_t* cnt;        // [0] stage-1 survivors appended, [1] stage-2 survivors appended
+    int2* surv;          // exact-stage candidates of the current phase: (row, query), rs per scan wave
+    int32_t* wcnt;       // candidates produced by each scan wave (the first rs are in its region)
     int64_t* counters;
-    int nlist, d, d4, D4, B, bq, G, stage2, use_ext, phase, k_max, cap;
+    int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, rs;
 };
 
 __device__ __forceinline__ float ord_to_float(uint32_t o) {
@@ -713,16 +750,51 @@ __device__ __forceinline__ float ord_to_float(uint32_t o) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Batched stage-1 scan of one phase (list-major, persistent).  A work item is (list j, 64-row block,
-// chunk of up to GT pair records of list j in this phase): the wave loads its block's codes and
-// factors once and tests them against every pair of the chunk, each pair's scalars and bit planes
-// arriving through scalar loads.  Survivors (LB < the phase threshold of their query) are appended to
-// the phase's survivor buffer with one atomic per item.  Every decision of a phase uses the fixed
-// phase threshold, so the set of candidates that reach each stage does not depend on the order in
-// which they are processed.
+// Batched scan of one phase (list-major, persistent), stages 1 to 2 on the matrix cores.
+//
+// A work item is (list j, 64-row block, chunk of up to GT pair records of list j in this phase).  The
+// wave treats it as a 64-row x GT-query tile, in 16 x 16 sub-tiles (rows = candidates, columns =
+// queries):
+//   stage 1   ip = <b_x, u_q> for all pairs of the sub-tile with v_mfma_i32_16x16x64_i8 (sign bits
+//             expanded to bytes in registers, query levels stored as bytes per pair), then the Eq 4-6
+//             test per entry;
+//   B bits    where any entry survived: ipB = <ux_x, u_q> the same way from the extended levels;
+//   stage 2   where any entry survived: <x_d, q_d> for the sub-tile with a v_mfma_f32_16x16x4_f32 chain
+//             and the Eq 7 test.
+// Integer products are exact; the FP32 chain rounds every element in the fixed order of dot_lane, so an
+// entry's values do not depend on its position in the tile, i.e. on the other queries of the batch.
+// Survivors go to the phase's exact-stage buffer with one atomic per item; entries beyond its capacity
+// get their exact distance inside this kernel, with the same arithmetic as k_exact.  Every decision of a
+// phase uses the phase threshold stored in the pair record, so the set of candidates reaching each
+// stage does not depend on the order in which items run.
 
-// Stages after stage 1 for the survivors of one wave, processed in place (used when the survivor
-// buffer is full): B-bit refinement and Eq 7 re-check per lane, exact distances four at a time.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 4 bits -> 4 bytes holding 0 or 1 (byte e <- bit e); the shifted copies never overlap, so no carries.
+__device__ __forceinline__ int nib_bytes(uint32_t n) { return (int)(((n & 0xFu) * 0x00204081u) & 0x01010101u); }
+
+// Bits of dimensions 64m + 16g .. 64m + 16g + 15 of a plane of WP words (bits beyond d are 0), as the
+// byte operand of lane group g in K-slice m: byte 4t + e of the operand is dimension 64m + 16g + 4t + e.
+__device__ __forceinline__ uint32_t plane_piece(const uint32_t* __restrict__ plane, int WP, int m, int g) {
+    const int w = 2 * m + (g >> 1);
+    const uint32_t word = plane[w < WP ? w : 0];  // unconditional load; words beyond WP read as 0
+    return w < WP ? (word >> ((g & 1) << 4)) & 0xFFFFu : 0u;
+}
+// Query operand of K-slice m (qb points at a valid pair; an invalid column is zeroed after the load).
+__device__ __forceinline__ i32x4 qop(const int8_t* __restrict__ qb, int m, bool qv) {
+    const i32x4 v = *reinterpret_cast<const i32x4*>(qb + 64 * m);
+    return qv ? v : i32x4{0, 0, 0, 0};
+}
+__device__ __forceinline__ i32x4 piece_bytes(uint32_t p) {
+    i32x4 r;
+    r.x = nib_bytes(p);
+    r.y = nib_bytes(p >> 4);
+    r.z = nib_bytes(p >> 8);
+    r.w = nib_bytes(p >> 12);
+    return r;
+}
+
 // Low-register form of exact_dist_group with the same operation order (hence the same results), for
 // the rarely taken in-place path of the scan kernel.
 __device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
@@ -741,176 +813,248 @@ __device__ __forceinline__ float exact_dist_group_small(const float* __restrict_
     return s;
 }
 
-template <int WP>
-__device__ void finish_inline(const ScanCtx& c, bool pass, int64_t row, int pos, int lane) {
-    int q = 0;
-    float tau = 0.f, er = 0.f;
-    if (pass) {
-        const PairRec R = c.recs[pos];
-        q = R.q;
-        tau = R.tau;
-        er = R.er;
-        if (c.B > 1 && c.use_ext) {
-            const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
-            pass = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
-                          c.fEB[row], c.fSX[row], R, U, c.bq) < tau;
-        }
-        if (pass && c.stage2) {
-            const float dot = dot_lane_small(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < tau;
-        }
-    }
-    unsigned long long m2 = __ballot(pass);
-    while (m2) {
-        const int src = take4(&m2, lane);
-        const int64_t rs = __shfl(row, src < 0 ? 0 : src);
-        const int qs = __shfl(q, src < 0 ? 0 : src);
-        const float dist = exact_dist_group_small(c.X + rs * c.D4, c.qpad + (int64_t)qs * c.D4, c.D4, lane & 15);
+// Exact distances of the sub-tile entries in mask m (bit l: row rbase + (l & 15), query of pair slot
+// cbase + 4 (l >> 4) + v) that did not fit the buffer, four at a time, into the result queues.
+__device__ void finish_inline(const ScanCtx& c, const PairRec* rec, unsigned long long m, int64_t rbase,
+                              int cbase, int v, int lane) {
+    const int first = __ffsll((long long)m) - 1;  // a valid entry, evaluated by groups without one
+    while (m) {
+        const int src = take4(&m, lane);
+        const int s0 = src < 0 ? first : src;
+        const int64_t row = rbase + (s0 & 15);
+        const int q = rec[cbase + 4 * (s0 >> 4) + v].q;
+        const float dist = exact_dist_group_small(c.X + row * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         if (src >= 0 && (lane & 15) == 0) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
-            topk_insert(c.slots + c.slot_off[qs], c.kq[qs], key);
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
+            topk_insert(c.slots + c.slot_off[q], c.kq[q], key);
         }
     }
 }
 
-template <int WP, int BQT, int GT>
+__device__ __forceinline__ int4 const_load4(const int4* p) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(p);
+    return make_int4((int)const_load(w), (int)const_load(w + 1), (int)const_load(w + 2), (int)const_load(w + 3));
+}
+
+// <q_d, x_d> for the 16 x 16 sub-tile (A operand: the query of pair slot li, B operand: row li), lane
+// group kg feeding dimensions 16t + 4kg .. 16t + 4kg + 3 of slice t.  Both row pointers are valid rows
+// (already offset by 4kg); slices beyond d4 and an invalid query column read offset 0 and are zeroed, so
+// every load is an unconditional dwordx4.  SU > 0: at most SU slices, two loaded ahead of their
+// multiply-adds; SU = 0: any d4.
+__device__ __forceinline__ void mfma4(f32x4& acc, const float4& q, const float4& x) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.x, x.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.y, x.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.z, x.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(q.w, x.w, acc, 0, 0, 0);
+}
+__device__ __forceinline__ float4 zero_unless(float4 v, bool keep) {
+    return make_float4(keep ? v.x : 0.f, keep ? v.y : 0.f, keep ? v.z : 0.f, keep ? v.w : 0.f);
+}
+template <int SU>
+__device__ __forceinline__ f32x4 dot_tile(const float* __restrict__ qp, const float* __restrict__ xp, bool qv,
+                                          int d4, int kg) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float4* __restrict__ q4 = reinterpret_cast<const float4*>(qp);
+    const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xp);
+    if (SU > 0) {
+        constexpr int CH = 2;
+#pragma unroll
+        for (int t0 = 0; t0 < (SU > 0 ? SU : 1); t0 += CH) {
+            float4 xa[CH], qa[CH];
+#pragma unroll
+            for (int u = 0; u < CH; u++) {
+                const bool in = 16 * (t0 + u) + 4 * kg < d4;
+                const int o = in ? 4 * (t0 + u) : 0;
+                xa[u] = zero_unless(x4[o], in);
+                qa[u] = zero_unless(q4[o], in && qv);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; u++) mfma4(acc, qa[u], xa[u]);
+        }
+    } else {
+        for (int t = 0; 16 * t < d4; t++) {
+            const bool in = 16 * t + 4 * kg < d4;
+            const int o = in ? 4 * t : 0;
+            mfma4(acc, zero_unless(q4[o], in && qv), zero_unless(x4[o], in));
+        }
+    }
+    return acc;
+}
+
+// Ordering of LDS accesses between the lanes of one wave (they execute in program order; this only
+// keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// KIT > 0: d <= 64 KIT (K-slice loops unrolled); KIT = 0: any d.
+template <int GT, int KIT>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
-    __shared__ unsigned long long sh_mask[4][GT];
+    constexpr int NCT = GT / 16;
+    __shared__ PairRec sh_rec[4][GT];
+    __shared__ unsigned long long sh_m[4][NCT * 16];  // surviving entries per (column tile, row tile, v)
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
+    const int li = lane & 15, kg = lane >> 4;
     const int p = c.phase;
-    const int* ioff = c.ioff + p * c.nlist;
-    const int base_item = (int)const_load((const uint32_t*)ioff);
-    const int total = (int)const_load((const uint32_t*)ioff + c.nlist) - base_item;
-    constexpr int NBQ = BQT > 0 ? BQT : 8;
-    const int bq = BQT > 0 ? BQT : c.bq;
-    const int64_t pstride = (int64_t)bq * WP;
-    long long nscan = 0, n1 = 0;
+    const int base_item = (int)const_load((const uint32_t*)(c.ioff + p * c.nlist));
+    const int total = (int)const_load((const uint32_t*)(c.ioff + (p + 1) * c.nlist)) - base_item;
+    const int KI = KIT > 0 ? KIT : c.KI;
+    const int ob = c.bq == 8 ? 128 : 0;  // query levels are stored as the signed bytes u - ob
+    const int oa = c.B == 8 ? 128 : 0;   // extended levels enter the product as the signed bytes ux - oa
+    const bool do_ext = c.B > 1 && c.use_ext;
+    const int WP = c.WP;
+    PairRec* rec = sh_rec[wv];
+    unsigned long long* msk = sh_m[wv];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    // this wave's region of the exact-stage buffer
+    const int wid = blockIdx.x * 4 + wv;
+    int2* region = c.surv + (int64_t)wid * c.rs;
+    int nreg = 0;  // candidates this wave produced (may exceed rs; the rest is finished in place)
+    long long nscan = 0, n1 = 0, next = 0;
     // items are dealt to the waves round-robin: neighbouring waves take neighbouring blocks of a list
     const int nwaves = gridDim.x * 4;
-    for (int it = blockIdx.x * 4 + wv; it < total; it += nwaves) {
-        const int git = base_item + it;
-        int lo = 0, hi = c.nlist - 1;  // last list j with ioff[j] <= git
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if ((int)const_load((const uint32_t*)ioff + mid) <= git) lo = mid; else hi = mid - 1;
+    for (int it = wid; it < total; it += nwaves) {
+        const int4 dsc = const_load4(c.desc + base_item + it);
+        const int64_t row0 = dsc.x;
+        const int pbeg = dsc.y, ng = dsc.z;
+        const int nct = (ng + 15) >> 4;
+        {
+            const PairRec rg = c.recs[pbeg + (lane < ng ? lane : 0)];
+            if (lane < ng) rec[lane] = rg;
         }
-        const int j = uniform(lo);
-        const int local = git - (int)const_load((const uint32_t*)ioff + j);
-        const int nb = c.list_nb[j];
-        const int blk = local % nb, ch = local / nb;
-        const int pbeg = c.boff[p * c.nlist + j] + ch * GT;
-        const int pend0 = c.boff[p * c.nlist + j + 1];
-        const int ng = uniform(pbeg + GT < pend0 ? GT : pend0 - pbeg);
-        const int64_t row = c.list_off[j] + (int64_t)blk * 64 + lane;
-        uint32_t cw[WP];
+        wave_lds_fence();
+        int tot = 0;
+        for (int ct = 0; ct < NCT; ct++) {
+            if (ct >= nct) break;
+            const int qs = ct * 16 + li;  // pair slot whose query this lane feeds to the A operand
+            const bool qv = qs < ng;
+            const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+            for (int rt = 0; rt < 4; rt++) {
+                const int64_t row = row0 + 16 * rt + li;
+                const uint32_t* cp = c.code + row * WP;
+                i32x4 acc = {0, 0, 0, 0};
+                int pcs = 0;
 #pragma unroll
-        for (int w = 0; w < WP; w++) cw[w] = c.code[row * WP + w];
-        int pc = 0;
-#pragma unroll
-        for (int w = 0; w < WP; w++) pc += __builtin_popcount(cw[w]);
-        const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
-        int nsurv = 0;
-#pragma unroll
-        for (int g = 0; g < GT; g++) {
-            if (g < ng) {
-                const int pos = pbeg + g;
-                const PairRec R = const_load(c.recs + pos);
-                uint32_t U[NBQ * WP];
-#pragma unroll
-                for (int t = 0; t < NBQ * WP; t++) U[t] = t < bq * WP ? const_load(c.planes + pos * pstride + t) : 0u;
-                const float lb = stage1_lb<WP, BQT>(cw, pc, A, F, E, R, U, bq, c.d);
-                const unsigned long long m = __ballot(lb < R.tau);
-                if (lane == 0) sh_mask[wv][g] = m;
-                nsurv += __popcll(m);
-            }
-        }
-        nscan += 64ll * ng;
-        n1 += nsurv;
-        if (nsurv == 0) continue;
-        __threadfence_block();
-        int base = 0;
-        if (lane == 0) base = atomicAdd(c.cnt, nsurv);
-        base = uniform(__shfl(base, 0));
-        int off = base;
-#pragma unroll
-        for (int g = 0; g < GT; g++) {
-            if (g < ng) {
-                const unsigned long long m = sh_mask[wv][g];
-                if (m) {
-                    const bool mine = (m >> lane) & 1ull;
-                    if (off + __popcll(m) <= c.cap) {
-                        if (mine) c.surv1[off + __popcll(m & ((1ull << lane) - 1ull))] = make_int2((int)row, pbeg + g);
-                    } else {
-                        finish_inline<WP>(c, mine, row, pbeg + g, lane);
+                for (int m = 0; m < (KIT > 0 ? KIT : 1); m++) {
+                    if (KIT == 0 && m >= KI) break;
+                    const uint32_t pb = plane_piece(cp, WP, m, kg);
+                    pcs += __builtin_popcount(pb);
+                    const i32x4 av = qop(qb, m, qv);
+                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, piece_bytes(pb), acc, 0, 0, 0);
+                }
+                if (KIT == 0) {
+                    for (int m = 1; m < KI; m++) {
+                        const uint32_t pb = plane_piece(cp, WP, m, kg);
+                        pcs += __builtin_popcount(pb);
+                        const i32x4 av = qop(qb, m, qv);
+                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, piece_bytes(pb), acc, 0, 0, 0);
                     }
-                    off += __popcll(m);
+                }
+                const int pc2 = pcs + __shfl_xor(pcs, 16);
+                const int pc = pc2 + __shfl_xor(pc2, 32);  // popcount of the whole sign code of `row`
+                const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
+                bool pass[4];
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int g = ct * 16 + 4 * kg + v;
+                    const PairRec& R = rec[g < ng ? g : 0];
+                    pass[v] = g < ng && stage1_from_ip(acc[v] + ob * pc, pc, A, F, E, R, c.d) < R.tau;
+                }
+                int cnt1 = 0;
+#pragma unroll
+                for (int v = 0; v < 4; v++) cnt1 += __popcll(__ballot(pass[v]));
+                n1 += cnt1;
+                if (cnt1 == 0) {
+                    if (lane < 4) msk[(ct * 4 + rt) * 4 + lane] = 0ull;
+                    continue;
+                }
+                if (do_ext) {
+                    i32x4 acc2 = {0, 0, 0, 0};
+                    const uint32_t* ew = c.ext + row * (int64_t)(c.B - 1) * WP;
+                    for (int m = 0; m < KI; m++) {
+                        i32x4 ub = piece_bytes(plane_piece(cp, WP, m, kg)) << (c.B - 1);
+                        for (int a = 0; a < c.B - 1; a++) ub |= piece_bytes(plane_piece(ew + a * WP, WP, m, kg)) << a;
+                        if (oa) ub ^= (int)0x80808080u;
+                        acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(qop(qb, m, qv), ub, acc2, 0, 0, 0);
+                    }
+                    const float FB = c.fFB[row], EB = c.fEB[row], SX = c.fSX[row];
+                    const long long sumux = ((long long)SX + (long long)((1 << c.B) - 1) * c.d) / 2;
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        if (pass[v]) {
+                            const PairRec& R = rec[ct * 16 + 4 * kg + v];
+                            // sum_i ux_i u_i from sum_i (ux_i - oa)(u_i - ob) over the d real dimensions
+                            const long long ipB = (long long)acc2[v] + ob * sumux + oa * (long long)R.su -
+                                                  (long long)oa * ob * c.d;
+                            pass[v] = ext_from_ip(ipB, c.B, A, FB, EB, SX, R) < R.tau;
+                        }
+                    }
+                }
+                int cntx = 0;
+#pragma unroll
+                for (int v = 0; v < 4; v++) cntx += __popcll(__ballot(pass[v]));
+                next += cntx;
+                if (cntx > 0 && c.stage2) {
+                    const int qrow = rec[qv ? qs : 0].q;
+                    const f32x4 dot = dot_tile<4 * KIT>(c.qd + (int64_t)qrow * c.d4 + 4 * kg,
+                                                        c.xd + row * c.d4 + 4 * kg, qv, c.d4, kg);
+                    const float axr = c.ax[row];
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        if (pass[v]) {
+                            const PairRec& R = rec[ct * 16 + 4 * kg + v];
+                            pass[v] = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const unsigned long long mv = __ballot(pass[v]);
+                    if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
+                    tot += __popcll(mv);
                 }
             }
         }
-        __threadfence_block();
-    }
-    if (c.counters && lane == 0) {  // nscan and n1 are wave-uniform
-        atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
-        atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
-    }
-}
-
-// Stage-1 survivors -> B-bit refinement and Eq 7 re-check, one survivor per lane, grid-stride over the
-// phase's survivor buffer.
-template <int WP>
-__global__ __launch_bounds__(256) void k_stage2(ScanCtx c) {
-    const int lane = lane_id();
-    const int n = min(c.cnt[0], c.cap);
-    long long next = 0, n2 = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < n; i0 += stride) {
-        const int64_t i = i0 + lane;
-        bool pass = i < n;
-        int64_t row = 0;
-        int q = 0;
-        float tau = 0.f, er = 0.f;
-        if (pass) {
-            const int2 e = c.surv1[i];
-            row = e.x;
-            const PairRec R = c.recs[e.y];
-            q = R.q;
-            tau = R.tau;
-            er = R.er;
-            if (c.B > 1 && c.use_ext) {
-                const uint32_t* U = c.planes + (int64_t)e.y * c.bq * WP;
-                pass = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
-                              c.fEB[row], c.fSX[row], R, U, c.bq) < tau;
+        nscan += 64ll * ng;
+        if (tot > 0) {
+            wave_lds_fence();
+            for (int ct = 0; ct < nct; ct++) {
+                for (int rt = 0; rt < 4; rt++) {
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const unsigned long long mv = msk[(ct * 4 + rt) * 4 + v];
+                        if (!mv) continue;
+                        const bool mine = (mv >> lane) & 1ull;
+                        const int pos = nreg + __popcll(mv & lt);
+                        const bool fits = mine && pos < c.rs;
+                        if (fits) region[pos] = make_int2((int)(row0 + 16 * rt + li), rec[ct * 16 + 4 * kg + v].q);
+                        const unsigned long long rest = __ballot(mine && !fits);
+                        if (rest) finish_inline(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane);
+                        nreg += __popcll(mv);
+                    }
+                }
             }
         }
-        next += __popcll(__ballot(pass));
-        if (pass && c.stage2) {
-            const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < tau;
-        }
-        const unsigned long long m = __ballot(pass);
-        if (m) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(c.cnt + 1, __popcll(m));
-            base = __shfl(base, 0);
-            if ((m >> lane) & 1ull) c.surv2[base + __popcll(m & ((1ull << lane) - 1ull))] = make_int2((int)row, q);
-            n2 += __popcll(m);
-        }
+        wave_lds_fence();
     }
-    if (c.counters && lane == 0) {  // next and n2 are wave-uniform
+    if (lane == 0) c.wcnt[wid] = nreg;
+    if (c.counters && lane == 0) {  // the counts are wave-uniform
+        atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
+        atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
         atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
-        atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)n2);
+        atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)nreg);
     }
 }
 
-// Stage-2 survivors -> exact distances (16 lanes each, four per wave) and the result queues.
+// Exact stage of a phase: block b takes the candidates in region b of the buffer (written by scan wave
+// b), 16 lanes per candidate, four per wave, into the result queues.
 __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     const int lane = lane_id();
-    const int n = c.cnt[1];
-    const int64_t groups = (int64_t)gridDim.x * 16;  // 16-lane groups in the grid
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4; i - (lane >> 4) < n; i += groups) {
+    const int b = blockIdx.x;
+    const int n = min(c.wcnt[b], c.rs);
+    const int2* region = c.surv + (int64_t)b * c.rs;
+    for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
         const bool valid = i < n;
-        const int2 e = c.surv2[valid ? i : 0];
+        const int2 e = region[valid ? i : 0];
         const float dist = exact_dist_group(c.X + (int64_t)e.x * c.D4, c.qpad + (int64_t)e.y * c.D4, c.D4, lane & 15);
         if (valid && (lane & 15) == 0) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[e.x];
@@ -1170,21 +1314,33 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
-    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *scnt;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt;
+    int4* desc;
     PairRec* recs;
     uint32_t* planes;
+    int8_t* qu8;
     unsigned long long* slots;
-    int2 *surv1, *surv2;
+    int2* surv;
 };
 
-// Survivor buffer capacity of a phase (entries): half of the candidates the search can scan, within
-// [2^16, 2^27]; survivors beyond it are finished inside the scan kernel with the same decisions.
+// Exact-stage buffer capacity of a phase (entries): 1/16 of the candidates the search can scan, within
+// [2^16, 2^27]; candidates beyond it get their exact distance inside the scan kernel (same arithmetic).
 int64_t surv_capacity(const Index& ix, int64_t total_pairs) {
     const int64_t avg = (ix.N + ix.nlist - 1) / ix.nlist;
-    int64_t want = total_pairs * avg / 2;
+    int64_t want = total_pairs * avg / 16;
     if (want < ((int64_t)1 << 16)) want = (int64_t)1 << 16;
     if (want > ((int64_t)1 << 27)) want = (int64_t)1 << 27;
     return want;
+}
+
+// Upper bound of the work items of all phases: sum over (phase, list) of blocks(list) * ceil(pairs / G)
+// <= max_blocks * pairs / 16 + phases * (sum of blocks), for any G >= 16.
+constexpr int kMaxScanBlocks = 2048;
+
+int64_t max_items(const Index& ix, int64_t total_pairs) {
+    const int64_t max_nb = (ix.max_list_len + 63) / 64;
+    const int64_t sum_nb = ix.Npad / 64;
+    return max_nb * ((total_pairs + 15) / 16) + std::min<int64_t>((int64_t)kPhases * sum_nb, total_pairs * max_nb) + 1;
 }
 
 WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
@@ -1209,13 +1365,14 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.fill = c.take<int32_t>(P);
     w.items = c.take<int32_t>(P);
     w.ioff = c.take<int32_t>(P + 1);
+    w.desc = c.take<int4>(max_items(ix, total_pairs));
     w.recs = c.take<PairRec>(total_pairs);
     w.planes = c.take<uint32_t>(total_pairs * bq * ix.WP);
+    w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
     w.slots = c.take<unsigned long long>(total_slots);
-    w.scnt = c.take<int32_t>(2 * kPhases);
+    w.wcnt = c.take<int32_t>(4 * kMaxScanBlocks);
     const int64_t cap = surv_capacity(ix, total_pairs);
-    w.surv1 = c.take<int2>(cap);
-    w.surv2 = c.take<int2>(cap);
+    w.surv = c.take<int2>(cap);
     *used = c.used;
     return w;
 }
@@ -1243,15 +1400,61 @@ size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, 
 
 template <int WP, int BQT>
 static void launch_phase_kernels(const ScanCtx& c, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
-    if (which == 0) {
-        if (c.G <= 16) hipLaunchKernelGGL((k_scan<WP, BQT, 16>), dim3(2048), dim3(256), 0, s, c);
-        else hipLaunchKernelGGL((k_scan<WP, BQT, 32>), dim3(2048), dim3(256), 0, s, c);
-    } else if (which == 2) {
-        hipLaunchKernelGGL((k_stage2<WP>), dim3(2048), dim3(256), 0, s, c);
-    } else {
-        hipLaunchKernelGGL((k_query_pass<WP, BQT>), dim3((unsigned)nq), dim3(64),
-                           sizeof(unsigned long long) * 2 * c.k_max, s, c, mode, r_lo, r_hi);
+    (void)which;
+    hipLaunchKernelGGL((k_query_pass<WP, BQT>), dim3((unsigned)nq), dim3(64),
+                       sizeof(unsigned long long) * 2 * c.k_max, s, c, mode, r_lo, r_hi);
+}
+
+// Blocks of a persistent kernel that are resident at once on the current device (cached per device).
+template <class K>
+static int resident_blocks(K kernel, int threads, int slot) {
+    static int cache[16][16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
+    int& v = cache[dev][slot];
+    if (v == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        v = per_cu * cus;
     }
+    return v;
+}
+
+template <int GT>
+static void launch_scan_g(const ScanCtx& c, hipStream_t s, int blocks) {
+    switch (c.KI) {
+        case 1: hipLaunchKernelGGL((k_scan<GT, 1>), dim3(blocks), dim3(256), 0, s, c); break;
+        case 2: hipLaunchKernelGGL((k_scan<GT, 2>), dim3(blocks), dim3(256), 0, s, c); break;
+        case 3: case 4: hipLaunchKernelGGL((k_scan<GT, 4>), dim3(blocks), dim3(256), 0, s, c); break;
+        default: hipLaunchKernelGGL((k_scan<GT, 0>), dim3(blocks), dim3(256), 0, s, c); break;
+    }
+}
+
+static void launch_scan(const ScanCtx& c, hipStream_t s, int blocks) {
+    if (c.G <= 16) launch_scan_g<16>(c, s, blocks);
+    else if (c.G <= 32) launch_scan_g<32>(c, s, blocks);
+    else launch_scan_g<64>(c, s, blocks);
+}
+
+// Blocks of the persistent scan grid: what is resident at once on the device, at most kMaxScanBlocks.
+template <int GT>
+static int scan_grid_g(const ScanCtx& c, int slot) {
+    int b;
+    switch (c.KI) {
+        case 1: b = resident_blocks(k_scan<GT, 1>, 256, slot + 0); break;
+        case 2: b = resident_blocks(k_scan<GT, 2>, 256, slot + 1); break;
+        case 3: case 4: b = resident_blocks(k_scan<GT, 4>, 256, slot + 2); break;
+        default: b = resident_blocks(k_scan<GT, 0>, 256, slot + 3); break;
+    }
+    return std::min(b, kMaxScanBlocks);
+}
+static int scan_grid(const ScanCtx& c) {
+    if (c.G <= 16) return scan_grid_g<16>(c, 0);
+    if (c.G <= 32) return scan_grid_g<32>(c, 4);
+    return scan_grid_g<64>(c, 8);
 }
 
 template <int WP>
@@ -1260,7 +1463,7 @@ static void dispatch_bq(const ScanCtx& c, int which, int mode, int r_lo, int r_h
     else launch_phase_kernels<WP, 0>(c, which, mode, r_lo, r_hi, nq, s);
 }
 
-// which = 0: batched stage-1 scan; which = 1: query pass in `mode` over probe ranks [r_lo, r_hi)
+// query pass in `mode` over probe ranks [r_lo, r_hi)
 static void dispatch(const ScanCtx& c, int WP, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
     switch (WP) {
         case 1: dispatch_bq<1>(c, which, mode, r_lo, r_hi, nq, s); break;
@@ -1296,6 +1499,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     const int64_t nq = a.nq;
     const int d = ix.d, d4 = ix.d4, D = ix.D, D4 = ix.D4, nlist = ix.nlist;
     const int64_t P = (int64_t)kPhases * nlist;
+    const int G = a.group <= 16 ? 16 : (a.group <= 32 ? 32 : 64);  // queries per scan work item
 
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
         Timed t(tm, s, "project");
@@ -1318,16 +1522,16 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
-        HIP_TRY(launch_fill_i32(w.scnt, 0, 2 * kPhases, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
+        const int KP = 64 * nh;
         const dim3 gp((unsigned)((a.total_pairs + 3) / 4));
 #define PREP(NHV)                                                                                          \
     hipLaunchKernelGGL(k_pair_prep<NHV>, gp, dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, \
-                       nlist, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.boff, w.fill, w.recs,      \
-                       w.planes, w.pair_pos)
+                       nlist, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP,   \
+                       w.recs, w.planes, w.qu8, w.pair_pos)
         if (nh <= 1) PREP(1);
         else if (nh <= 2) PREP(2);
         else if (nh <= 4) PREP(4);
@@ -1336,21 +1540,28 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         else PREP(24);
 #undef PREP
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
-                           nlist, a.group <= 16 ? 16 : 32, (int)P, w.items);
+                           nlist, G, (int)P, w.items);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, P);
+        hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff, ix.list_nb,
+                           ix.list_off, nlist, G, P, w.desc);
         HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
         HIP_TRY(hipGetLastError());
     }
     ScanCtx c;
-    c.recs = w.recs; c.planes = w.planes; c.boff = w.boff; c.ioff = w.ioff;
+    c.recs = w.recs; c.planes = w.planes; c.qu8 = w.qu8; c.boff = w.boff; c.ioff = w.ioff; c.desc = w.desc;
     c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.list_len = ix.list_len; c.code = ix.code; c.ext = ix.ext;
     c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
     c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
-    c.slots = w.slots; c.surv1 = w.surv1; c.surv2 = w.surv2; c.cnt = w.scnt; c.counters = a.counters;
-    c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = a.group <= 16 ? 16 : 32;
+    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.counters = a.counters;
+    c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
+    c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
-    c.cap = (int)surv_capacity(ix, a.total_pairs);
+    // persistent scan grid (resident blocks) and each scan wave's share of the exact-stage buffer
+    const int scan_blocks = scan_grid(c);
+    int64_t cap = surv_capacity(ix, a.total_pairs);
+    if (a.exact_cap > 0 && a.exact_cap < cap) cap = a.exact_cap;
+    c.rs = (int)(cap / (4ll * scan_blocks));
     {
         Timed t(tm, s, "seed");
         dispatch(c, ix.WP, 1, PASS_SEED, 0, 1, nq, s);
@@ -1359,7 +1570,6 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     for (int p = 1; p < kPhases; p++) {
         if (a.np_max <= phase_lo(p)) break;
         c.phase = p;
-        c.cnt = w.scnt + 2 * p;
         {
             Timed t(tm, s, "tau");
             hipLaunchKernelGGL(k_tau_snap, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
@@ -1367,17 +1577,12 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         }
         {
             Timed t(tm, s, "scan");
-            dispatch(c, ix.WP, 0, 0, 0, 0, nq, s);
-            HIP_TRY(hipGetLastError());
-        }
-        {
-            Timed t(tm, s, "stage2");
-            dispatch(c, ix.WP, 2, 0, 0, 0, nq, s);
+            launch_scan(c, s, scan_blocks);
             HIP_TRY(hipGetLastError());
         }
         {
             Timed t(tm, s, "exact");
-            hipLaunchKernelGGL(k_exact, dim3(2048), dim3(256), 0, s, c);
+            hipLaunchKernelGGL(k_exact, dim3((unsigned)(4 * scan_blocks)), dim3(256), 0, s, c);
             HIP_TRY(hipGetLastError());
         }
     }

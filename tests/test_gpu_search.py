@@ -240,3 +240,40 @@ def test_save_load_roundtrip(small):
     c, d = ix2.search(small["Qd"], 10, 8)
     torch.cuda.synchronize()
     assert np.array_equal(a, c.cpu().numpy()) and np.array_equal(b, d.cpu().numpy())
+
+
+def test_exact_buffer_overflow_gives_same_results(small, small_ext):
+    """Candidates that do not fit the exact-stage buffer are finished inside the scan with the same
+    arithmetic, so a buffer of a single entry returns bit-identical results."""
+    for env in (small, small_ext):
+        ix, Q = env["ix"], env["Q"]
+        a_ids, a_d = ix.search(Q, 10, 16)
+        b_ids, b_d = ix.search(Q, 10, 16, opts=mrq.search_opts(exact_cap=1))
+        assert np.array_equal(a_ids, b_ids)
+        assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+
+
+@pytest.mark.parametrize("group", [16, 32, 64])
+def test_group_size_does_not_change_results(small, group):
+    ix, Q = small["ix"], small["Q"]
+    a_ids, a_d = ix.search(Q, 10, 16)
+    b_ids, b_d = ix.search(Q, 10, 16, opts=mrq.search_opts(group=group))
+    assert np.array_equal(a_ids, b_ids)
+    assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+
+
+def test_eight_bit_codes_and_query_levels():
+    """B = 8 extended codes and B_q = 8 query levels exceed the signed-byte range of the i8 matrix-core
+    operands; the scan stores them with an offset and corrects the products exactly."""
+    print("\n[gpu] build N=6000 D=128 d=32 B=8 nlist=24", flush=True)
+    env = _mk("small", 6000, 40, 32, 8, 24)
+    cnt = {}
+    for bq in (4, 8):
+        c = torch.zeros(8, dtype=torch.int64, device="cuda")
+        ids, dists = _search(env, 10, 8, bq=bq, counters=c)
+        _assert_parity(env, ids, dists, 10, 8, prm=oracle.params(bq=bq))
+        cnt[bq] = c.cpu().numpy()
+    # both query resolutions prune a similar share of candidates at stage 1 and with the B-bit codes
+    for i in (1, 2):
+        r4, r8 = cnt[4][i] / cnt[4][0], cnt[8][i] / cnt[8][0]
+        assert 0.5 * r4 <= r8 <= 1.5 * r4 + 1e-3, (i, r4, r8)
