@@ -20,6 +20,9 @@
 
 namespace mrq {
 
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------------------------------------------------
 // small helpers
 
@@ -309,6 +312,130 @@ static hipError_t launch_gemm_dist(const float* A, int64_t lda, const float* Bm,
     dim3 grid((unsigned)((M + 63) / 64), (N + 63) / 64);
     hipLaunchKernelGGL(k_gemm_nt<1>, grid, dim3(256), 0, s, A, lda, nullptr, Bm, ldb, Cm, ldc, M, N, K,
                        rowv, colv);
+    return hipGetLastError();
+}
+
+// FP32 matrix-core form of the same product, C = (A - asub) B^T, for the large query-side products.
+// One wave computes a 64 x 64 tile of C as 4 x 4 v_mfma_f32_16x16x4_f32 sub-tiles; its A and B
+// fragments are read straight from memory (rows are K-contiguous), VEC = 4: one dwordx4 per lane per
+// fragment and 16-wide K step (lane group g feeds k = 16s + 4g + e in multiply step e), VEC = 1: one
+// float per lane per 4-wide K step.  Every element is one chain of fused multiply-adds over k in a fixed
+// order that depends only on K and VEC, so a row's result does not depend on the other rows.
+// EPI 0: C[m][n];  EPI 1: max(0, rowv[m] + colv[n] - 2 C) (squared distances);  EPI 2: columns below
+// nsplit go to C (ldc), the others to C2 (ldc2) at column n - nsplit.
+template <int VEC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, int64_t lda,
+                                                   const float* __restrict__ asub,
+                                                   const float* __restrict__ Bm, int64_t ldb,
+                                                   float* __restrict__ Cm, int64_t ldc, int64_t M, int N, int K,
+                                                   const float* __restrict__ rowv, const float* __restrict__ colv,
+                                                   float* __restrict__ C2, int64_t ldc2, int nsplit) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, kg = lane >> 4;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const int n0 = blockIdx.y * 64;
+    if (m0 >= M) return;
+    const float* ar[4];
+    const float* br[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t m = m0 + 16 * i + li;
+        ar[i] = A + (m < M ? m : M - 1) * lda;
+        const int n = n0 + 16 * i + li;
+        br[i] = Bm + (int64_t)(n < N ? n : N - 1) * ldb;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (VEC == 4) {
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            const int k = k0 + 4 * kg;
+            const int kc = k < K ? k : 0;  // in-row offset actually read (always valid)
+            const bool e0 = k < K, e1 = k + 1 < K, e2 = k + 2 < K, e3 = k + 3 < K;
+            float4 av[4], bv[4];
+            float4 sub = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (asub) sub = *reinterpret_cast<const float4*>(asub + kc);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                float4 a = *reinterpret_cast<const float4*>(ar[i] + kc);
+                float4 b = *reinterpret_cast<const float4*>(br[i] + kc);
+                if (asub) { a.x -= sub.x; a.y -= sub.y; a.z -= sub.z; a.w -= sub.w; }
+                av[i] = make_float4(e0 ? a.x : 0.f, e1 ? a.y : 0.f, e2 ? a.z : 0.f, e3 ? a.w : 0.f);
+                bv[i] = make_float4(e0 ? b.x : 0.f, e1 ? b.y : 0.f, e2 ? b.z : 0.f, e3 ? b.w : 0.f);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
+        }
+    } else {
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + kg;
+            const bool in = k < K;
+            const int kc = in ? k : 0;
+            const float sub = asub ? asub[kc] : 0.f;
+            float av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const float a = ar[i][kc] - sub;
+                av[i] = in ? a : 0.f;
+                bv[i] = in ? br[i][kc] : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // lane holds C[m0 + 16 i + 4 kg + v][n0 + 16 j + li]
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int n = n0 + 16 * j + li;
+        if (n >= N) continue;
+        const float cv = EPI == 1 ? colv[n] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int64_t m = m0 + 16 * i + 4 * kg + v;
+                if (m >= M) continue;
+                float r = acc[i][j][v];
+                if (EPI == 1) r = fmaxf(0.f, fmaf(-2.f, r, rowv[m] + cv));
+                if (EPI == 2 && n >= nsplit) C2[m * ldc2 + (n - nsplit)] = r;
+                else Cm[m * ldc + n] = r;
+            }
+        }
+    }
+}
+
+static bool vec4_ok(const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0 && (ld & 3) == 0; }
+
+template <int EPI>
+static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
+                                   float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
+                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 63) / 64));
+    if (vec4_ok(A, lda) && vec4_ok(Bm, ldb) && (!asub || vec4_ok(asub, 0)))
+        hipLaunchKernelGGL((k_gemm_mfma<4, EPI>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K,
+                           rowv, colv, C2, ldc2, nsplit);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<1, EPI>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K,
+                           rowv, colv, C2, ldc2, nsplit);
     return hipGetLastError();
 }
 
@@ -767,9 +894,6 @@ __device__ __forceinline__ float ord_to_float(uint32_t o) {
 // get their exact distance inside this kernel, with the same arithmetic as k_exact.  Every decision of a
 // phase uses the phase threshold stored in the pair record, so the set of candidates reaching each
 // stage does not depend on the order in which items run.
-
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // 4 bits -> 4 bytes holding 0 or 1 (byte e <- bit e); the shifted copies never overlap, so no carries.
 __device__ __forceinline__ int nib_bytes(uint32_t n) { return (int)(((n & 0xFu) * 0x00204081u) & 0x01010101u); }
@@ -1504,16 +1628,19 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
         Timed t(tm, s, "project");
         HIP_TRY(launch_fill_f32(w.qd, 0.f, nq * d4, s));
-        HIP_TRY(launch_gemm_nt(a.Q, D, ix.mu, ix.PpLead, D, w.qd, d4, nq, d, D, s));
-        if (D > d) HIP_TRY(launch_gemm_nt(a.Q, D, ix.mu, ix.PpTail, D, w.qtail, D - d, nq, D - d, D, s));
+        // all D axes in one product: columns < d are q_d, the rest the tail coordinates of Eq 6
+        HIP_TRY(launch_gemm_mfma<2>(a.Q, D, ix.mu, ix.Pp, D, w.qd, d4, nq, D, D, nullptr, nullptr, w.qtail,
+                                    D - d, d, s));
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4,
                            w.qtail, ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
         HIP_TRY(hipGetLastError());
-        HIP_TRY(launch_gemm_nt(w.qd, d4, nullptr, ix.PrT, d4, w.rq, d4, nq, d, d, s));
+        HIP_TRY(launch_gemm_mfma<0>(w.qd, d4, nullptr, ix.PrT, d4, w.rq, d4, nq, d, d, nullptr, nullptr, nullptr, 0,
+                                    0, s));
     }
     {   // centroid ranking
         Timed t(tm, s, "probe");
-        HIP_TRY(launch_gemm_dist(w.qd, d4, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, s));
+        HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr,
+                                    0, 0, s));
         hipLaunchKernelGGL(k_select, dim3((unsigned)nq), dim3(256), 0, s, w.G, nlist, a.npq, a.pair_off,
                            w.pair_list, w.pair_q);
         HIP_TRY(hipGetLastError());
