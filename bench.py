@@ -286,6 +286,8 @@ def main():
         "pass_rates": {"stage1": round(p1 / max(scanned, 1), 5), "ext": round(pext / max(scanned, 1), 5),
                        "stage2_exact": round(p2 / max(scanned, 1), 6),
                        "seed_scanned_per_query": round(float(cnt[4]) / nq, 1),
+                       "seed_exact_per_query": round(float(cnt[7]) / nq, 1),
+                       "exact_per_query": round(p2 / nq, 1),
                        "scanned_per_query": round(scanned / nq, 1)},
         "nprobe_sweep": sweep,
     }

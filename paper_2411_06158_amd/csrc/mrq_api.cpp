@@ -295,9 +295,10 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     }
 
     // x_d = P_p[:d] (x - mu) by id, and the FP64 norms
-    DevTemp xd_id(sizeof(float) * (size_t)N * d4);
+    DevTemp xd_id(sizeof(float) * (size_t)N * d4), xt_id(sizeof(float) * (size_t)N * std::max(D - d, 1));
     hip_check(launch_fill_f32(xd_id.as<float>(), 0.f, N * (int64_t)d4, s), "fill");
-    hip_check(launch_gemm_nt(Xd, D, ix->mu, ix->Pp, D, xd_id.as<float>(), d4, N, d, D, s), "project data");
+    hip_check(launch_project(Xd, N, D, ix->mu, ix->Pp, d, xd_id.as<float>(), d4, xt_id.as<float>(), D - d, s),
+              "project data");
     DevTemp ax64(sizeof(double) * N), tx64(sizeof(double) * N);
     hip_check(launch_rownorms(Xd, N, D, mu64.as<double>(), xd_id.as<float>(), d4, d, ax64.as<double>(),
                               tx64.as<double>(), s), "row norms");
@@ -428,7 +429,7 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     ix->yn = dalloc<float>(ix.get(), Np);
     DevTemp O(sizeof(float) * Np * d4), Xpp(sizeof(float) * Np * d4), txr(sizeof(double) * Np),
         rowl(sizeof(int32_t) * Np);
-    hip_check(launch_gather_layout(*ix, Xd, permd.as<int32_t>(), xd_id.as<float>(), ax64.as<double>(),
+    hip_check(launch_gather_layout(*ix, xt_id.as<float>(), permd.as<int32_t>(), xd_id.as<float>(), ax64.as<double>(),
                                    tx64.as<double>(), txr.as<double>(), rowl.as<int32_t>(), O.as<float>(), s),
               "layout");
 
@@ -865,7 +866,7 @@ mrq_status mrq_save(const mrq_index* cix, const char* path) {
         mrq_index* ix = const_cast<mrq_index*>(cix);
         hip_check(hipDeviceSynchronize(), "sync");
         File f(path, "wb");
-        f.w("MRQS0001", 8);
+        f.w("MRQS0002", 8);
         int64_t h64[2] = {ix->N, ix->Npad};
         int32_t h32[6] = {ix->D, ix->d, ix->B, ix->nlist, ix->WP, ix->max_list_len};
         f.w(h64, sizeof(h64));
@@ -888,7 +889,7 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         File f(path, "rb");
         char magic[8];
         f.r(magic, 8);
-        if (std::memcmp(magic, "MRQS0001", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0001 file");
+        if (std::memcmp(magic, "MRQS0002", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0002 file");
         std::unique_ptr<mrq_index> ix(new mrq_index());
         hip_check(hipGetDevice(&ix->device), "hipGetDevice");
         int64_t h64[2];

@@ -93,7 +93,7 @@ struct Index {
     float* fSX = nullptr;        // Npad: 2 sum_i u_i - (2^B - 1) d
     float* xd = nullptr;         // Npad x d4 leading coordinates of x_p
     float* ax = nullptr;         // Npad: ||x - mu||^2
-    float* X = nullptr;          // Npad x D4 original vectors in list order
+    float* X = nullptr;          // Npad x D4 vectors in PCA coordinates x_p = P_p (x - mu), list order
     // export-only per-row summaries (list order)
     float *nx = nullptr, *tx = nullptr, *xi1 = nullptr, *xiB = nullptr, *yn = nullptr;
 
@@ -147,6 +147,10 @@ hipError_t launch_colmean(const float* X, int64_t N, int D, double* part, int nc
 hipError_t launch_cov(const float* X, int64_t N, int D, const double* mu64, double* part, int nsplit,
                       double* S, hipStream_t s);
 int cov_splits(int64_t N, int D);
+// x_p = P_p (x - mu) for M rows of X (row stride D) on the matrix cores: coordinates < d into lead
+// (row stride ld_lead), the others into tail (row stride ld_tail).
+hipError_t launch_project(const float* X, int64_t M, int D, const float* mu, const float* Pp, int d, float* lead,
+                          int64_t ld_lead, float* tail, int64_t ld_tail, hipStream_t s);
 hipError_t launch_gemm_nt(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
                           float* Cm, int64_t ldc, int64_t M, int N, int K, hipStream_t s);
 hipError_t launch_rownorms(const float* X, int64_t N, int D, const double* mu64, const float* xd,
@@ -160,7 +164,7 @@ hipError_t launch_kmeans_accum(const float* P, int64_t n, int ldp, int dim, cons
 hipError_t launch_kmeans_centroids(const double* sums, const int32_t* cnt, int k, int dim, float* C,
                                    int ldc, float* cn2, hipStream_t s);
 hipError_t launch_sqnorms(const float* A, int64_t n, int lda, int dim, float* out, hipStream_t s);
-hipError_t launch_gather_layout(const Index& ix, const float* Xuser, const int32_t* perm,
+hipError_t launch_gather_layout(const Index& ix, const float* xt_id, const int32_t* perm,
                                 const float* xd_id, const double* ax64, const double* tx64, double* txr,
                                 int32_t* row_list, float* O, hipStream_t s);
 hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, const double* tx64_rows,

@@ -68,10 +68,17 @@ __device__ __forceinline__ uint32_t ord_bits(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Exact squared distance (Algorithm 2, exact stage) of two zero-padded rows of D4 floats, computed
-// by a group of 16 lanes: lane l of the group accumulates the float4 chunks l, l + 16, l + 32, ... in
-// ascending order, then a butterfly over the group.  A wave evaluates four pairs at once; the value of
-// a pair depends only on its two rows.
+// Exact squared distance (Algorithm 2, exact stage) ||x_p - q_p||^2 (= ||x - q||^2, Eq 1) of two
+// zero-padded rows of D4 floats in PCA coordinates, computed by a group of 16 lanes: lane l of the group
+// accumulates the float4 chunks l, l + 16, l + 32, ... in ascending order, then a butterfly over the
+// group.  A wave evaluates four pairs at once; the value of a pair depends only on its two rows.
+__device__ __forceinline__ void acc_sqdiff(float& s, const float4& a, const float4& b) {
+    float t;
+    t = a.x - b.x; s = fmaf(t, t, s);
+    t = a.y - b.y; s = fmaf(t, t, s);
+    t = a.z - b.z; s = fmaf(t, t, s);
+    t = a.w - b.w; s = fmaf(t, t, s);
+}
 __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, const float* __restrict__ q,
                                                   int D4, int l16) {
     const int nc = D4 >> 2;  // float4 chunks per row
@@ -89,13 +96,19 @@ __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, c
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             if (base + 16 * u + l16 >= nc) break;
-            float t;
-            t = a[u].x - b[u].x; s = fmaf(t, t, s);
-            t = a[u].y - b[u].y; s = fmaf(t, t, s);
-            t = a[u].z - b[u].z; s = fmaf(t, t, s);
-            t = a[u].w - b[u].w; s = fmaf(t, t, s);
+            acc_sqdiff(s, a[u], b[u]);
         }
     }
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+// Low-register form with the same operation order (hence the same results), for the rarely taken
+// in-place path of the scan kernel.
+__device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
+                                                        int D4, int l16) {
+    float s = 0.f;
+    for (int ci = l16; ci < (D4 >> 2); ci += 16)
+        acc_sqdiff(s, reinterpret_cast<const float4*>(x)[ci], reinterpret_cast<const float4*>(q)[ci]);
     for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     return s;
 }
@@ -427,6 +440,16 @@ static bool vec4_ok(const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0
 template <int EPI>
 static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
                                    float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
+                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s);
+
+hipError_t launch_project(const float* X, int64_t M, int D, const float* mu, const float* Pp, int d, float* lead,
+                          int64_t ld_lead, float* tail, int64_t ld_tail, hipStream_t s) {
+    return launch_gemm_mfma<2>(X, D, mu, Pp, D, lead, ld_lead, M, D, D, nullptr, nullptr, tail, ld_tail, d, s);
+}
+
+template <int EPI>
+static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
+                                   float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
                                    const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 63) / 64));
@@ -498,12 +521,13 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
     const int64_t q = blockIdx.x;
     const int lane = threadIdx.x;
     const float* qr = Q + q * D;
+    const int r = D - d;
     float s = 0.f;
     for (int i = lane; i < D4; i += 64) {
-        float v = i < D ? qr[i] : 0.f;
-        qpad[q * D4 + i] = v;
+        // q_p = P_p (q - mu) padded to D4: the leading d coordinates, then the tail
+        qpad[q * D4 + i] = i < d ? qd[q * d4 + i] : (i < D ? qtail[q * (int64_t)r + (i - d)] : 0.f);
         if (i < D) {
-            float c = v - mu[i];
+            float c = qr[i] - mu[i];
             s = fmaf(c, c, s);
         }
     }
@@ -515,7 +539,6 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
     }
     sd = wave_sum(sd);
     float var = 0.f;
-    const int r = D - d;
     for (int i = lane; i < r; i += 64) {
         float v = qtail[q * (int64_t)r + i];
         var = fmaf(lam_tail[i], v * v, var);
@@ -866,6 +889,7 @@ struct ScanCtx {
     const int64_t* pair_off;
     const int32_t* pair_pos;
     unsigned long long* slots;
+    int32_t* claims;     // per (phase, claim group): items of the group's range taken so far
     int2* surv;          // exact-stage candidates of the current phase: (row, query), rs per scan wave
     int32_t* wcnt;       // candidates produced by each scan wave (the first rs are in its region)
     int64_t* counters;
@@ -917,24 +941,6 @@ __device__ __forceinline__ i32x4 piece_bytes(uint32_t p) {
     r.z = nib_bytes(p >> 8);
     r.w = nib_bytes(p >> 12);
     return r;
-}
-
-// Low-register form of exact_dist_group with the same operation order (hence the same results), for
-// the rarely taken in-place path of the scan kernel.
-__device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
-                                                        int D4, int l16) {
-    float s = 0.f;
-    for (int ci = l16; ci < (D4 >> 2); ci += 16) {
-        const float4 a = reinterpret_cast<const float4*>(x)[ci];
-        const float4 b = reinterpret_cast<const float4*>(q)[ci];
-        float t;
-        t = a.x - b.x; s = fmaf(t, t, s);
-        t = a.y - b.y; s = fmaf(t, t, s);
-        t = a.z - b.z; s = fmaf(t, t, s);
-        t = a.w - b.w; s = fmaf(t, t, s);
-    }
-    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    return s;
 }
 
 // Exact distances of the sub-tile entries in mask m (bit l: row rbase + (l & 15), query of pair slot
@@ -1005,16 +1011,52 @@ __device__ __forceinline__ f32x4 dot_tile(const float* __restrict__ qp, const fl
     return acc;
 }
 
+// The same product with the row tile's x_d slices already in registers (SU slices, zero beyond d4).
+template <int SU>
+__device__ __forceinline__ void load_x_slices(float4 (&xa)[SU], const float* __restrict__ xp, int d4, int kg) {
+    const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xp);
+#pragma unroll
+    for (int t = 0; t < SU; t++) {
+        const bool in = 16 * t + 4 * kg < d4;
+        xa[t] = zero_unless(x4[in ? 4 * t : 0], in);
+    }
+}
+template <int SU>
+__device__ __forceinline__ f32x4 dot_tile_x(const float4 (&xa)[SU], const float* __restrict__ qp, bool qv, int d4,
+                                            int kg) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float4* __restrict__ q4 = reinterpret_cast<const float4*>(qp);
+    float4 qa[SU];
+#pragma unroll
+    for (int t = 0; t < SU; t++) {
+        const bool in = 16 * t + 4 * kg < d4;
+        qa[t] = zero_unless(q4[in ? 4 * t : 0], in && qv);
+    }
+#pragma unroll
+    for (int t = 0; t < SU; t++) mfma4(acc, qa[t], xa[t]);
+    return acc;
+}
+
 // Ordering of LDS accesses between the lanes of one wave (they execute in program order; this only
 // keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// KIT > 0: d <= 64 KIT (K-slice loops unrolled); KIT = 0: any d.
-template <int GT, int KIT>
+constexpr int kClaimGroups = 64;
+
+// LDS staging of an item's q_d rows for stage 2 (QL): rows of d4 floats, d4 a multiple of 64, float4
+// column f of pair slot s stored at f ^ (s & 15), so the 16 lanes of a lane group read 16 different banks.
+__device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slot * nf4 + (f4 ^ (slot & 15)); }
+
+// One phase of the batched scan.  KIT > 0: d <= 64 KIT (stage-1 operands of an item loaded up front);
+// KIT = 0: any d.  QL: the item's q_d rows are staged in LDS for stage 2 (d4 = 64 KIT).
+template <int GT, int KIT, bool QL>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
+    constexpr int KA = KIT > 0 ? KIT : 1;
+    constexpr int XS = QL && KIT > 0 ? 4 * KIT : 1;  // x_d slices of a row tile held in registers
     __shared__ PairRec sh_rec[4][GT];
     __shared__ unsigned long long sh_m[4][NCT * 16];  // surviving entries per (column tile, row tile, v)
+    extern __shared__ float4 qsh_dyn[];               // QL: 4 x GT rows of d4 / 4 float4
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
     const int li = lane & 15, kg = lane >> 4;
@@ -1022,125 +1064,241 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     const int base_item = (int)const_load((const uint32_t*)(c.ioff + p * c.nlist));
     const int total = (int)const_load((const uint32_t*)(c.ioff + (p + 1) * c.nlist)) - base_item;
     const int KI = KIT > 0 ? KIT : c.KI;
+    const int nf4 = c.d4 >> 2;
     const int ob = c.bq == 8 ? 128 : 0;  // query levels are stored as the signed bytes u - ob
     const int oa = c.B == 8 ? 128 : 0;   // extended levels enter the product as the signed bytes ux - oa
     const bool do_ext = c.B > 1 && c.use_ext;
     const int WP = c.WP;
     PairRec* rec = sh_rec[wv];
     unsigned long long* msk = sh_m[wv];
+    float4* qsh = qsh_dyn + (QL ? wv * GT * nf4 : 0);
     const unsigned long long lt = (1ull << lane) - 1ull;
     // this wave's region of the exact-stage buffer
-    const int wid = blockIdx.x * 4 + wv;
+    const int wid = uniform(blockIdx.x * 4 + wv);
     int2* region = c.surv + (int64_t)wid * c.rs;
     int nreg = 0;  // candidates this wave produced (may exceed rs; the rest is finished in place)
     long long nscan = 0, n1 = 0, next = 0;
-    // items are dealt to the waves round-robin: neighbouring waves take neighbouring blocks of a list
+    // Items are dealt to the waves round-robin (neighbouring waves take neighbouring blocks of a list).
+    // The descriptor and the pair records of the next item are requested while the current one is
+    // scanned; the records travel in plain registers (three float4 per lane) until they are stored.
     const int nwaves = gridDim.x * 4;
+    int4 dnext = make_int4(0, 0, 1, 0);
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    auto fetch = [&](int item) {
+        dnext = const_load4(c.desc + base_item + item);
+        const float4* rp = reinterpret_cast<const float4*>(c.recs + dnext.y + (lane < dnext.z ? lane : 0));
+        r0 = rp[0];
+        r1 = rp[1];
+        r2 = rp[2];
+    };
+    if (wid < total) fetch(wid);
     for (int it = wid; it < total; it += nwaves) {
-        const int4 dsc = const_load4(c.desc + base_item + it);
+        const int4 dsc = dnext;
         const int64_t row0 = dsc.x;
         const int pbeg = dsc.y, ng = dsc.z;
         const int nct = (ng + 15) >> 4;
-        {
-            const PairRec rg = c.recs[pbeg + (lane < ng ? lane : 0)];
-            if (lane < ng) rec[lane] = rg;
+        if (lane < ng) {
+            float4* rw = reinterpret_cast<float4*>(rec + lane);
+            rw[0] = r0;
+            rw[1] = r1;
+            rw[2] = r2;
         }
-        wave_lds_fence();
-        int tot = 0;
-        for (int ct = 0; ct < NCT; ct++) {
-            if (ct >= nct) break;
-            const int qs = ct * 16 + li;  // pair slot whose query this lane feeds to the A operand
-            const bool qv = qs < ng;
-            const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+        if (it + nwaves < total) fetch(it + nwaves);
+
+        // ---- stage 1 for every 16 x 16 sub-tile: pass masks into msk ----
+        int cnt = 0;
+        if (KIT > 0) {
+            uint32_t cw[4][KA];
+            float fa[4], ff[4], fe[4];
+            i32x4 qa[NCT][KA];
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++) {
+                const int64_t row = row0 + 16 * rt + li;
+#pragma unroll
+                for (int m = 0; m < KA; m++) {
+                    const int w = 2 * m + (kg >> 1);
+                    const uint32_t word = c.code[row * WP + (w < WP ? w : 0)];
+                    cw[rt][m] = w < WP ? (word >> ((kg & 1) << 4)) & 0xFFFFu : 0u;
+                }
+                fa[rt] = c.fA[row];
+                ff[rt] = c.fF[row];
+                fe[rt] = c.fE[row];
+            }
+#pragma unroll
+            for (int ct = 0; ct < NCT; ct++) {
+                const int qs = ct * 16 + li;
+                const bool qv = qs < ng;
+                const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+#pragma unroll
+                for (int m = 0; m < KA; m++) qa[ct][m] = qop(qb, m, qv);
+            }
+            wave_lds_fence();
+#pragma unroll
+            for (int rt = 0; rt < 4; rt++) {
+                int sp = 0;
+#pragma unroll
+                for (int m = 0; m < KA; m++) sp += __builtin_popcount(cw[rt][m]);
+                const int s2 = sp + __shfl_xor(sp, 16);
+                const int pc = s2 + __shfl_xor(s2, 32);  // popcount of the whole sign code of the row
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++) {
+                    if (ct < nct) {
+                        i32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+                        for (int m = 0; m < KA; m++)
+                            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(qa[ct][m], piece_bytes(cw[rt][m]), acc, 0, 0, 0);
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int g = ct * 16 + 4 * kg + v;
+                            const PairRec& R = rec[g < ng ? g : 0];
+                            const bool ps = g < ng &&
+                                            stage1_from_ip(acc[v] + ob * pc, pc, fa[rt], ff[rt], fe[rt], R, c.d) < R.tau;
+                            const unsigned long long mv = __ballot(ps);
+                            if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
+                            cnt += __popcll(mv);
+                        }
+                    }
+                }
+            }
+        } else {
+            wave_lds_fence();
             for (int rt = 0; rt < 4; rt++) {
                 const int64_t row = row0 + 16 * rt + li;
                 const uint32_t* cp = c.code + row * WP;
-                i32x4 acc = {0, 0, 0, 0};
-                int pcs = 0;
+                int sp = 0;
+                for (int m = 0; m < KI; m++) sp += __builtin_popcount(plane_piece(cp, WP, m, kg));
+                const int s2 = sp + __shfl_xor(sp, 16);
+                const int pc = s2 + __shfl_xor(s2, 32);
+                const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
+                for (int ct = 0; ct < nct; ct++) {
+                    const int qs = ct * 16 + li;
+                    const bool qv = qs < ng;
+                    const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+                    i32x4 acc = {0, 0, 0, 0};
+                    for (int m = 0; m < KI; m++)
+                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(qop(qb, m, qv), piece_bytes(plane_piece(cp, WP, m, kg)),
+                                                                     acc, 0, 0, 0);
 #pragma unroll
-                for (int m = 0; m < (KIT > 0 ? KIT : 1); m++) {
-                    if (KIT == 0 && m >= KI) break;
-                    const uint32_t pb = plane_piece(cp, WP, m, kg);
-                    pcs += __builtin_popcount(pb);
-                    const i32x4 av = qop(qb, m, qv);
-                    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, piece_bytes(pb), acc, 0, 0, 0);
-                }
-                if (KIT == 0) {
-                    for (int m = 1; m < KI; m++) {
-                        const uint32_t pb = plane_piece(cp, WP, m, kg);
-                        pcs += __builtin_popcount(pb);
-                        const i32x4 av = qop(qb, m, qv);
-                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, piece_bytes(pb), acc, 0, 0, 0);
+                    for (int v = 0; v < 4; v++) {
+                        const int g = ct * 16 + 4 * kg + v;
+                        const PairRec& R = rec[g < ng ? g : 0];
+                        const bool ps = g < ng && stage1_from_ip(acc[v] + ob * pc, pc, A, F, E, R, c.d) < R.tau;
+                        const unsigned long long mv = __ballot(ps);
+                        if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
+                        cnt += __popcll(mv);
                     }
                 }
-                const int pc2 = pcs + __shfl_xor(pcs, 16);
-                const int pc = pc2 + __shfl_xor(pc2, 32);  // popcount of the whole sign code of `row`
-                const float A = c.fA[row], F = c.fF[row], E = c.fE[row];
-                bool pass[4];
+            }
+        }
+        nscan += 64ll * ng;
+        n1 += cnt;
+        wave_lds_fence();
+
+        // ---- B-bit refinement of the stage-1 survivors ----
+        if (cnt > 0 && do_ext) {
+            cnt = 0;
+            for (int rt = 0; rt < 4; rt++) {
+                const int64_t row = row0 + 16 * rt + li;
+                const uint32_t* cp = c.code + row * WP;
+                const uint32_t* ew = c.ext + row * (int64_t)(c.B - 1) * WP;
+                for (int ct = 0; ct < nct; ct++) {
+                    unsigned long long mv[4];
+                    bool any = false;
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int g = ct * 16 + 4 * kg + v;
-                    const PairRec& R = rec[g < ng ? g : 0];
-                    pass[v] = g < ng && stage1_from_ip(acc[v] + ob * pc, pc, A, F, E, R, c.d) < R.tau;
-                }
-                int cnt1 = 0;
-#pragma unroll
-                for (int v = 0; v < 4; v++) cnt1 += __popcll(__ballot(pass[v]));
-                n1 += cnt1;
-                if (cnt1 == 0) {
-                    if (lane < 4) msk[(ct * 4 + rt) * 4 + lane] = 0ull;
-                    continue;
-                }
-                if (do_ext) {
+                    for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
+                    if (!any) continue;
+                    const int qs = ct * 16 + li;
+                    const bool qv = qs < ng;
+                    const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
                     i32x4 acc2 = {0, 0, 0, 0};
-                    const uint32_t* ew = c.ext + row * (int64_t)(c.B - 1) * WP;
                     for (int m = 0; m < KI; m++) {
                         i32x4 ub = piece_bytes(plane_piece(cp, WP, m, kg)) << (c.B - 1);
                         for (int a = 0; a < c.B - 1; a++) ub |= piece_bytes(plane_piece(ew + a * WP, WP, m, kg)) << a;
                         if (oa) ub ^= (int)0x80808080u;
                         acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(qop(qb, m, qv), ub, acc2, 0, 0, 0);
                     }
-                    const float FB = c.fFB[row], EB = c.fEB[row], SX = c.fSX[row];
+                    const float A = c.fA[row], FB = c.fFB[row], EB = c.fEB[row], SX = c.fSX[row];
                     const long long sumux = ((long long)SX + (long long)((1 << c.B) - 1) * c.d) / 2;
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        if (pass[v]) {
+                        bool ps = (mv[v] >> lane) & 1ull;
+                        if (ps) {
                             const PairRec& R = rec[ct * 16 + 4 * kg + v];
                             // sum_i ux_i u_i from sum_i (ux_i - oa)(u_i - ob) over the d real dimensions
                             const long long ipB = (long long)acc2[v] + ob * sumux + oa * (long long)R.su -
                                                   (long long)oa * ob * c.d;
-                            pass[v] = ext_from_ip(ipB, c.B, A, FB, EB, SX, R) < R.tau;
+                            ps = ext_from_ip(ipB, c.B, A, FB, EB, SX, R) < R.tau;
                         }
+                        const unsigned long long nm = __ballot(ps);
+                        if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
+                        cnt += __popcll(nm);
                     }
                 }
-                int cntx = 0;
+            }
+            wave_lds_fence();
+        }
+        next += cnt;
+
+        // ---- stage 2 (Eq 7) of the remaining survivors ----
+        if (cnt > 0 && c.stage2) {
+            if (QL) {  // the item's q_d rows into LDS
+                const float4* q4 = reinterpret_cast<const float4*>(c.qd);
+                for (int e = lane; e < ng * nf4; e += 64) {
+                    const int slot = e / nf4, f = e - slot * nf4;
+                    qsh[qsh_index(slot, f, nf4)] = q4[(int64_t)rec[slot].q * nf4 + f];
+                }
+                wave_lds_fence();
+            }
+            cnt = 0;
+            for (int rt = 0; rt < 4; rt++) {
+                const int64_t row = row0 + 16 * rt + li;
+                float4 xa[XS];
+                bool xl = false;
+                for (int ct = 0; ct < nct; ct++) {
+                    unsigned long long mv[4];
+                    bool any = false;
 #pragma unroll
-                for (int v = 0; v < 4; v++) cntx += __popcll(__ballot(pass[v]));
-                next += cntx;
-                if (cntx > 0 && c.stage2) {
-                    const int qrow = rec[qv ? qs : 0].q;
-                    const f32x4 dot = dot_tile<4 * KIT>(c.qd + (int64_t)qrow * c.d4 + 4 * kg,
-                                                        c.xd + row * c.d4 + 4 * kg, qv, c.d4, kg);
+                    for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
+                    if (!any) continue;
+                    const int qs = ct * 16 + li;
+                    const bool qv = qs < ng;
+                    f32x4 dot;
+                    if (QL) {
+                        if (!xl) {
+                            load_x_slices<XS>(xa, c.xd + row * c.d4 + 4 * kg, c.d4, kg);
+                            xl = true;
+                        }
+                        dot = f32x4{0.f, 0.f, 0.f, 0.f};
+                        float4 qv4[XS];
+#pragma unroll
+                        for (int t = 0; t < XS; t++)
+                            qv4[t] = zero_unless(qsh[qsh_index(qv ? qs : 0, 4 * t + kg, nf4)], qv);
+#pragma unroll
+                        for (int t = 0; t < XS; t++) mfma4(dot, qv4[t], xa[t]);
+                    } else {
+                        const int qrow = rec[qv ? qs : 0].q;
+                        dot = dot_tile<4 * KIT>(c.qd + (int64_t)qrow * c.d4 + 4 * kg, c.xd + row * c.d4 + 4 * kg, qv,
+                                                c.d4, kg);
+                    }
                     const float axr = c.ax[row];
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        if (pass[v]) {
+                        bool ps = (mv[v] >> lane) & 1ull;
+                        if (ps) {
                             const PairRec& R = rec[ct * 16 + 4 * kg + v];
-                            pass[v] = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                            ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
                         }
+                        const unsigned long long nm = __ballot(ps);
+                        if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
+                        cnt += __popcll(nm);
                     }
                 }
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const unsigned long long mv = __ballot(pass[v]);
-                    if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
-                    tot += __popcll(mv);
-                }
             }
-        }
-        nscan += 64ll * ng;
-        if (tot > 0) {
             wave_lds_fence();
+        }
+
+        // ---- exact-stage candidates into this wave's region ----
+        if (cnt > 0) {
             for (int ct = 0; ct < nct; ct++) {
                 for (int rt = 0; rt < 4; rt++) {
 #pragma unroll
@@ -1187,17 +1345,17 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     }
 }
 
-// Query-major passes.  One wave owns one query: it holds the query's result queue in LDS (loaded from
-// and written back to the global slots), sorts a chunk of candidates by (lower bound, row) and walks
-// them in that order exactly as Algorithm 2 treats a candidate - stage-1 bound, B-bit refinement,
-// Eq 7 re-check, exact distance, queue update - with the threshold tau of the queue updated after
-// every batch of 64.  Because the chunk is sorted by lower bound, the walk stops at the first
-// candidate whose bound reaches tau.
-// The seed pass runs it over each query's nearest list (probe rank 0), so that the first batched phase
-// starts from a finite threshold.
+// Seed pass: each query's nearest list (probe rank 0), one wave per query, before the batched phases,
+// so that the first batched phase starts from a finite threshold.  The wave holds the query's result
+// queue in LDS and treats the list in two deterministic rounds:
+//   1. the s = min(k, n') candidates with the smallest (stage-1 lower bound, row) among the first
+//      n' = min(n, kSeedMax) rows of the list (found by a bitwise search for the s-th smallest key);
+//   2. every other candidate of the list, in row order, 64 at a time,
+// each candidate going through the Algorithm 2 steps (stage-1 bound, B-bit refinement, Eq 7 re-check,
+// exact distance) against the queue's threshold tau, which is updated after every batch of 64.
+// Round 1 fills the queue with candidates the estimator ranks best, so round 2 prunes with a tight tau.
 
-enum { PASS_SEED = 0 };
-constexpr int kChunk = 512;
+constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
 
 // sort 64 keys held one per lane, ascending (bitonic network over shuffles)
 __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
@@ -1219,169 +1377,137 @@ struct QueryState {
     float tau;
 };
 
-// Sort keys/vals[0, P) ascending by key (one wave, LDS).
-__device__ void sort_chunk(unsigned long long* keys, int32_t* vals, int P, int lane) {
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = lane; i < P; i += 64) {
-                const int ixj = i ^ stride;
-                if (ixj > i) {
-                    const bool asc = (i & size) == 0;
-                    const unsigned long long a = keys[i], b = keys[ixj];
-                    if ((a > b) == asc) {
-                        keys[i] = b;
-                        keys[ixj] = a;
-                        const int32_t t = vals[i];
-                        vals[i] = vals[ixj];
-                        vals[ixj] = t;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Walk m sorted candidates (key = ord(lb) << 32 | row, val = pair record position).
+// One batch of at most 64 candidates (one per lane; `pass` = passed stage 1 against st.tau): B-bit
+// refinement, Eq 7 re-check, exact distances four at a time, then a merge of the new keys into the
+// sorted queue and the new tau.
 template <int WP>
-__device__ void walk_chunk(const ScanCtx& c, int q, float er, const unsigned long long* keys,
-                           const int32_t* vals, int m, QueryState& st, unsigned long long* nk, int lane,
-                           long long* n1, long long* next, long long* n2) {
-    int at = 0;
-    while (at < m) {
-        const float lb0 = ord_to_float((uint32_t)(keys[at] >> 32));
-        if (!(lb0 < st.tau)) break;  // every later candidate has a bound >= tau
-        int bs = m - at < 64 ? m - at : 64;
-        if (st.have < st.k && st.k - st.have < bs) bs = st.k - st.have;
-        bool pass = false;
-        int64_t row = 0;
-        int pos = 0;
-        if (lane < bs) {
-            const unsigned long long key = keys[at + lane];
-            row = (int64_t)(uint32_t)(key & 0xFFFFFFFFull);
-            pos = vals[at + lane];
-            pass = ord_to_float((uint32_t)(key >> 32)) < st.tau;
-        }
-        *n1 += __popcll(__ballot(pass));
-        if (pass && c.B > 1 && c.use_ext) {
-            const PairRec R = c.recs[pos];
-            const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
-            const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
-                                    c.fEB[row], c.fSX[row], R, U, c.bq);
-            pass = lb < st.tau;
-        }
-        *next += __popcll(__ballot(pass));
-        if (pass && c.stage2) {
-            const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-            pass = fmaf(-2.f, dot, c.ax[row] + c.qn2[q]) - er < st.tau;
-        }
-        unsigned long long m2 = __ballot(pass);
-        *n2 += __popcll(m2);
-        unsigned long long mine = kEmptyKey;
-        while (m2) {
-            const int src = take4(&m2, lane);
-            const int64_t rs = __shfl(row, src < 0 ? 0 : src);
-            const float dist = exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
-            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
-            for (int g = 0; g < 4; g++) {
-                const int sg = __shfl(src, g * 16);
-                const unsigned long long kg = __shfl(key, g * 16);
-                if (sg >= 0 && lane == sg) mine = kg;
-            }
-        }
-        // merge the new keys into the sorted queue
-        const unsigned long long sv = wave_sort64(mine, lane);
-        const int mnew = __popcll(__ballot(sv != kEmptyKey));
-        if (mnew > 0) {
-            nk[lane] = sv;
-            __syncthreads();
-            const unsigned long long* src = st.tk[st.cur];
-            unsigned long long* dst = st.tk[st.cur ^ 1];
-            for (int i = lane; i < st.have; i += 64) {  // existing key: rank among the new keys
-                const unsigned long long e = src[i];
-                int lo = 0, hi = mnew;
-                while (lo < hi) { int mid = (lo + hi) >> 1; if (nk[mid] < e) lo = mid + 1; else hi = mid; }
-                if (i + lo < st.k) dst[i + lo] = e;
-            }
-            if (lane < mnew) {
-                int lo = 0, hi = st.have;
-                while (lo < hi) { int mid = (lo + hi) >> 1; if (src[mid] < sv) lo = mid + 1; else hi = mid; }
-                if (lane + lo < st.k) dst[lane + lo] = sv;
-            }
-            __syncthreads();
-            st.cur ^= 1;
-            st.have = st.have + mnew < st.k ? st.have + mnew : st.k;
-            if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.tk[st.cur][st.k - 1] >> 32));
-        }
-        at += bs;
+__device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, int pos, bool pass, int64_t row,
+                           QueryState& st, unsigned long long* nk, int lane, long long* n1, long long* next,
+                           long long* n2) {
+    *n1 += __popcll(__ballot(pass));
+    if (pass && c.B > 1 && c.use_ext) {
+        const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
+        const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
+                                c.fEB[row], c.fSX[row], R, U, c.bq);
+        pass = lb < st.tau;
     }
+    *next += __popcll(__ballot(pass));
+    if (pass && c.stage2) {
+        const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+        pass = fmaf(-2.f, dot, c.ax[row] + R.qn2) - er < st.tau;
+    }
+    unsigned long long m2 = __ballot(pass);
+    *n2 += __popcll(m2);
+    if (!m2) return;
+    unsigned long long mine = kEmptyKey;
+    const int first = __ffsll((long long)m2) - 1;
+    while (m2) {
+        const int src = take4(&m2, lane);
+        const int64_t rs = __shfl(row, src < 0 ? first : src);
+        const float dist = exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
+        const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+        for (int g = 0; g < 4; g++) {
+            const int sg = __shfl(src, g * 16);
+            const unsigned long long kgv = __shfl(key, g * 16);
+            if (sg >= 0 && lane == sg) mine = kgv;
+        }
+    }
+    // merge the new keys into the sorted queue
+    const unsigned long long sv = wave_sort64(mine, lane);
+    const int mnew = __popcll(__ballot(sv != kEmptyKey));
+    nk[lane] = sv;
+    __syncthreads();
+    const unsigned long long* src = st.tk[st.cur];
+    unsigned long long* dst = st.tk[st.cur ^ 1];
+    for (int i = lane; i < st.have; i += 64) {  // existing key: rank among the new keys
+        const unsigned long long e = src[i];
+        int lo = 0, hi = mnew;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (nk[mid] < e) lo = mid + 1; else hi = mid; }
+        if (i + lo < st.k) dst[i + lo] = e;
+    }
+    if (lane < mnew) {
+        int lo = 0, hi = st.have;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (src[mid] < sv) lo = mid + 1; else hi = mid; }
+        if (lane + lo < st.k) dst[lane + lo] = sv;
+    }
+    __syncthreads();
+    st.cur ^= 1;
+    st.have = st.have + mnew < st.k ? st.have + mnew : st.k;
+    if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.tk[st.cur][st.k - 1] >> 32));
 }
 
 template <int WP, int BQT>
-__global__ __launch_bounds__(64) void k_query_pass(ScanCtx c, int mode, int r_lo, int r_hi) {
-    __shared__ unsigned long long keys[kChunk];
-    __shared__ int32_t vals[kChunk];
+__device__ __forceinline__ float seed_lb(const ScanCtx& c, int64_t row, const PairRec& R, const uint32_t* U) {
+    uint32_t cw[WP];
+    int pc = 0;
+#pragma unroll
+    for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
+    return stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
+}
+
+template <int WP, int BQT>
+__global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
-    extern __shared__ unsigned long long tk_dyn[];  // 2 x k_max keys
+    extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, then kSeedMax candidate keys
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
-    const int np = c.npq[q];
     QueryState st;
-    st.tk[0] = tk_dyn;
-    st.tk[1] = tk_dyn + c.k_max;
+    st.tk[0] = dyn;
+    st.tk[1] = dyn + c.k_max;
+    unsigned long long* keys = dyn + 2 * c.k_max;
     st.cur = 0;
     st.k = c.kq[q];
-    unsigned long long* slots = c.slots + c.slot_off[q];
-    int have = 0;
-    for (int i = lane; i < st.k; i += 64) {
-        const unsigned long long v = slots[i];
-        st.tk[0][i] = v;
-        have += v != kEmptyKey;
-    }
-    st.have = wave_sum_i(have);
-    __syncthreads();
-    st.tau = st.have == st.k ? __uint_as_float((uint32_t)(st.tk[0][st.k - 1] >> 32)) : INFINITY;
+    st.have = 0;
+    st.tau = INFINITY;
     const float er = c.er[q];
-    long long nscan = 0, n1 = 0, next = 0, n2 = 0;
-    {
-        const int rhi = r_hi < np ? r_hi : np;
-        for (int r = r_lo; r < rhi; r++) {
-            const int pos = c.pair_pos[c.pair_off[q] + r];
-            const PairRec R = c.recs[pos];
-            const uint32_t* U = c.planes + (int64_t)pos * (BQT > 0 ? BQT : c.bq) * WP;
-            const int j = R.list;
-            const int n = c.list_len[j];
-            const int64_t base = c.list_off[j];
-            for (int cs = 0; cs < n; cs += kChunk) {
-                const int m = n - cs < kChunk ? n - cs : kChunk;
-                int P = 64;
-                while (P < m) P <<= 1;
-                for (int i = lane; i < P; i += 64) {
-                    if (i < m) {
-                        const int64_t row = base + cs + i;
-                        uint32_t cw[WP];
-                        int pc = 0;
-#pragma unroll
-                        for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
-                        const float lb = stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
-                        keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)row;
-                        vals[i] = pos;
-                    } else {
-                        keys[i] = kEmptyKey;
-                        vals[i] = 0;
-                    }
-                }
-                __syncthreads();
-                nscan += m;
-                sort_chunk(keys, vals, P, lane);
-                walk_chunk<WP>(c, q, er, keys, vals, m, st, nk, lane, &n1, &next, &n2);
-                __syncthreads();
+    const int pos = c.pair_pos[c.pair_off[q]];
+    const PairRec R = c.recs[pos];
+    const uint32_t* U = c.planes + (int64_t)pos * (BQT > 0 ? BQT : c.bq) * WP;
+    const int j = R.list;
+    const int n = c.list_len[j];
+    const int64_t base = c.list_off[j];
+    const int nsel = n < kSeedMax ? n : kSeedMax;
+    long long n1 = 0, next = 0, n2 = 0;
+    // round 1: keys (ord(lb), row) of the first nsel rows, and the s-th smallest of them
+    for (int i = lane; i < nsel; i += 64) {
+        const float lb = seed_lb<WP, BQT>(c, base + i, R, U);
+        keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)i;
+    }
+    __syncthreads();
+    const int s = st.k < nsel ? st.k : nsel;
+    unsigned long long T = 0;  // the s-th smallest key: the largest value with fewer than s keys below it
+    for (int b = 63; b >= 0; b--) {
+        const unsigned long long t = T | (1ull << b);
+        int cnt = 0;
+        for (int i = lane; i < nsel; i += 64) cnt += keys[i] < t;
+        if (wave_sum_i(cnt) < s) T = t;
+    }
+    for (int i0 = 0; i0 < nsel; i0 += 64) {
+        const int i = i0 + lane;
+        const bool sel = i < nsel && keys[i] <= T;
+        if (!__ballot(sel)) continue;
+        seed_batch<WP>(c, q, er, R, pos, sel && ord_to_float((uint32_t)(keys[i] >> 32)) < st.tau, base + (sel ? i : 0),
+                       st, nk, lane, &n1, &next, &n2);
+    }
+    // round 2: every other candidate in row order
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        bool pass = false;
+        if (i < n) {
+            if (i < nsel) {
+                const unsigned long long key = keys[i];
+                pass = key > T && ord_to_float((uint32_t)(key >> 32)) < st.tau;
+            } else {
+                pass = seed_lb<WP, BQT>(c, base + i, R, U) < st.tau;
             }
         }
+        if (!__ballot(pass)) continue;
+        seed_batch<WP>(c, q, er, R, pos, pass, base + (pass ? i : 0), st, nk, lane, &n1, &next, &n2);
     }
+    unsigned long long* slots = c.slots + c.slot_off[q];
     for (int i = lane; i < st.k; i += 64) slots[i] = i < st.have ? st.tk[st.cur][i] : kEmptyKey;
     if (c.counters && lane == 0) {
-        atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)nscan);
+        atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)n);
         atomicAdd((unsigned long long*)&c.counters[5], (unsigned long long)n1);
         atomicAdd((unsigned long long*)&c.counters[6], (unsigned long long)next);
         atomicAdd((unsigned long long*)&c.counters[7], (unsigned long long)n2);
@@ -1438,7 +1564,7 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
-    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt, *claims;
     int4* desc;
     PairRec* recs;
     uint32_t* planes;
@@ -1495,6 +1621,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
     w.slots = c.take<unsigned long long>(total_slots);
     w.wcnt = c.take<int32_t>(4 * kMaxScanBlocks);
+    w.claims = c.take<int32_t>(kPhases * kClaimGroups);
     const int64_t cap = surv_capacity(ix, total_pairs);
     w.surv = c.take<int2>(cap);
     *used = c.used;
@@ -1523,22 +1650,21 @@ size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, 
 }
 
 template <int WP, int BQT>
-static void launch_phase_kernels(const ScanCtx& c, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
-    (void)which;
-    hipLaunchKernelGGL((k_query_pass<WP, BQT>), dim3((unsigned)nq), dim3(64),
-                       sizeof(unsigned long long) * 2 * c.k_max, s, c, mode, r_lo, r_hi);
+static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
+    hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64),
+                       sizeof(unsigned long long) * (2 * c.k_max + kSeedMax), s, c);
 }
 
 // Blocks of a persistent kernel that are resident at once on the current device (cached per device).
 template <class K>
-static int resident_blocks(K kernel, int threads, int slot) {
-    static int cache[16][16];
+static int resident_blocks(K kernel, int threads, int slot, size_t lds) {
+    static int cache[16][32];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
     int& v = cache[dev][slot];
     if (v == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess || per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
@@ -1547,13 +1673,30 @@ static int resident_blocks(K kernel, int threads, int slot) {
     return v;
 }
 
+template <int GT, int KIT>
+static bool scan_ql(const ScanCtx& c) {
+    return (KIT == 1 || KIT == 2) && c.d4 == 64 * KIT && c.stage2;
+}
+static size_t scan_lds(const ScanCtx& c, int GT) { return (size_t)4 * GT * c.d4 * sizeof(float); }
+
+template <int GT, int KIT>
+static void launch_scan_k(const ScanCtx& c, hipStream_t s, int blocks) {
+    if constexpr (KIT == 1 || KIT == 2) {
+        if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536) {
+            hipLaunchKernelGGL((k_scan<GT, KIT, true>), dim3(blocks), dim3(256), scan_lds(c, GT), s, c);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_scan<GT, KIT, false>), dim3(blocks), dim3(256), 0, s, c);
+}
+
 template <int GT>
 static void launch_scan_g(const ScanCtx& c, hipStream_t s, int blocks) {
     switch (c.KI) {
-        case 1: hipLaunchKernelGGL((k_scan<GT, 1>), dim3(blocks), dim3(256), 0, s, c); break;
-        case 2: hipLaunchKernelGGL((k_scan<GT, 2>), dim3(blocks), dim3(256), 0, s, c); break;
-        case 3: case 4: hipLaunchKernelGGL((k_scan<GT, 4>), dim3(blocks), dim3(256), 0, s, c); break;
-        default: hipLaunchKernelGGL((k_scan<GT, 0>), dim3(blocks), dim3(256), 0, s, c); break;
+        case 1: launch_scan_k<GT, 1>(c, s, blocks); break;
+        case 2: launch_scan_k<GT, 2>(c, s, blocks); break;
+        case 3: case 4: launch_scan_k<GT, 4>(c, s, blocks); break;
+        default: launch_scan_k<GT, 0>(c, s, blocks); break;
     }
 }
 
@@ -1564,39 +1707,44 @@ static void launch_scan(const ScanCtx& c, hipStream_t s, int blocks) {
 }
 
 // Blocks of the persistent scan grid: what is resident at once on the device, at most kMaxScanBlocks.
+template <int GT, int KIT>
+static int scan_grid_k(const ScanCtx& c, int slot) {
+    if constexpr (KIT == 1 || KIT == 2) {
+        if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536)
+            return std::min(resident_blocks(k_scan<GT, KIT, true>, 256, slot, scan_lds(c, GT)), kMaxScanBlocks);
+    }
+    return std::min(resident_blocks(k_scan<GT, KIT, false>, 256, slot + 1, 0), kMaxScanBlocks);
+}
 template <int GT>
 static int scan_grid_g(const ScanCtx& c, int slot) {
-    int b;
     switch (c.KI) {
-        case 1: b = resident_blocks(k_scan<GT, 1>, 256, slot + 0); break;
-        case 2: b = resident_blocks(k_scan<GT, 2>, 256, slot + 1); break;
-        case 3: case 4: b = resident_blocks(k_scan<GT, 4>, 256, slot + 2); break;
-        default: b = resident_blocks(k_scan<GT, 0>, 256, slot + 3); break;
+        case 1: return scan_grid_k<GT, 1>(c, slot + 0);
+        case 2: return scan_grid_k<GT, 2>(c, slot + 2);
+        case 3: case 4: return scan_grid_k<GT, 4>(c, slot + 4);
+        default: return scan_grid_k<GT, 0>(c, slot + 6);
     }
-    return std::min(b, kMaxScanBlocks);
 }
 static int scan_grid(const ScanCtx& c) {
     if (c.G <= 16) return scan_grid_g<16>(c, 0);
-    if (c.G <= 32) return scan_grid_g<32>(c, 4);
-    return scan_grid_g<64>(c, 8);
+    if (c.G <= 32) return scan_grid_g<32>(c, 8);
+    return scan_grid_g<64>(c, 16);
 }
 
 template <int WP>
-static void dispatch_bq(const ScanCtx& c, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
-    if (c.bq == 4) launch_phase_kernels<WP, 4>(c, which, mode, r_lo, r_hi, nq, s);
-    else launch_phase_kernels<WP, 0>(c, which, mode, r_lo, r_hi, nq, s);
+static void launch_seed_w(const ScanCtx& c, int64_t nq, hipStream_t s) {
+    if (c.bq == 4) launch_seed_t<WP, 4>(c, nq, s);
+    else launch_seed_t<WP, 0>(c, nq, s);
 }
 
-// query pass in `mode` over probe ranks [r_lo, r_hi)
-static void dispatch(const ScanCtx& c, int WP, int which, int mode, int r_lo, int r_hi, int64_t nq, hipStream_t s) {
-    switch (WP) {
-        case 1: dispatch_bq<1>(c, which, mode, r_lo, r_hi, nq, s); break;
-        case 2: dispatch_bq<2>(c, which, mode, r_lo, r_hi, nq, s); break;
-        case 4: dispatch_bq<4>(c, which, mode, r_lo, r_hi, nq, s); break;
-        case 8: dispatch_bq<8>(c, which, mode, r_lo, r_hi, nq, s); break;
-        case 16: dispatch_bq<16>(c, which, mode, r_lo, r_hi, nq, s); break;
-        case 32: dispatch_bq<32>(c, which, mode, r_lo, r_hi, nq, s); break;
-        default: dispatch_bq<48>(c, which, mode, r_lo, r_hi, nq, s); break;
+static void launch_seed(const ScanCtx& c, int64_t nq, hipStream_t s) {
+    switch (c.WP) {
+        case 1: launch_seed_w<1>(c, nq, s); break;
+        case 2: launch_seed_w<2>(c, nq, s); break;
+        case 4: launch_seed_w<4>(c, nq, s); break;
+        case 8: launch_seed_w<8>(c, nq, s); break;
+        case 16: launch_seed_w<16>(c, nq, s); break;
+        case 32: launch_seed_w<32>(c, nq, s); break;
+        default: launch_seed_w<48>(c, nq, s); break;
     }
 }
 
@@ -1649,6 +1797,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
+        HIP_TRY(launch_fill_i32(w.claims, 0, kPhases * kClaimGroups, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, P);
@@ -1680,7 +1829,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
     c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
-    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.counters = a.counters;
+    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.claims = w.claims; c.counters = a.counters;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
@@ -1691,7 +1840,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.rs = (int)(cap / (4ll * scan_blocks));
     {
         Timed t(tm, s, "seed");
-        dispatch(c, ix.WP, 1, PASS_SEED, 0, 1, nq, s);
+        launch_seed(c, nq, s);
         HIP_TRY(hipGetLastError());
     }
     for (int p = 1; p < kPhases; p++) {
