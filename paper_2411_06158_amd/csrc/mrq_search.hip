@@ -1348,7 +1348,7 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 // Seed pass: each query's nearest list (probe rank 0), one wave per query, before the batched phases,
 // so that the first batched phase starts from a finite threshold.  The wave holds the query's result
 // queue in LDS and treats the list in two deterministic rounds:
-//   1. the s = min(k, n') candidates with the smallest (stage-1 lower bound, row) among the first
+//   1. the s = min(max(k, 32), n') candidates with the smallest (stage-1 lower bound, row) among the first
 //      n' = min(n, kSeedMax) rows of the list (found by a bitwise search for the s-th smallest key);
 //   2. every other candidate of the list, in row order, 64 at a time,
 // each candidate going through the Algorithm 2 steps (stage-1 bound, B-bit refinement, Eq 7 re-check,
@@ -1356,6 +1356,7 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 // Round 1 fills the queue with candidates the estimator ranks best, so round 2 prunes with a tight tau.
 
 constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
+constexpr int kSeedFirst = 32;  // round 1 takes at least this many best-bound candidates
 
 // sort 64 keys held one per lane, ascending (bitonic network over shuffles)
 __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
@@ -1474,7 +1475,8 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)i;
     }
     __syncthreads();
-    const int s = st.k < nsel ? st.k : nsel;
+    const int s0 = st.k > kSeedFirst ? st.k : kSeedFirst;
+    const int s = s0 < nsel ? s0 : nsel;
     unsigned long long T = 0;  // the s-th smallest key: the largest value with fewer than s keys below it
     for (int b = 63; b >= 0; b--) {
         const unsigned long long t = T | (1ull << b);
