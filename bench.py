@@ -94,6 +94,12 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="skip GT/sweep/baselines (profiler runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: Poisson arrivals on the embedding-shaped index")
+    ap.add_argument("--rates", default="5000,10000,20000,50000", help="--serve: arrival rates (queries/s)")
+    ap.add_argument("--requests", type=int, default=20000, help="--serve: requests per rate")
+    ap.add_argument("--max-slots", type=int, default=512, help="--serve: queries per batch at most")
+    ap.add_argument("--mem-budget", type=float, default=4.0, help="--serve: device GiB for the batch slots")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -109,6 +115,9 @@ def main():
 
     torch.backends.cuda.matmul.allow_tf32 = False
     dev = torch.device("cuda:0")
+    if args.serve:
+        serve_main(args, np, torch, mrq, synth, dev)
+        return
     t0 = time.time()
     X, Q, spec = synth.workload(args.workload, N=args.N, nq=args.nq)
     N, D = X.shape
@@ -293,6 +302,78 @@ def main():
     }
     res.update(out_extra)
     print(json.dumps(res), flush=True)
+    ix.close()
+
+
+def serve_main(args, np, torch, mrq, synth, dev):
+    """Continuous batching under Poisson arrivals: the embedding-shaped index (N = 2,000,000, D = 1,536,
+    d_r = 256, 4-bit codes, nlist = 4,096), requests drawn from its 20,000 queries with k in {10, 50, 100}
+    and nprobe in {16, 32, 64}; per rate: achieved QPS, p50 / p99 latency (arrival to completion, as the
+    server measures it) and recall@10 of the answers against exact brute force."""
+    import ctypes as C
+    t0 = time.time()
+    X, Q, _ = synth.workload("openai2m")
+    log(f"data {X.shape[0]}x{X.shape[1]}, {Q.shape[0]} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    t1 = time.time()
+    ix = mrq.Index.build(Xd, d_r=256, bits=4, nlist=4096)
+    log(f"build {time.time() - t1:.1f}s, index {ix.device_bytes / 2**30:.2f} GiB")
+    gt = ground_truth(torch, Xd, torch.from_numpy(Q).to(dev), 10)
+    del Xd
+    torch.cuda.empty_cache()
+    L = mrq.lib()
+    rng = np.random.default_rng(5005)
+    out = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        R = args.requests
+        qi = rng.integers(0, Q.shape[0], R)
+        ks = rng.choice(np.array([10, 50, 100], np.int32), R)
+        nps = rng.choice(np.array([16, 32, 64], np.int32), R)
+        arrive = np.cumsum(rng.exponential(1.0 / rate, R))
+        srv = C.c_void_p()
+        budget = int(args.mem_budget * (1 << 30))
+        if L.mrq_server_create(ix._h, C.c_size_t(budget), args.max_slots, None, C.byref(srv)) != mrq.MRQ_OK:
+            raise mrq.MRQError(L.mrq_last_error().decode())
+        cap = 4096
+        rid = np.zeros(cap, np.uint64)
+        kk = np.zeros(cap, np.int32)
+        ids = np.zeros((cap, 100), np.int64)
+        dd = np.zeros((cap, 100), np.float32)
+        lat = np.zeros(cap, np.float64)
+        lat_all = np.zeros(R)
+        hit = np.zeros(R)
+        Qc = np.ascontiguousarray(Q)
+        late = 0.0
+        i, done = 0, 0
+        ts = time.perf_counter()
+        while done < R:
+            now = time.perf_counter() - ts
+            while i < R and arrive[i] <= now:
+                late = max(late, now - arrive[i])
+                if L.mrq_server_submit(srv, C.c_uint64(i), Qc[qi[i]].ctypes.data, int(ks[i]), int(nps[i])) != 0:
+                    raise mrq.MRQError(L.mrq_last_error().decode())
+                i += 1
+            got = L.mrq_server_poll(srv, rid.ctypes.data, kk.ctypes.data, ids.ctypes.data, dd.ctypes.data, 100, cap,
+                                    lat.ctypes.data)
+            for j in range(got):
+                r = int(rid[j])
+                lat_all[r] = lat[j]
+                hit[r] = len(set(ids[j, :10].tolist()) & set(gt[qi[r], :10].tolist())) / 10.0
+            done += got
+        span = time.perf_counter() - ts
+        L.mrq_server_destroy(srv)
+        row = {"rate": rate, "requests": R, "qps": round(R / span, 1),
+               "p50_ms": round(float(np.percentile(lat_all, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat_all, 99)), 3),
+               "recall_at_10": round(float(hit.mean()), 4), "max_submit_lag_ms": round(float(1e3 * late), 3)}
+        log(f"rate {rate:,.0f}: {row}")
+        out.append(row)
+    print(json.dumps({"metric": "serving latency under Poisson arrivals (continuous batching)",
+                      "unit": "ms", "n_gpus": 1, "data": "synthetic", "higher_is_better": False,
+                      "config": {"workload": "openai2m: N=2000000 D=1536 d_r=256 bits=4 nlist=4096, "
+                                             "k in {10,50,100}, nprobe in {16,32,64}",
+                                 "max_slots": args.max_slots, "mem_budget_gib": args.mem_budget},
+                      "rates": out}), flush=True)
     ix.close()
 
 
