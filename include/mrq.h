@@ -95,7 +95,7 @@ void mrq_search_opts_default(mrq_search_opts *o);
  * the exact stage, which computes ||x_p - q_p||^2 (= ||x - q||^2, Eq 1) over the axes in descending
  * variance order.
  *   X      N x D FP32, host or device, finite values only (checked: MRQ_EINVAL otherwise)
- *   d_r    in [2, D];  bits B in [1, 8];  nlist in [1, N]
+ *   d_r    in [2, min(D, 1536)];  bits B in [1, 8];  nlist in [1, min(N, 16384)]
  *   stream where the device work runs; the call synchronises it before returning
  *   out    receives a new index on MRQ_OK (free with mrq_free); untouched on failure
  */

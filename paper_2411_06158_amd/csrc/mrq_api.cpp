@@ -177,6 +177,7 @@ void check_args_build(const float* X, int64_t N, int32_t D, int32_t d, int32_t B
     if (d > 1536) throw Fail(MRQ_EINVAL, "d_r above 1536 is not supported");
     if (B < 1 || B > 8) throw Fail(MRQ_EINVAL, "bits must be in [1, 8]");
     if (nlist < 1 || nlist > N) throw Fail(MRQ_EINVAL, "nlist must be in [1, N]");
+    if (nlist > 16384) throw Fail(MRQ_EINVAL, "nlist above 16384 is not supported");
     if (N + 64 * (int64_t)nlist >= (int64_t)0x7fffffff)
         throw Fail(MRQ_EINVAL, "N + 64 nlist must be below 2^31 - 1 (rows are addressed with int32)");
 }

@@ -554,85 +554,95 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
 
 // ------------------------------------------------------------------------------------------------
 // Probe selection (Algorithm 2, centroid ranking): the np nearest lists by g_j = ||q_d - c_j||^2,
-// ties -> smaller list id, nearest first.  Radix select of the np-th smallest key, collection of the
-// keys below it plus the first equal keys in id order, then a bitonic sort of (g, j).
+// ties -> smaller list id, nearest first.  One block per query, each thread holding up to kSelV of the
+// query's nlist distances (non-negative, so their bit patterns order like the values): a bitwise search
+// for the np-th smallest pattern T (32 block-wide counting rounds), then every j with g_j <= T is
+// gathered in LDS and the gathered (g, j) keys are sorted; the first np are the probe lists.
 
+constexpr int kSelMaxList = 16384;          // nlist <= 256 x 64
+constexpr int kSelCap = kMaxProbe + 1024;   // gathered keys (np plus ties at T)
+
+__device__ __forceinline__ int block_sum256(int v, int* red) {
+    v = wave_sum_i(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+template <int V>
 __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int nlist,
                                                const int32_t* __restrict__ npq,
                                                const int64_t* __restrict__ pair_off,
                                                int32_t* __restrict__ pair_list,
                                                int32_t* __restrict__ pair_q) {
-    __shared__ uint32_t hist[256];
-    __shared__ unsigned long long sel[kMaxProbe];
-    __shared__ uint32_t s_prefix, s_kth;
-    __shared__ int s_nless, s_eqbase, s_wtot[4];
+    __shared__ unsigned long long sel[kSelCap];
+    __shared__ int red[4];
+    __shared__ int s_cnt, s_wt[4];
     const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const float* g = G + (int64_t)q * nlist;
     const int np = npq[q];
-    uint32_t prefix = 0, mask = 0, kth = (uint32_t)np;
-    for (int pass = 0; pass < 4; pass++) {
-        const int shift = 24 - 8 * pass;
-        hist[t] = 0;
-        __syncthreads();
-        for (int j = t; j < nlist; j += 256) {
-            uint32_t key = __float_as_uint(g[j]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        if (t == 0) {
-            uint32_t cum = 0;
-            for (int b = 0; b < 256; b++) {
-                if (cum + hist[b] >= kth) {
-                    s_prefix = prefix | ((uint32_t)b << shift);
-                    s_kth = kth - cum;
-                    break;
-                }
-                cum += hist[b];
-            }
-        }
-        __syncthreads();
-        prefix = s_prefix;
-        kth = s_kth;
-        mask |= 255u << shift;
-        __syncthreads();
+    uint32_t v[V];
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+        const int j = t + 256 * u;
+        v[u] = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
     }
-    const uint32_t T = prefix;
-    const int nless = np - (int)kth;
-    if (t == 0) { s_nless = 0; s_eqbase = 0; }
+    uint32_t T = 0;  // the np-th smallest pattern: the largest value with fewer than np patterns below it
+    for (int b = 31; b >= 0; b--) {
+        const uint32_t cand = T | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < V; u++) c += v[u] < cand;
+        if (block_sum256(c, red) < np) T = cand;
+    }
+    int cl = 0, ce = 0;
+#pragma unroll
+    for (int u = 0; u < V; u++) { cl += v[u] < T; ce += v[u] == T; }
+    const int nless = block_sum256(cl, red);  // < np
+    const int neq = block_sum256(ce, red);    // >= np - nless
+    if (t == 0) s_cnt = 0;
     __syncthreads();
-    for (int base = 0; base < nlist; base += 256) {
-        const int j = base + t;
-        const uint32_t key = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
-        const bool less = j < nlist && key < T;
-        const bool eq = j < nlist && key == T;
-        if (less) {
-            int p = atomicAdd(&s_nless, 1);
-            sel[p] = ((unsigned long long)key << 32) | (uint32_t)j;
+    const bool all_ties = nless + neq <= kSelCap;
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+        const int j = t + 256 * u;
+        if (j < nlist && (v[u] < T || (all_ties && v[u] == T))) {
+            const int at = atomicAdd(&s_cnt, 1);
+            sel[at] = ((unsigned long long)v[u] << 32) | (uint32_t)j;
         }
-        unsigned long long bm = __ballot(eq);
-        int before = __popcll(bm & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wtot[w] = __popcll(bm);
-        __syncthreads();
-        int woff = 0;
-        for (int i = 0; i < w; i++) woff += s_wtot[i];
-        const int r = s_eqbase + woff + before;
-        if (eq && r < (int)kth) sel[nless + r] = ((unsigned long long)key << 32) | (uint32_t)j;
-        __syncthreads();
-        if (t == 0) s_eqbase += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
-        __syncthreads();
     }
-    int P = 1;
-    while (P < np) P <<= 1;
-    for (int i = np + t; i < P; i += 256) sel[i] = kEmptyKey;
+    __syncthreads();
+    int m = s_cnt;
+    if (!all_ties) {  // more ties at T than fit: take the first np - nless of them in list order
+        int taken = 0;
+        for (int u = 0; u < V && taken < np - nless; u++) {
+            const int j = t + 256 * u;
+            const bool eq = j < nlist && v[u] == T;
+            const unsigned long long bm = __ballot(eq);
+            if (lane == 0) s_wt[w] = __popcll(bm);
+            __syncthreads();
+            int r = taken + __popcll(bm & ((1ull << lane) - 1ull));
+            for (int i = 0; i < w; i++) r += s_wt[i];
+            if (eq && r < np - nless) sel[nless + r] = ((unsigned long long)T << 32) | (uint32_t)j;
+            taken += s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+            __syncthreads();
+        }
+        m = np;
+    }
+    int P = 64;
+    while (P < m) P <<= 1;
+    for (int i = m + t; i < P; i += 256) sel[i] = kEmptyKey;
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = t; i < P; i += 256) {
-                int ixj = i ^ stride;
+                const int ixj = i ^ stride;
                 if (ixj > i) {
-                    bool asc = (i & size) == 0;
-                    unsigned long long a = sel[i], b = sel[ixj];
-                    if ((a > b) == asc) { sel[i] = b; sel[ixj] = a; }
+                    const bool asc = (i & size) == 0;
+                    const unsigned long long a = sel[i], bb = sel[ixj];
+                    if ((a > bb) == asc) { sel[i] = bb; sel[ixj] = a; }
                 }
             }
             __syncthreads();
@@ -643,6 +653,14 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         pair_list[o + r] = (int32_t)(sel[r] & 0xFFFFFFFFull);
         pair_q[o + r] = q;
     }
+}
+
+static void launch_select(const float* G, int nlist, const int32_t* npq, const int64_t* pair_off, int32_t* pair_list,
+                          int32_t* pair_q, int64_t nq, hipStream_t s) {
+    const dim3 grid((unsigned)nq), blk(256);
+    if (nlist <= 256 * 16) hipLaunchKernelGGL(k_select<16>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
+    else if (nlist <= 256 * 32) hipLaunchKernelGGL(k_select<32>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
+    else hipLaunchKernelGGL(k_select<64>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1350,9 +1368,10 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 // queue in LDS and treats the list in two deterministic rounds:
 //   1. the s = min(max(k, 32), n') candidates with the smallest (stage-1 lower bound, row) among the first
 //      n' = min(n, kSeedMax) rows of the list (found by a bitwise search for the s-th smallest key);
-//   2. every other candidate of the list, in row order, 64 at a time,
-// each candidate going through the Algorithm 2 steps (stage-1 bound, B-bit refinement, Eq 7 re-check,
-// exact distance) against the queue's threshold tau, which is updated after every batch of 64.
+//   2. every other candidate of the list whose bound is below tau, in row order,
+// gathered into dense batches of 64; each candidate of a batch goes through the Algorithm 2 steps
+// (stage-1 bound, B-bit refinement, Eq 7 re-check, exact distance) against the queue's threshold tau,
+// which is updated after every batch.
 // Round 1 fills the queue with candidates the estimator ranks best, so round 2 prunes with a tight tau.
 
 constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
@@ -1386,24 +1405,27 @@ __device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, 
                            QueryState& st, unsigned long long* nk, int lane, long long* n1, long long* next,
                            long long* n2) {
     *n1 += __popcll(__ballot(pass));
-    if (pass && c.B > 1 && c.use_ext) {
+    const bool open = st.tau == INFINITY;  // every test passes until the queue holds k results
+    if (pass && !open && c.B > 1 && c.use_ext) {
         const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
         const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
                                 c.fEB[row], c.fSX[row], R, U, c.bq);
         pass = lb < st.tau;
     }
     *next += __popcll(__ballot(pass));
-    if (pass && c.stage2) {
+    if (pass && !open && c.stage2) {
         const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
         pass = fmaf(-2.f, dot, c.ax[row] + R.qn2) - er < st.tau;
     }
-    unsigned long long m2 = __ballot(pass);
+    const unsigned long long m2 = __ballot(pass);
     *n2 += __popcll(m2);
     if (!m2) return;
+    // exact distances, four candidates at a time (16 lanes each)
     unsigned long long mine = kEmptyKey;
+    unsigned long long mm = m2;
     const int first = __ffsll((long long)m2) - 1;
-    while (m2) {
-        const int src = take4(&m2, lane);
+    while (mm) {
+        const int src = take4(&mm, lane);
         const int64_t rs = __shfl(row, src < 0 ? first : src);
         const float dist = exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
@@ -1449,6 +1471,8 @@ __device__ __forceinline__ float seed_lb(const ScanCtx& c, int64_t row, const Pa
 template <int WP, int BQT>
 __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
+    __shared__ int32_t pend_row[128];
+    __shared__ float pend_lb[128];
     extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, then kSeedMax candidate keys
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
@@ -1484,28 +1508,60 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         for (int i = lane; i < nsel; i += 64) cnt += keys[i] < t;
         if (wave_sum_i(cnt) < s) T = t;
     }
+    // candidates of a round are gathered, in row order, into dense batches of 64 (LDS list `pend`);
+    // a batch re-checks each bound against the queue's current tau
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int np = 0;
+    auto flush = [&](int cnt) {
+        const bool in = lane < cnt;
+        const int i = in ? pend_row[lane] : 0;
+        const float lb = in ? pend_lb[lane] : INFINITY;
+        seed_batch<WP>(c, q, er, R, pos, in && lb < st.tau, base + i, st, nk, lane, &n1, &next, &n2);
+        const int rest = np - cnt;  // move the remaining entries to the front
+        int r_row = 0;
+        float r_lb = 0.f;
+        if (lane < rest) { r_row = pend_row[cnt + lane]; r_lb = pend_lb[cnt + lane]; }
+        __syncthreads();
+        if (lane < rest) { pend_row[lane] = r_row; pend_lb[lane] = r_lb; }
+        __syncthreads();
+        np = rest;
+    };
+    auto append = [&](bool take, int i, float lb) {
+        const unsigned long long m = __ballot(take);
+        if (take) {
+            const int at = np + __popcll(m & lt);
+            pend_row[at] = i;
+            pend_lb[at] = lb;
+        }
+        np += __popcll(m);
+        __syncthreads();
+        if (np >= 64) flush(64);
+    };
+    // round 1: the selected candidates
     for (int i0 = 0; i0 < nsel; i0 += 64) {
         const int i = i0 + lane;
-        const bool sel = i < nsel && keys[i] <= T;
-        if (!__ballot(sel)) continue;
-        seed_batch<WP>(c, q, er, R, pos, sel && ord_to_float((uint32_t)(keys[i] >> 32)) < st.tau, base + (sel ? i : 0),
-                       st, nk, lane, &n1, &next, &n2);
+        const unsigned long long key = i < nsel ? keys[i] : ~0ull;
+        append(i < nsel && key <= T, i, ord_to_float((uint32_t)(key >> 32)));
     }
+    if (np > 0) flush(np);
     // round 2: every other candidate in row order
     for (int i0 = 0; i0 < n; i0 += 64) {
         const int i = i0 + lane;
-        bool pass = false;
+        bool take = false;
+        float lb = INFINITY;
         if (i < n) {
             if (i < nsel) {
                 const unsigned long long key = keys[i];
-                pass = key > T && ord_to_float((uint32_t)(key >> 32)) < st.tau;
+                lb = ord_to_float((uint32_t)(key >> 32));
+                take = key > T && lb < st.tau;
             } else {
-                pass = seed_lb<WP, BQT>(c, base + i, R, U) < st.tau;
+                lb = seed_lb<WP, BQT>(c, base + i, R, U);
+                take = lb < st.tau;
             }
         }
-        if (!__ballot(pass)) continue;
-        seed_batch<WP>(c, q, er, R, pos, pass, base + (pass ? i : 0), st, nk, lane, &n1, &next, &n2);
+        append(take, i, lb);
     }
+    if (np > 0) flush(np);
     unsigned long long* slots = c.slots + c.slot_off[q];
     for (int i = lane; i < st.k; i += 64) slots[i] = i < st.have ? st.tk[st.cur][i] : kEmptyKey;
     if (c.counters && lane == 0) {
@@ -1791,8 +1847,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "probe");
         HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr,
                                     0, 0, s));
-        hipLaunchKernelGGL(k_select, dim3((unsigned)nq), dim3(256), 0, s, w.G, nlist, a.npq, a.pair_off,
-                           w.pair_list, w.pair_q);
+        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, s);
         HIP_TRY(hipGetLastError());
     }
     {   // per-pair query codes, grouped by (phase, list)

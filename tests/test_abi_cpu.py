@@ -52,6 +52,7 @@ def _build(X, N, D, d, B, nlist):
 @pytest.mark.parametrize("N,D,d,B,nlist,msg", [
     (0, 8, 4, 1, 1, "N"), (100, 1, 1, 1, 1, "D"), (100, 8, 9, 1, 4, "d_r"), (100, 8, 1, 1, 4, "d_r"),
     (100, 8, 4, 0, 4, "bits"), (100, 8, 4, 9, 4, "bits"), (100, 8, 4, 1, 0, "nlist"), (100, 8, 4, 1, 101, "nlist"),
+    (20000, 8, 4, 1, 16385, "nlist"),
 ])
 def test_build_rejects_bad_arguments(N, D, d, B, nlist, msg):
     X = np.zeros((max(N, 1), D), np.float32)
