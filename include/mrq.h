@@ -95,7 +95,8 @@ void mrq_search_opts_default(mrq_search_opts *o);
  * the exact stage, which computes ||x_p - q_p||^2 (= ||x - q||^2, Eq 1) over the axes in descending
  * variance order.
  *   X      N x D FP32, host or device, finite values only (checked: MRQ_EINVAL otherwise)
- *   d_r    in [2, min(D, 1536)];  bits B in [1, 8];  nlist in [1, min(N, 16384)]
+ *   d_r    in [2, min(D, 1536)], or 0 for the Eq 8 choice (mrq_choose_dr on the data's eigenvalues);
+ *          bits B in [1, 8];  nlist in [1, min(N, 16384)]
  *   stream where the device work runs; the call synchronises it before returning
  *   out    receives a new index on MRQ_OK (free with mrq_free); untouched on failure
  */
@@ -116,6 +117,16 @@ mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_
                       int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
 
 /*
+ * mrq_tune — autotuner of the scan schedule: runs mrq_search on Q (nq queries, host or device) with each
+ * query-group size of the scan work items (16, 32, 64 queries per 64-vector block), times each on
+ * `stream` with HIP events, and makes the fastest the index's default (used when
+ * mrq_search_opts.group is 0).  Results do not depend on the schedule.  Synchronous; `group` (may be
+ * NULL) receives the choice.  The index must not be in use by another call meanwhile.
+ */
+mrq_status mrq_tune(mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe, mrq_stream stream,
+                    int32_t *group);
+
+/*
  * mrq_search_mixed — as mrq_search, with a per-query k[i] and nprobe[i] (host or device int32
  * arrays of nq entries) in one launch.  Results of query i are written at ids + out_off[i] and
  * dists + out_off[i] (k[i] entries); out_off is an int64 array of nq entries (host or device).
@@ -123,6 +134,15 @@ mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_
 mrq_status mrq_search_mixed(const mrq_index *index, const float *Q, int64_t nq, const int32_t *k,
                             const int32_t *nprobe, const int64_t *out_off, int64_t *ids, float *dists,
                             const mrq_search_opts *opts, mrq_stream stream);
+
+/*
+ * mrq_choose_dr — the rule of Eq 8 (Section 5.3): the smallest power of two d = 2^i with d >= 128 whose
+ * leading eigenvalues hold at least 80 % of the total variance, sum_{j<d} lambda_j >= 0.8 sum_j lambda_j
+ * (lambda: the D eigenvalues in descending order, host FP64).  A choice reaching D returns D; above
+ * 1536 dimensions (the largest supported d_r) it returns 1536 when D <= 1536, else 1024.  Host only;
+ * returns -1 for a NULL pointer or D < 2.
+ */
+int32_t mrq_choose_dr(const double *lambda, int32_t D);
 
 /* Index shape: any pointer may be NULL. */
 mrq_status mrq_index_info(const mrq_index *index, int64_t *N, int32_t *D, int32_t *d_r, int32_t *bits,

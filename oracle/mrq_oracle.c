@@ -30,6 +30,8 @@
  *       centroid of each x_d under the stored centroids
  *   R16 P_r: Haar orthogonal matrix from modified Gram-Schmidt (twice) of a seeded Gaussian matrix
  *   R17 ||x_r||^2 of an imported index is ||x - mu||^2 - ||x_d||^2 (P_p orthogonal; Eq 1)
+ *   R18 the variances lambda_i of Eq 6 are non-negative: an eigenvalue that round-off puts below zero
+ *       (rank-deficient data) counts as 0
  *
  * Parity unpinned: the absolute constant c0 of Eq 5 (the paper gives none), hence the exact failure
  * probability of eps_b; recall figures on synthetic data (no paper value applies).
@@ -637,7 +639,8 @@ static void query_state(const orc_index *ix, const float *q, double m, qstate *s
         for (int i = 0; i < D; i++) v += ix->Pp[(size_t)r * D + i] * qc[i];
         s->qp[r] = v;
         s->qn2 += v * v;
-        if (r >= d) { s->Tq += v * v; var += ix->lam[r] * v * v; }
+        /* Eq 6: sigma_i^2 = lambda_i is a variance; round-off below zero counts as 0 (R18) */
+        if (r >= d) { s->Tq += v * v; var += (ix->lam[r] > 0.0 ? ix->lam[r] : 0.0) * v * v; }
     }
     s->sq = sqrt(var);
     s->er = 2.0 * m * s->sq;

@@ -22,7 +22,7 @@ EXPORTED = [
     "mrq_build_opts_default", "mrq_search_opts_default", "mrq_build", "mrq_search", "mrq_search_mixed",
     "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
     "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
-    "mrq_server_destroy",
+    "mrq_server_destroy", "mrq_choose_dr", "mrq_tune",
 ]
 
 
@@ -77,6 +77,9 @@ def lib() -> C.CDLL:
             L.mrq_server_drain.argtypes = [P, I64]
             L.mrq_server_destroy.argtypes = [P]
             L.mrq_server_destroy.restype = None
+        L.mrq_choose_dr.argtypes = [P, I32]
+        L.mrq_choose_dr.restype = I32
+        L.mrq_tune.argtypes = [P, P, I64, I32, I32, P, P]
         _lib = L
     return _lib
 
@@ -124,6 +127,12 @@ def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=Tr
     o.exact_cap = int(exact_cap)
     o.counters = _ptr(counters) if counters is not None else None
     return o
+
+
+def choose_dr(lam) -> int:
+    """Eq 8: the projection dimension for eigenvalues `lam` (descending)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    return int(lib().mrq_choose_dr(lam.ctypes.data, len(lam)))
 
 
 class Index:
@@ -193,6 +202,12 @@ class Index:
         _check(lib().mrq_search_mixed(self._h, _ptr(Q), len(k), _ptr(k), _ptr(nprobe), _ptr(off), _ptr(ids),
                                       _ptr(dists), C.byref(o), _stream(stream)))
         return ids, dists, off
+
+    def tune(self, Q, k: int, nprobe: int, stream=None) -> int:
+        """Time the scan schedules on queries Q and keep the fastest as this index's default."""
+        g = C.c_int32(0)
+        _check(lib().mrq_tune(self._h, _ptr(Q), int(Q.shape[0]), k, nprobe, _stream(stream), C.byref(g)))
+        return g.value
 
     def timing_enable(self, on: bool = True, reset: bool = True):
         _check(lib().mrq_timing_enable(self._h, int(on), int(reset)))

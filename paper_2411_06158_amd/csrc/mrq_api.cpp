@@ -173,7 +173,7 @@ void check_args_build(const float* X, int64_t N, int32_t D, int32_t d, int32_t B
     if (!X) throw Fail(MRQ_EINVAL, "X is NULL");
     if (N < 1 || N >= (int64_t)0x7fffffff) throw Fail(MRQ_EINVAL, "N must be in [1, 2^31 - 1)");
     if (D < 2) throw Fail(MRQ_EINVAL, "D must be >= 2");
-    if (d < 2 || d > D) throw Fail(MRQ_EINVAL, "d_r must be in [2, D]");
+    if (d != 0 && (d < 2 || d > D)) throw Fail(MRQ_EINVAL, "d_r must be 0 (automatic) or in [2, D]");
     if (d > 1536) throw Fail(MRQ_EINVAL, "d_r above 1536 is not supported");
     if (B < 1 || B > 8) throw Fail(MRQ_EINVAL, "bits must be in [1, 8]");
     if (nlist < 1 || nlist > N) throw Fail(MRQ_EINVAL, "nlist must be in [1, N]");
@@ -239,12 +239,8 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
                               const mrq_build_opts& o, hipStream_t s) {
     std::unique_ptr<mrq_index> ix(new mrq_index());
     hip_check(hipGetDevice(&ix->device), "hipGetDevice");
-    ix->N = N; ix->D = D; ix->d = d; ix->B = B; ix->nlist = nlist;
-    ix->W = (d + 31) / 32;
-    ix->WP = padded_words(d);
-    ix->d4 = (d + 3) & ~3;
+    ix->N = N; ix->D = D; ix->B = B; ix->nlist = nlist;
     ix->D4 = (D + 3) & ~3;
-    const int d4 = ix->d4;
 
     // input on the device
     const float* Xd = X;
@@ -280,7 +276,14 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     }
     std::vector<double> lam(D), V((size_t)D * D);
     eigh_host(Sh.data(), D, lam.data(), V.data());
+    for (double& l : lam) l = l > 0.0 ? l : 0.0;  // variances (Eq 6): round-off below zero is 0
     ix->lam64 = lam;
+    if (d == 0) d = mrq_choose_dr(lam.data(), D);  // Eq 8
+    ix->d = d;
+    ix->W = (d + 31) / 32;
+    ix->WP = padded_words(d);
+    ix->d4 = (d + 3) & ~3;
+    const int d4 = ix->d4;
     {
         std::vector<float> Pp32(V.begin(), V.end()), mu32(muh.begin(), muh.end());
         std::vector<float> lt(std::max(D - d, 1), 0.f);
@@ -798,6 +801,19 @@ void mrq_build_opts_default(mrq_build_opts* o) {
     o->kmeans_iters = 25;
 }
 
+int32_t mrq_choose_dr(const double* lambda, int32_t D) {
+    if (!lambda || D < 2) return -1;
+    double tot = 0.0;
+    for (int j = 0; j < D; j++) tot += lambda[j];
+    for (int dd = 128;; dd *= 2) {
+        if (dd >= D) return D <= 1536 ? D : 1024;
+        if (dd > 1536) return 1024;
+        double part = 0.0;
+        for (int j = 0; j < dd; j++) part += lambda[j];
+        if (part >= 0.8 * tot) return dd;
+    }
+}
+
 void mrq_search_opts_default(mrq_search_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -829,6 +845,45 @@ mrq_status mrq_search(const mrq_index* index, const float* Q, int64_t nq, int32_
     return guarded([&]() {
         return run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts,
                           (hipStream_t)stream);
+    });
+}
+
+mrq_status mrq_tune(mrq_index* index, const float* Q, int64_t nq, int32_t k, int32_t nprobe, mrq_stream stream,
+                    int32_t* group) {
+    return guarded([&]() {
+        if (!index || !Q) throw Fail(MRQ_EINVAL, "index and Q must not be NULL");
+        if (nq < 1 || k < 1 || k > kMaxK || nprobe < 1) throw Fail(MRQ_EINVAL, "bad nq, k or nprobe");
+        hipStream_t s = (hipStream_t)stream;
+        DevTemp ids(sizeof(int64_t) * (size_t)nq * k), dd(sizeof(float) * (size_t)nq * k);
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        const int cands[3] = {16, 32, 64};
+        int best = index->group_default;
+        float best_ms = 0.f;
+        mrq_search_opts o;
+        mrq_search_opts_default(&o);
+        mrq_status st = MRQ_OK;
+        for (int g : cands) {
+            o.group = g;
+            for (int rep = 0; rep < 2 && st == MRQ_OK; rep++) {  // the first run warms the workspace
+                if (rep == 1) hip_check(hipEventRecord(e0, s), "event");
+                st = run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids.as<int64_t>(),
+                                dd.as<float>(), &o, s);
+                if (rep == 1) hip_check(hipEventRecord(e1, s), "event");
+            }
+            if (st != MRQ_OK) break;
+            hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (g == cands[0] || ms < best_ms) { best_ms = ms; best = g; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != MRQ_OK) return st;
+        index->group_default = best;
+        if (group) *group = best;
+        return MRQ_OK;
     });
 }
 

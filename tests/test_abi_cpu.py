@@ -86,3 +86,22 @@ def test_load_rejects_missing_and_corrupt_files():
         assert "MRQS0002" in mrq.lib().mrq_last_error().decode()
     finally:
         os.unlink(path)
+
+
+@pytest.mark.parametrize("spectrum,D,want", [
+    ("power1.2", 960, 128),     # 128 leading axes of i^-1.2 over 960 hold 85.5 % of the variance
+    ("flat", 960, 960),         # 80 % needs 768 axes: the next power of two passes D, so D
+    ("flat", 100, 100),         # fewer than 128 dimensions: all of them
+    ("power0.5", 1536, 1024),   # i^-0.5 over 1536: 512 axes hold 57 %, 1024 hold 81 %
+    ("flat", 2048, 1024),       # 80 % needs 2048 > 1536, the largest supported power of two
+    ("head", 1536, 256),        # 90 % in the top 200 axes
+])
+def test_choose_dr_follows_eq8(spectrum, D, want):
+    i = np.arange(1, D + 1, dtype=np.float64)
+    lam = {"power1.2": i ** -1.2, "flat": np.ones(D), "power0.5": i ** -0.5,
+           "head": np.where(i <= 200, 0.9 / 200, 0.1 / (D - 200))}[spectrum]
+    assert mrq.choose_dr(lam) == want
+
+
+def test_choose_dr_rejects_bad_input():
+    assert mrq.lib().mrq_choose_dr(None, 10) == -1

@@ -277,3 +277,34 @@ def test_eight_bit_codes_and_query_levels():
     for i in (1, 2):
         r4, r8 = cnt[4][i] / cnt[4][0], cnt[8][i] / cnt[8][0]
         assert 0.5 * r4 <= r8 <= 1.5 * r4 + 1e-3, (i, r4, r8)
+
+
+def test_automatic_dr_follows_eq8():
+    """d_r = 0 builds with the Eq 8 choice on the data's own eigenvalues."""
+    print("\n[gpu] build N=8000 D=256 d_r=auto B=1 nlist=16", flush=True)
+    X, Q, _ = synth.workload("small", N=8000, nq=20, cache=False)
+    X = np.ascontiguousarray(np.concatenate([X, X[:, ::-1] * 0.5], axis=1))  # D = 256
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=0, bits=1, nlist=16)
+    try:
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "ix.mrqx")
+            ix.export(path)
+            orc = oracle.Index.load_export(path)
+            lam = orc.get("lam")
+        assert ix.d == mrq.choose_dr(lam)
+        assert 128 <= ix.d <= 256
+        q = np.ascontiguousarray(np.concatenate([Q, Q[:, ::-1] * 0.5], axis=1))
+        ids, _ = ix.search(q, 10, 4)
+        assert np.all(ids[:, 0] >= 0)
+    finally:
+        ix.close()
+
+
+def test_tuner_picks_a_schedule_and_keeps_results(small):
+    ix, Q = small["ix"], small["Q"]
+    a_ids, a_d = ix.search(Q, 10, 16)
+    g = ix.tune(Q, 10, 16)
+    assert g in (16, 32, 64)
+    b_ids, b_d = ix.search(Q, 10, 16)
+    assert np.array_equal(a_ids, b_ids)
+    assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))

@@ -385,3 +385,18 @@ def test_eq4_eq5_stage1_values_from_definitions(orc, B):
                 assert np.allclose(cand["dis" + key], dis, rtol=1e-9, atol=1e-9)
                 assert np.allclose(cand["eb" + key], eb, rtol=1e-8, atol=1e-9)
                 assert np.allclose(cand["lb" + key], lb, rtol=1e-9, atol=1e-9)
+
+
+def test_rank_deficient_data_keeps_finite_bounds(orc):
+    """Duplicated dimensions make trailing eigenvalues zero up to round-off, possibly below zero; the
+    residual radius of Eq 6 must stay finite, so the search still returns k results that equal the
+    exact top-k of the probed lists (brute force over those lists)."""
+    X, Q, _ = small_data(N=600, D=16, cluster_dims=4)
+    X = np.ascontiguousarray(np.concatenate([X, X], axis=1))  # D = 32, rank 16
+    Q = np.ascontiguousarray(np.concatenate([Q, Q], axis=1))
+    ix = orc.Index.build(X, d=8, B=1, nlist=6)
+    for q in Q[:5]:
+        ids, dd = ix.search(q, 10, 3, mode=orc.ALG2)
+        assert np.all(ids >= 0) and np.all(np.isfinite(dd))
+        ex, exd = ix.search(q, 10, 3, mode=orc.EXACT_IVF)
+        np.testing.assert_allclose(dd, exd, rtol=1e-12)
