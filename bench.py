@@ -29,8 +29,10 @@ def log(*a):
 
 def ground_truth(torch, Xd, Qd, k, extra=32, chunk=1024):
     """Exact top-k (ties -> smaller id): FP32 distance tiles on the GPU pick k + extra candidates,
-    which are re-scored in FP64."""
+    which are re-scored in FP64.  A distance tile stays within 2^28 floats (1 GiB): tiles above 4 GiB
+    (107 x 10M and larger) have returned wrong top-k rows on this stack."""
     xn = (Xd * Xd).sum(1)
+    chunk = max(1, min(chunk, (1 << 28) // Xd.shape[0]))
     out = []
     for s in range(0, Qd.shape[0], chunk):
         q = Qd[s:s + chunk]
@@ -170,6 +172,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # the autotuner picks the scan schedule (query-group size) on this batch; results do not depend on it
+    group = ix.tune(Qd, k, chosen)
+    log(f"autotuned query group: {group}")
+
     # timed region: W warm-up steps, then K steps with per-kernel HIP events and device counters
     for _ in range(args.warmup):
         run(chosen)
@@ -287,6 +293,7 @@ def main():
                                f"bits={args.bits} k={k}",
                    "N": N, "D": D, "nq": nq, "nlist": args.nlist, "d_r": args.d, "bits": args.bits, "k": k,
                    "nprobe": chosen, "recall_at_10": None if rec_at is None else round(rec_at, 4),
+                   "query_group": group,
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
