@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline time budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="skip GT/sweep/baselines (profiler runs)")
+    ap.add_argument("--group", type=int, default=0,
+                    help="queries per scan work item (16, 32 or 64; 0 = autotune on the batch before timing)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -138,7 +140,7 @@ def main():
     d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
 
     def run(nprobe, counters=None, mode=mrq.MRQ_BATCHED, Qs=None, ib=None, db=None):
-        o = mrq.search_opts(mode=mode, counters=counters)
+        o = mrq.search_opts(mode=mode, counters=counters, group=args.group)
         Qs = Qd if Qs is None else Qs
         return ix.search(Qs, k, nprobe, ids=ids_buf if ib is None else ib, dists=d_buf if db is None else db,
                          opts=o)
@@ -173,8 +175,12 @@ def main():
         del src, dst
 
     # the autotuner picks the scan schedule (query-group size) on this batch; results do not depend on it
-    group = ix.tune(Qd, k, chosen)
-    log(f"autotuned query group: {group}")
+    if args.group:
+        group = args.group
+        log(f"query group: {group}")
+    else:
+        group = ix.tune(Qd, k, chosen)
+        log(f"autotuned query group: {group}")
 
     # timed region: W warm-up steps, then K steps with per-kernel HIP events and device counters
     for _ in range(args.warmup):

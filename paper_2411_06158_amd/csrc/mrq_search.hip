@@ -1066,15 +1066,25 @@ constexpr int kClaimGroups = 64;
 __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slot * nf4 + (f4 ^ (slot & 15)); }
 
 // One phase of the batched scan.  KIT > 0: d <= 64 KIT (stage-1 operands of an item loaded up front);
-// KIT = 0: any d.  QL: the item's q_d rows are staged in LDS for stage 2 (d4 = 64 KIT).
+// KIT = 0: any d.  QL (d4 = 64 KIT, KIT <= 2): operands reach LDS by direct global-to-LDS loads ahead of
+// their use (the next item's stage-1 operands during the current item, the current item's q_d rows at its
+// start) and the x_d slices of a row tile are loaded while the previous tile is multiplied.
 template <int GT, int KIT, bool QL>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
     constexpr int XS = QL && KIT > 0 ? 4 * KIT : 1;  // x_d slices of a row tile held in registers
+    static_assert(!QL || (KIT == 1 || KIT == 2), "QL: one direct load per lane covers an item's code block");
+    // QL staging area of the next item's stage-1 operands, per wave: the 64-row code block (64 x WP <= 2 KA
+    // words), the A, F, E factors of the block, the query levels of up to GT pairs (KP = 64 KA bytes each)
+    constexpr int PF_CODE = QL ? 512 * KA : 16;
+    constexpr int PF_FAC = QL ? 768 : 16;
+    constexpr int PF_LEV = QL ? GT * 64 * KA : 16;
     __shared__ PairRec sh_rec[4][GT];
     __shared__ unsigned long long sh_m[4][NCT * 16];  // surviving entries per (column tile, row tile, v)
+    __shared__ uint4 sh_pf[4][(PF_CODE + PF_FAC + PF_LEV) / 16];
     extern __shared__ float4 qsh_dyn[];               // QL: 4 x GT rows of d4 / 4 float4
+    typedef __attribute__((address_space(3))) void* lds_ptr;
     const int lane = lane_id();
     const int wv = threadIdx.x >> 6;
     const int li = lane & 15, kg = lane >> 4;
@@ -1089,6 +1099,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     const int WP = c.WP;
     PairRec* rec = sh_rec[wv];
     unsigned long long* msk = sh_m[wv];
+    uint4* pf = sh_pf[wv];
     float4* qsh = qsh_dyn + (QL ? wv * GT * nf4 : 0);
     const unsigned long long lt = (1ull << lane) - 1ull;
     // this wave's region of the exact-stage buffer
@@ -1097,23 +1108,44 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     int nreg = 0;  // candidates this wave produced (may exceed rs; the rest is finished in place)
     long long nscan = 0, n1 = 0, next = 0;
     // Items are dealt to the waves round-robin (neighbouring waves take neighbouring blocks of a list).
-    // The descriptor and the pair records of the next item are requested while the current one is
-    // scanned; the records travel in plain registers (three float4 per lane) until they are stored.
+    // Descriptors are read two items ahead; the pair records of the next item travel in registers (three
+    // float4 per lane) until they are stored.
     const int nwaves = gridDim.x * 4;
-    int4 dnext = make_int4(0, 0, 1, 0);
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    auto fetch = [&](int item) {
-        dnext = const_load4(c.desc + base_item + item);
-        const float4* rp = reinterpret_cast<const float4*>(c.recs + dnext.y + (lane < dnext.z ? lane : 0));
+    auto fetch_recs = [&](const int4 d, float4& r0, float4& r1, float4& r2) {
+        const float4* rp = reinterpret_cast<const float4*>(c.recs + d.y + (lane < d.z ? lane : 0));
         r0 = rp[0];
         r1 = rp[1];
         r2 = rp[2];
     };
-    if (wid < total) fetch(wid);
+    // QL: the stage-1 operands of item d into this wave's staging area (rows d.x .. d.x + 63, pairs d.y ..
+    // d.y + d.z - 1; every source is 16-byte aligned)
+    auto stage_operands = [&](const int4 d) {
+        if (lane < 16 * WP)
+            __builtin_amdgcn_global_load_lds((const void*)(reinterpret_cast<const uint4*>(c.code + (int64_t)d.x * WP) + lane),
+                                             (lds_ptr)pf, 16, 0, 0);
+        if (lane < 48) {
+            const float* fb = lane < 16 ? c.fA : (lane < 32 ? c.fF : c.fE);
+            __builtin_amdgcn_global_load_lds((const void*)(reinterpret_cast<const uint4*>(fb + d.x) + (lane & 15)),
+                                             (lds_ptr)(pf + PF_CODE / 16), 16, 0, 0);
+        }
+        const int nlev = d.z * (c.KP >> 4);
+        const uint4* ls = reinterpret_cast<const uint4*>(c.qu8 + (int64_t)d.y * c.KP);
+        for (int e0 = 0; e0 < nlev; e0 += 64)
+            if (e0 + lane < nlev)
+                __builtin_amdgcn_global_load_lds((const void*)(ls + e0 + lane),
+                                                 (lds_ptr)(pf + (PF_CODE + PF_FAC) / 16 + e0), 16, 0, 0);
+    };
+    int4 dcur = make_int4(0, 0, 1, 0), dnext = dcur;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    if (wid < total) {
+        dcur = const_load4(c.desc + base_item + wid);
+        fetch_recs(dcur, r0, r1, r2);
+        if (QL) stage_operands(dcur);
+        if (wid + nwaves < total) dnext = const_load4(c.desc + base_item + wid + nwaves);
+    }
     for (int it = wid; it < total; it += nwaves) {
-        const int4 dsc = dnext;
-        const int64_t row0 = dsc.x;
-        const int pbeg = dsc.y, ng = dsc.z;
+        const int64_t row0 = dcur.x;
+        const int pbeg = dcur.y, ng = dcur.z;
         const int nct = (ng + 15) >> 4;
         if (lane < ng) {
             float4* rw = reinterpret_cast<float4*>(rec + lane);
@@ -1121,35 +1153,97 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             rw[1] = r1;
             rw[2] = r2;
         }
-        if (it + nwaves < total) fetch(it + nwaves);
+        if (QL && c.stage2) {
+            // the item's q_d rows into LDS, landed before stage 2; LDS float4 f of slot s holds column
+            // f ^ (s & 15) of the slot's query (the swizzle of qsh_index, applied on the source side)
+            constexpr int NF4 = 16 * KA;
+            const int myq = __float_as_int(r2.x);  // query of the pair held by this lane
+            const float4* q4 = reinterpret_cast<const float4*>(c.qd);
+            const int tot = ng * NF4;
+            for (int e0 = 0; e0 < tot; e0 += 64) {
+                const int e = e0 + lane;
+                const int slot = e / NF4, f = e - slot * NF4;
+                const int qr = __shfl(myq, slot < ng ? slot : 0);
+                if (e < tot)
+                    __builtin_amdgcn_global_load_lds((const void*)(q4 + (int64_t)qr * NF4 + (f ^ (slot & 15))),
+                                                     (lds_ptr)(qsh + e0), 16, 0, 0);
+            }
+        }
+        // stage-1 operands of this item into registers: QL from the staging area (which is then refilled
+        // for the next item), otherwise from global memory
+        uint32_t cw[4][KA];
+        float fa[4], ff[4], fe[4];
+        i32x4 qa[NCT][KA];
+        if (KIT > 0) {
+            if (QL) {
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this item's staged operands have landed
+                wave_lds_fence();
+                const uint32_t* pcode = reinterpret_cast<const uint32_t*>(pf);
+                const float* pfac = reinterpret_cast<const float*>(pf + PF_CODE / 16);
+                const int8_t* plev = reinterpret_cast<const int8_t*>(pf + (PF_CODE + PF_FAC) / 16);
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    const int r = 16 * rt + li;
+#pragma unroll
+                    for (int m = 0; m < KA; m++) {
+                        const int w = 2 * m + (kg >> 1);
+                        const uint32_t word = pcode[r * WP + (w < WP ? w : 0)];
+                        cw[rt][m] = w < WP ? (word >> ((kg & 1) << 4)) & 0xFFFFu : 0u;
+                    }
+                    fa[rt] = pfac[r];
+                    ff[rt] = pfac[64 + r];
+                    fe[rt] = pfac[128 + r];
+                }
+                // columns beyond ng read stale levels: they only reach their own (never tested) outputs
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++)
+#pragma unroll
+                    for (int m = 0; m < KA; m++)
+                        qa[ct][m] = *reinterpret_cast<const i32x4*>(plev + (ct * 16 + li) * c.KP + 16 * kg + 64 * m);
+                __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): read out before the area is refilled
+                wave_lds_fence();
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    const int64_t row = row0 + 16 * rt + li;
+#pragma unroll
+                    for (int m = 0; m < KA; m++) {
+                        const int w = 2 * m + (kg >> 1);
+                        const uint32_t word = c.code[row * WP + (w < WP ? w : 0)];
+                        cw[rt][m] = w < WP ? (word >> ((kg & 1) << 4)) & 0xFFFFu : 0u;
+                    }
+                    fa[rt] = c.fA[row];
+                    ff[rt] = c.fF[row];
+                    fe[rt] = c.fE[row];
+                }
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++) {
+                    const int qs = ct * 16 + li;
+                    const bool qv = qs < ng;
+                    const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+#pragma unroll
+                    for (int m = 0; m < KA; m++) qa[ct][m] = qop(qb, m, qv);
+                }
+            }
+        }
+        // requests for the next item, then the x_d slices and norms of row tile 0 (nearly every tile
+        // reaches stage 2)
+        int4 dnn = dnext;
+        if (it + nwaves < total) {
+            fetch_recs(dnext, r0, r1, r2);
+            if (QL) stage_operands(dnext);
+            if (it + 2 * nwaves < total) dnn = const_load4(c.desc + base_item + it + 2 * nwaves);
+        }
+        float4 xs0[XS];
+        float ax0 = 0.f;
+        if (QL && c.stage2) {
+            load_x_slices<XS>(xs0, c.xd + (row0 + li) * c.d4 + 4 * kg, c.d4, kg);
+            ax0 = c.ax[row0 + li];
+        }
 
         // ---- stage 1 for every 16 x 16 sub-tile: pass masks into msk ----
         int cnt = 0;
         if (KIT > 0) {
-            uint32_t cw[4][KA];
-            float fa[4], ff[4], fe[4];
-            i32x4 qa[NCT][KA];
-#pragma unroll
-            for (int rt = 0; rt < 4; rt++) {
-                const int64_t row = row0 + 16 * rt + li;
-#pragma unroll
-                for (int m = 0; m < KA; m++) {
-                    const int w = 2 * m + (kg >> 1);
-                    const uint32_t word = c.code[row * WP + (w < WP ? w : 0)];
-                    cw[rt][m] = w < WP ? (word >> ((kg & 1) << 4)) & 0xFFFFu : 0u;
-                }
-                fa[rt] = c.fA[row];
-                ff[rt] = c.fF[row];
-                fe[rt] = c.fE[row];
-            }
-#pragma unroll
-            for (int ct = 0; ct < NCT; ct++) {
-                const int qs = ct * 16 + li;
-                const bool qv = qs < ng;
-                const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
-#pragma unroll
-                for (int m = 0; m < KA; m++) qa[ct][m] = qop(qb, m, qv);
-            }
             wave_lds_fence();
 #pragma unroll
             for (int rt = 0; rt < 4; rt++) {
@@ -1211,7 +1305,6 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         nscan += 64ll * ng;
         n1 += cnt;
         wave_lds_fence();
-
         // ---- B-bit refinement of the stage-1 survivors ----
         if (cnt > 0 && do_ext) {
             cnt = 0;
@@ -1256,59 +1349,86 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             wave_lds_fence();
         }
         next += cnt;
+        if (QL && c.stage2) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the item's q_d rows have landed in LDS
+            wave_lds_fence();
+        }
 
         // ---- stage 2 (Eq 7) of the remaining survivors ----
         if (cnt > 0 && c.stage2) {
-            if (QL) {  // the item's q_d rows into LDS
-                const float4* q4 = reinterpret_cast<const float4*>(c.qd);
-                for (int e = lane; e < ng * nf4; e += 64) {
-                    const int slot = e / nf4, f = e - slot * nf4;
-                    qsh[qsh_index(slot, f, nf4)] = q4[(int64_t)rec[slot].q * nf4 + f];
-                }
-                wave_lds_fence();
-            }
             cnt = 0;
-            for (int rt = 0; rt < 4; rt++) {
-                const int64_t row = row0 + 16 * rt + li;
-                float4 xa[XS];
-                bool xl = false;
-                for (int ct = 0; ct < nct; ct++) {
-                    unsigned long long mv[4];
-                    bool any = false;
+            if constexpr (QL) {
+                uint32_t rtany = 0;  // row tiles holding a surviving entry (wave-uniform)
 #pragma unroll
-                    for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
-                    if (!any) continue;
-                    const int qs = ct * 16 + li;
-                    const bool qv = qs < ng;
-                    f32x4 dot;
-                    if (QL) {
-                        if (!xl) {
-                            load_x_slices<XS>(xa, c.xd + row * c.d4 + 4 * kg, c.d4, kg);
-                            xl = true;
-                        }
-                        dot = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int rt = 0; rt < 4; rt++)
+                    for (int ct = 0; ct < nct; ct++)
+#pragma unroll
+                        for (int v = 0; v < 4; v++) rtany |= (msk[(ct * 4 + rt) * 4 + v] != 0ull ? 1u : 0u) << rt;
+                float4 xb[2][XS];
+                float axb[2] = {0.f, 0.f};
+#pragma unroll
+                for (int rt = 0; rt < 4; rt++) {
+                    // the next tile's slices and norms are requested before this tile's products
+                    if (rt < 3 && ((rtany >> (rt + 1)) & 1u)) {
+                        const int64_t rn = row0 + 16 * (rt + 1) + li;
+                        load_x_slices<XS>(xb[(rt + 1) & 1], c.xd + rn * c.d4 + 4 * kg, c.d4, kg);
+                        axb[(rt + 1) & 1] = c.ax[rn];
+                    }
+                    if (!((rtany >> rt) & 1u)) continue;
+                    const float4(&xa)[XS] = rt == 0 ? xs0 : xb[rt & 1];
+                    const float axr = rt == 0 ? ax0 : axb[rt & 1];
+                    for (int ct = 0; ct < nct; ct++) {
+                        unsigned long long mv[4];
+                        bool any = false;
+#pragma unroll
+                        for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
+                        if (!any) continue;
+                        // slots beyond ng hold stale rows: they only reach their own (never tested) outputs
+                        f32x4 dot = {0.f, 0.f, 0.f, 0.f};
                         float4 qv4[XS];
 #pragma unroll
-                        for (int t = 0; t < XS; t++)
-                            qv4[t] = zero_unless(qsh[qsh_index(qv ? qs : 0, 4 * t + kg, nf4)], qv);
+                        for (int t = 0; t < XS; t++) qv4[t] = qsh[qsh_index(ct * 16 + li, 4 * t + kg, nf4)];
 #pragma unroll
                         for (int t = 0; t < XS; t++) mfma4(dot, qv4[t], xa[t]);
-                    } else {
-                        const int qrow = rec[qv ? qs : 0].q;
-                        dot = dot_tile<4 * KIT>(c.qd + (int64_t)qrow * c.d4 + 4 * kg, c.xd + row * c.d4 + 4 * kg, qv,
-                                                c.d4, kg);
-                    }
-                    const float axr = c.ax[row];
 #pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        bool ps = (mv[v] >> lane) & 1ull;
-                        if (ps) {
-                            const PairRec& R = rec[ct * 16 + 4 * kg + v];
-                            ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                        for (int v = 0; v < 4; v++) {
+                            bool ps = (mv[v] >> lane) & 1ull;
+                            if (ps) {
+                                const PairRec& R = rec[ct * 16 + 4 * kg + v];
+                                ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                            }
+                            const unsigned long long nm = __ballot(ps);
+                            if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
+                            cnt += __popcll(nm);
                         }
-                        const unsigned long long nm = __ballot(ps);
-                        if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
-                        cnt += __popcll(nm);
+                    }
+                }
+            } else {
+                for (int rt = 0; rt < 4; rt++) {
+                    const int64_t row = row0 + 16 * rt + li;
+                    for (int ct = 0; ct < nct; ct++) {
+                        unsigned long long mv[4];
+                        bool any = false;
+#pragma unroll
+                        for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
+                        if (!any) continue;
+                        const int qs = ct * 16 + li;
+                        const bool qv = qs < ng;
+                        const int qrow = rec[qv ? qs : 0].q;
+                        const f32x4 dot = dot_tile<4 * KIT>(c.qd + (int64_t)qrow * c.d4 + 4 * kg,
+                                                            c.xd + row * c.d4 + 4 * kg, qv, c.d4, kg);
+                        const float axr = c.ax[row];
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            bool ps = (mv[v] >> lane) & 1ull;
+                            if (ps) {
+                                const PairRec& R = rec[ct * 16 + 4 * kg + v];
+                                ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                            }
+                            const unsigned long long nm = __ballot(ps);
+                            if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
+                            cnt += __popcll(nm);
+                        }
                     }
                 }
             }
@@ -1335,6 +1455,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             }
         }
         wave_lds_fence();
+        dcur = dnext;
+        dnext = dnn;
     }
     if (lane == 0) c.wcnt[wid] = nreg;
     if (c.counters && lane == 0) {  // the counts are wave-uniform
@@ -1345,14 +1467,15 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     }
 }
 
-// Exact stage of a phase: block b takes the candidates in region b of the buffer (written by scan wave
-// b), 16 lanes per candidate, four per wave, into the result queues.
-__global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
+// Exact stage of a phase: the candidates in region r of the buffer (written by scan wave r) are shared by
+// blocks r * split .. r * split + split - 1 (block part j takes groups of 16 candidates j, j + split, ...),
+// 16 lanes per candidate, four per wave, into the result queues.
+__global__ __launch_bounds__(256) void k_exact(ScanCtx c, int split) {
     const int lane = lane_id();
-    const int b = blockIdx.x;
-    const int n = min(c.wcnt[b], c.rs);
-    const int2* region = c.surv + (int64_t)b * c.rs;
-    for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
+    const int r = blockIdx.x / split, part = blockIdx.x - r * split;
+    const int n = min(c.wcnt[r], c.rs);
+    const int2* region = c.surv + (int64_t)r * c.rs;
+    for (int i = 16 * part + (threadIdx.x >> 4); i - (lane >> 4) < n; i += 16 * split) {
         const bool valid = i < n;
         const int2 e = region[valid ? i : 0];
         const float dist = exact_dist_group(c.X + (int64_t)e.x * c.D4, c.qpad + (int64_t)e.y * c.D4, c.D4, lane & 15);
@@ -1915,7 +2038,9 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         }
         {
             Timed t(tm, s, "exact");
-            hipLaunchKernelGGL(k_exact, dim3((unsigned)(4 * scan_blocks)), dim3(256), 0, s, c);
+            // at least about 4096 blocks, however many scan waves wrote the regions
+            const int split = std::max(1, 4096 / (4 * scan_blocks));
+            hipLaunchKernelGGL(k_exact, dim3((unsigned)(4 * scan_blocks * split)), dim3(256), 0, s, c, split);
             HIP_TRY(hipGetLastError());
         }
     }
