@@ -81,6 +81,11 @@ def lib():
         L.orc_topk_risk.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(Params), C.c_double, P, P,
                                     P]
         L.orc_bruteforce.argtypes = [P, C.c_int64, C.c_int32, P, C.c_int64, C.c_int32, P, P]
+        L.orc_sq8_range.argtypes = [P, C.c_int64, C.c_int, C.c_int, P, P]
+        L.orc_sq8_encode.argtypes = [P, C.c_int, P, P, P]
+        L.orc_sq8_build.argtypes = [P]
+        L.orc_mrsq_estimates.argtypes = [P, P, C.c_int32, P, P, P]
+        L.orc_mrsq_search.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P]
         _lib = L
     return _lib
 
@@ -172,6 +177,26 @@ def bruteforce(X: np.ndarray, Q: np.ndarray, k: int):
     return ids, dd
 
 
+def sq8_range(xd: np.ndarray):
+    """MR-SQ grid (readings S1, S2): per-coordinate lo and delta of FP32 rows."""
+    x = np.ascontiguousarray(xd, dtype=np.float32)
+    lo = np.empty(x.shape[1], dtype=np.float32)
+    dl = np.empty(x.shape[1], dtype=np.float32)
+    lib().orc_sq8_range(_p(x), x.shape[0], x.shape[1], x.shape[1], _p(lo), _p(dl))
+    return lo, dl
+
+
+def sq8_encode(x: np.ndarray, lo: np.ndarray, delta: np.ndarray) -> np.ndarray:
+    """MR-SQ 8-bit codes (reading S2) of FP32 rows."""
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float32)
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    delta = np.ascontiguousarray(delta, dtype=np.float32)
+    u = np.empty(x.shape, dtype=np.uint8)
+    for i in range(x.shape[0]):
+        lib().orc_sq8_encode(_p(x[i]), x.shape[1], _p(lo), _p(delta), _p(u[i]))
+    return u
+
+
 # ---- index ------------------------------------------------------------------------------------
 
 class Index:
@@ -221,8 +246,10 @@ class Index:
     def get(self, name):
         shapes = {"mu": (self.D,), "Pp": (self.D, self.D), "lam": (self.D,), "Pr": (self.d, self.d),
                   "C": (self.nlist, self.d), "off": (self.nlist + 1,), "lid": (self.N,),
-                  "code": (self.N, self.d), "xd": (self.N, self.d)}
-        dtypes = {"off": np.int64, "lid": np.int64, "code": np.uint8}
+                  "code": (self.N, self.d), "xd": (self.N, self.d), "sq_lo": (self.d,),
+                  "sq_delta": (self.d,), "sq_code": (self.N, self.d)}
+        dtypes = {"off": np.int64, "lid": np.int64, "code": np.uint8, "sq_lo": np.float32,
+                  "sq_delta": np.float32, "sq_code": np.uint8}
         shp = shapes.get(name, (self.N,))
         out = np.empty(shp, dtype=dtypes.get(name, np.float64))
         if lib().orc_get(self._h, name.encode(), _p(out)) != 0:
@@ -274,6 +301,35 @@ class Index:
         keys = ["nq", "Tq", "er", "qn2", "vl", "delta", "su", "sigma"]
         cols = ["dis1", "eb1", "lb1", "disB", "ebB", "lbB", "diso", "dis", "ip", "pc"]
         return (dict(zip(keys, qs)), qp, u, ids[:n], {c: cand[:n, i] for i, c in enumerate(cols)})
+
+    def build_sq8(self):
+        """MR-SQ codes from this index's own leading coordinates (readings S1, S2)."""
+        if lib().orc_sq8_build(self._h) != 0:
+            raise MemoryError
+        return self
+
+    def mrsq_estimates(self, q, nprobe):
+        """Reading S3 for every candidate of the probed lists: (ids, estimates, exact distances)."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        lists, _ = self.probe(q, nprobe)
+        off = self.get("off")
+        n = int(sum(off[j + 1] - off[j] for j in lists))
+        ids = np.empty(max(n, 1), dtype=np.int64)
+        est = np.empty(max(n, 1))
+        ex = np.empty(max(n, 1))
+        r = lib().orc_mrsq_estimates(self._h, _p(q), nprobe, _p(ids), _p(est), _p(ex))
+        if r < 0:
+            raise ValueError("no MR-SQ codes or bad nprobe")
+        return ids[:r], est[:r], ex[:r]
+
+    def search_mrsq(self, q, k, nprobe, R=500):
+        """MR-SQ search of one query (reading S4): ids (-1 padded) and FP64 distances."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        ids = np.empty(k, dtype=np.int64)
+        dd = np.empty(k)
+        if lib().orc_mrsq_search(self._h, _p(q), k, nprobe, R, _p(ids), _p(dd)) < 0:
+            raise ValueError("MR-SQ search arguments")
+        return ids, dd
 
     def topk_risk(self, q, k, nprobe, prm=None, margin=0.0):
         q = np.ascontiguousarray(q, dtype=np.float32)

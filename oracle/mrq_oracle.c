@@ -33,6 +33,17 @@
  *   R18 the variances lambda_i of Eq 6 are non-negative: an eigenvalue that round-off puts below zero
  *       (rank-deficient data) counts as 0
  *
+ * MR-SQ (Appendix A.2, Exp-5: the projection and split of MRQ applied to 8-bit scalar quantisation):
+ *   S1  the codes quantise the leading d PCA coordinates, one uniform 8-bit grid per coordinate over
+ *       that coordinate's range in the data set, [lo_i, hi_i] = min / max of the FP32 coordinates
+ *   S2  delta_i = (hi_i - lo_i)/255, u_i = min(255, floor((x_i - lo_i) * (1/delta_i) + 1/2)), each step
+ *       one FP32 rounding (an integer decided from floating point: FP32, the device precision);
+ *       delta_i = 1 and u_i = 0 when hi_i == lo_i; the reconstruction is lo_i + delta_i u_i
+ *   S3  estimate = ||xhat_d - q_d||^2 + ||x_r||^2 + ||q_r||^2, i.e. Eq 7's projected distance with x_d
+ *       replaced by its reconstruction (the tail enters through its norms only, as in MRQ)
+ *   S4  with no error bound, the R candidates of the probed lists with the smallest (estimate, id) are
+ *       re-ranked by exact distance and the result is their k nearest by (dis, id); R = 500 by default
+ *
  * Parity unpinned: the absolute constant c0 of Eq 5 (the paper gives none), hence the exact failure
  * probability of eps_b; recall figures on synthetic data (no paper value applies).
  */
@@ -363,6 +374,8 @@ struct orc_index {
     double *mu, *Pp, *lam, *Pr, *C;  /* D, D*D (row i = axis i), D, d*d, nlist*d */
     int64_t *off, *lid;               /* list boundaries; ids in list order */
     uint8_t *code;                    /* per list position: d level indices */
+    float *sq_lo, *sq_delta;          /* MR-SQ grid (S1, S2): d each, or NULL */
+    uint8_t *sq_code;                 /* MR-SQ codes per list position: d bytes each */
     double *xd;                       /* per list position: leading d coordinates of x_p */
     double *nx, *tx, *ax, *xi1, *xiB, *yn;
     const float *X;                   /* caller-owned original vectors, id order */
@@ -373,6 +386,7 @@ void orc_free(orc_index *ix) {
     free(ix->mu); free(ix->Pp); free(ix->lam); free(ix->Pr); free(ix->C);
     free(ix->off); free(ix->lid); free(ix->code); free(ix->xd);
     free(ix->nx); free(ix->tx); free(ix->ax); free(ix->xi1); free(ix->xiB); free(ix->yn);
+    free(ix->sq_lo); free(ix->sq_delta); free(ix->sq_code);
     free(ix);
 }
 
@@ -538,6 +552,21 @@ orc_index *orc_import(const char *path, const float *X, int64_t Nx, int32_t Dx) 
     RD_F32(ix->xiB, N);
     RD_F32(ix->yn, N);
 #undef RD_F32
+    if (ok) { /* optional MR-SQ section: "SQ8G", lo and delta (d FP32 each), codes (N x d bytes) */
+        char tag[4];
+        if (fread(tag, 1, 4, f) == 4) {
+            if (memcmp(tag, "SQ8G", 4) != 0) ok = 0;
+            else {
+                ix->sq_lo = malloc(sizeof(float) * d);
+                ix->sq_delta = malloc(sizeof(float) * d);
+                ix->sq_code = malloc((size_t)N * d);
+                if (!ix->sq_lo || !ix->sq_delta || !ix->sq_code ||
+                    fread(ix->sq_lo, 4, d, f) != (size_t)d || fread(ix->sq_delta, 4, d, f) != (size_t)d ||
+                    fread(ix->sq_code, 1, (size_t)N * d, f) != (size_t)N * d)
+                    ok = 0;
+            }
+        }
+    }
     fclose(f);
     if (!ok) { orc_free(ix); return NULL; }
     if (X) {
@@ -611,9 +640,15 @@ int orc_get(const orc_index *ix, const char *name, void *out) {
         {"tx", ix->tx, sizeof(double) * N},      {"ax", ix->ax, sizeof(double) * N},
         {"xi1", ix->xi1, sizeof(double) * N},    {"xiB", ix->xiB, sizeof(double) * N},
         {"yn", ix->yn, sizeof(double) * N},
+        {"sq_lo", ix->sq_lo, sizeof(float) * d},  {"sq_delta", ix->sq_delta, sizeof(float) * d},
+        {"sq_code", ix->sq_code, (size_t)(N * d)},
     };
     for (size_t i = 0; i < sizeof(t) / sizeof(t[0]); i++)
-        if (strcmp(t[i].n, name) == 0) { memcpy(out, t[i].p, t[i].bytes); return 0; }
+        if (strcmp(t[i].n, name) == 0) {
+            if (!t[i].p) return -1;
+            memcpy(out, t[i].p, t[i].bytes);
+            return 0;
+        }
     return -1;
 }
 
@@ -889,6 +924,119 @@ int orc_topk_risk(const orc_index *ix, const float *q, int32_t k, int32_t nprobe
     }
     free(qs.qp); free(ps.qprime); free(ps.u); free(ps.qbar);
     return n;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* MR-SQ (S1-S4).                                                                                   */
+
+/* S1, S2: the grid of each of the d coordinates from N rows (row stride ld) of FP32 values. */
+void orc_sq8_range(const float *xd, int64_t N, int d, int ld, float *lo, float *delta) {
+    for (int i = 0; i < d; i++) {
+        float a = xd[i], b = xd[i];
+        for (int64_t n = 1; n < N; n++) {
+            float v = xd[n * ld + i];
+            if (v < a) a = v;
+            if (v > b) b = v;
+        }
+        lo[i] = a;
+        delta[i] = b > a ? (b - a) / 255.0f : 1.0f;
+    }
+}
+
+/* S2: the 8-bit code of one row (FP32 steps; -ffp-contract=off keeps them separate roundings). */
+void orc_sq8_encode(const float *x, int d, const float *lo, const float *delta, uint8_t *u) {
+    for (int i = 0; i < d; i++) {
+        const float inv = 1.0f / delta[i];
+        const float t = (x[i] - lo[i]) * inv + 0.5f;
+        float fl = floorf(t);
+        int v = (int)fl;
+        u[i] = (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v));
+    }
+}
+
+/* MR-SQ codes of an index from its own leading coordinates x_d (rounded to FP32). */
+int orc_sq8_build(orc_index *ix) {
+    const int64_t N = ix->N;
+    const int d = ix->d;
+    float *xf = malloc(sizeof(float) * (size_t)N * d);
+    free(ix->sq_lo); free(ix->sq_delta); free(ix->sq_code);
+    ix->sq_lo = malloc(sizeof(float) * d);
+    ix->sq_delta = malloc(sizeof(float) * d);
+    ix->sq_code = malloc((size_t)N * d);
+    if (!xf || !ix->sq_lo || !ix->sq_delta || !ix->sq_code) { free(xf); return -1; }
+    for (int64_t i = 0; i < N * d; i++) xf[i] = (float)ix->xd[i];
+    orc_sq8_range(xf, N, d, d, ix->sq_lo, ix->sq_delta);
+    for (int64_t p = 0; p < N; p++) orc_sq8_encode(xf + p * d, d, ix->sq_lo, ix->sq_delta, ix->sq_code + p * d);
+    free(xf);
+    return 0;
+}
+
+/* S3 for every candidate of the nprobe probed lists (lists nearest first, R12), FP64: ids, estimates
+ * and (with X attached) exact distances.  Returns the number of candidates, or -1. */
+int orc_mrsq_estimates(const orc_index *ix, const float *q, int32_t nprobe, int64_t *ids, double *est,
+                       double *exact) {
+    if (!ix || !ix->sq_code || nprobe < 1 || nprobe > ix->nlist) return -1;
+    const int d = ix->d;
+    qstate qs;
+    qs.qp = malloc(sizeof(double) * ix->D);
+    query_state(ix, q, 0.0, &qs);
+    int32_t *lists = malloc(sizeof(int32_t) * nprobe);
+    rank_lists(ix, qs.qp, nprobe, lists, NULL);
+    int n = 0;
+    for (int r = 0; r < nprobe; r++) {
+        const int32_t j = lists[r];
+        for (int64_t pos = ix->off[j]; pos < ix->off[j + 1]; pos++, n++) {
+            const uint8_t *u = ix->sq_code + pos * d;
+            double s = 0.0;
+            for (int i = 0; i < d; i++) {
+                const double xh = (double)ix->sq_lo[i] + (double)ix->sq_delta[i] * (double)u[i];
+                const double t = xh - qs.qp[i];
+                s += t * t;
+            }
+            ids[n] = ix->lid[pos];
+            est[n] = s + ix->tx[pos] + qs.Tq;
+            if (exact) exact[n] = ix->X ? exact_dist(ix, ids[n], q) : NAN;
+        }
+    }
+    free(qs.qp); free(lists);
+    return n;
+}
+
+typedef struct { double e; int64_t id; } eent;
+static int cmp_eent(const void *a, const void *b) {
+    const eent *x = a, *y = b;
+    if (x->e < y->e) return -1;
+    if (x->e > y->e) return 1;
+    return x->id < y->id ? -1 : (x->id > y->id);
+}
+
+/* S4: MR-SQ search of one query; returns the number of results (<= k), or -1. */
+int orc_mrsq_search(const orc_index *ix, const float *q, int32_t k, int32_t nprobe, int32_t R, int64_t *ids,
+                    double *dists) {
+    if (!ix || !ix->X || !ix->sq_code || k < 1 || R < k || nprobe < 1 || nprobe > ix->nlist) return -1;
+    int64_t cap = 0;
+    {
+        int32_t *lists = malloc(sizeof(int32_t) * nprobe);
+        if (orc_probe(ix, q, nprobe, lists, NULL) != 0) { free(lists); return -1; }
+        for (int r = 0; r < nprobe; r++) cap += ix->off[lists[r] + 1] - ix->off[lists[r]];
+        free(lists);
+    }
+    int64_t *cid = malloc(sizeof(int64_t) * (cap ? cap : 1));
+    double *ce = malloc(sizeof(double) * (cap ? cap : 1));
+    const int n = orc_mrsq_estimates(ix, q, nprobe, cid, ce, NULL);
+    eent *e = malloc(sizeof(eent) * (n ? n : 1));
+    for (int i = 0; i < n; i++) { e[i].e = ce[i]; e[i].id = cid[i]; }
+    qsort(e, n, sizeof(eent), cmp_eent);
+    topk t = {malloc(sizeof(double) * k), malloc(sizeof(int64_t) * k), 0, k};
+    const int take = n < R ? n : R;
+    for (int i = 0; i < take; i++) topk_push(&t, exact_dist(ix, e[i].id, q), e[i].id);
+    for (int i = 0; i < k; i++) {
+        ids[i] = i < t.n ? t.id[i] : -1;
+        dists[i] = i < t.n ? t.dis[i] : INFINITY;
+    }
+    const int got = t.n;
+    free(cid); free(ce); free(e); free(t.dis); free(t.id);
+    return got;
 }
 
 /* Exact k-NN over the whole set (Section 2.1 problem statement), FP64, ties -> smaller id. */

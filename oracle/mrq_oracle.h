@@ -11,6 +11,7 @@
  *   Section 4.2, Eq 4-6        sign codes, unbiased estimator, error bounds
  *   Algorithm 1 (Section 5.1)  index build: PCA, residual variances, IVF on x_d, encoding
  *   Algorithm 2 + Eq 7 (5.2)   the multi-stage query
+ *   Appendix A.2, Exp-5        MR-SQ: 8-bit scalar codes of the leading dimensions, fixed re-ranking
  *
  * Parity pins live in tests/test_oracle_*.py; "parity unpinned" items are named in the .c header.
  */
@@ -77,6 +78,14 @@ int orc_topk_risk(const orc_index *ix, const float *q, int32_t k, int32_t nprobe
                   double margin, int64_t *ids, double *dists, uint8_t *risk);
 void orc_bruteforce(const float *X, int64_t N, int32_t D, const float *Q, int64_t nq, int32_t k,
                     int64_t *ids, double *dists);
+/* ---- MR-SQ (Appendix A.2, Exp-5; readings S1-S4 in the .c header) ---- */
+void orc_sq8_range(const float *xd, int64_t N, int d, int ld, float *lo, float *delta);
+void orc_sq8_encode(const float *x, int d, const float *lo, const float *delta, uint8_t *u);
+int orc_sq8_build(orc_index *ix);
+int orc_mrsq_estimates(const orc_index *ix, const float *q, int32_t nprobe, int64_t *ids, double *est,
+                       double *exact);
+int orc_mrsq_search(const orc_index *ix, const float *q, int32_t k, int32_t nprobe, int32_t R, int64_t *ids,
+                    double *dists);
 
 #ifdef __cplusplus
 }
