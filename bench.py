@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="--serve: requests per rate")
     ap.add_argument("--max-slots", type=int, default=512, help="--serve: queries per batch at most")
     ap.add_argument("--mem-budget", type=float, default=4.0, help="--serve: device GiB for the batch slots")
+    ap.add_argument("--sweep-d", default="",
+                    help="comma-separated d_r values: QPS at the target recall per projection dimension "
+                         "(Exp-4 grid) instead of the headline measurement")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -121,6 +124,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.serve:
         serve_main(args, np, torch, mrq, synth, dev)
+        return
+    if args.sweep_d:
+        sweep_d_main(args, np, torch, mrq, synth, dev)
         return
     t0 = time.time()
     X, Q, spec = synth.workload(args.workload, N=args.N, nq=args.nq)
@@ -316,6 +322,65 @@ def main():
     res.update(out_extra)
     print(json.dumps(res), flush=True)
     ix.close()
+
+
+def sweep_d_main(args, np, torch, mrq, synth, dev):
+    """Exp-4 (Section 6, the choice of d): for each projection dimension d_r of --sweep-d, build the index
+    of --workload, find the smallest nprobe whose recall@k reaches --target-recall and time the batched
+    search there (query group from the tuner); Eq 8's own choice of d_r for the same data is reported
+    beside the grid."""
+    X, Q, _ = synth.workload(args.workload, N=args.N, nq=args.nq)
+    N, D = X.shape
+    nq, k = Q.shape[0], args.k
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    gt = ground_truth(torch, Xd, Qd, k)
+    ix = mrq.Index.build(Xd, d_r=0, bits=args.bits, nlist=args.nlist)
+    eq8 = ix.d
+    ix.close()
+    log(f"Eq 8 chooses d_r = {eq8}")
+    ids_buf = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    rows = []
+    for d in [int(v) for v in args.sweep_d.split(",") if v]:
+        if d < 2 or d > D:
+            continue
+        t1 = time.time()
+        ix = mrq.Index.build(Xd, d_r=d, bits=args.bits, nlist=args.nlist)
+        build_s = time.time() - t1
+        chosen, rec = None, None
+        for npb in [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]:
+            if npb > args.nlist:
+                break
+            ix.search(Qd, k, npb, ids=ids_buf, dists=d_buf)
+            torch.cuda.synchronize()
+            chosen, rec = npb, recall(ids_buf.cpu().numpy(), gt, k)
+            if rec >= args.target_recall:
+                break
+        group = ix.tune(Qd, k, chosen)
+        for _ in range(args.warmup):
+            ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf)
+        ix.timing_enable(True, reset=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        ix.timing_enable(False, reset=False)
+        kt = ix.timing()
+        row = {"d_r": d, "nprobe": chosen, "recall_at_k": round(rec, 4), "qps": round(nq * args.steps / el, 1),
+               "query_group": group, "build_s": round(build_s, 2),
+               "index_gib": round(ix.device_bytes / 2**30, 3),
+               "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in kt.items()}}
+        log(f"d_r {d}: nprobe {chosen} recall {rec:.4f} {row['qps']:,.0f} QPS")
+        rows.append(row)
+        ix.close()
+    print(json.dumps({"metric": f"QPS at recall@{k}={args.target_recall} vs d_r (1 GPU)", "unit": "queries/s",
+                      "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} "
+                                             f"bits={args.bits} k={k}", "steps": args.steps},
+                      "eq8_d_r": eq8, "grid": rows}), flush=True)
 
 
 def serve_main(args, np, torch, mrq, synth, dev):
