@@ -32,6 +32,8 @@
  *     f32 xd[N*d]; f32 nx[N], tx[N], ax[N], xi1[N], xiB[N], yn[N]   (all in list order)
  *   where nx = ||x_d - c||, tx = ||x_r||^2, ax = ||x - mu||^2, xi1 = <xbar_1bit, x_b>,
  *   xiB = <xbar_Bbit, x_b>, yn = ||u - (2^B - 1)/2||.
+ *   An index built with MR-SQ codes appends: char tag[4] = "SQ8G"; f32 lo[d], delta[d];
+ *   u8 sq[N*d] (list order, leading dim i of vector n at n*d + i).
  */
 #ifndef MRQ_H
 #define MRQ_H
@@ -58,10 +60,19 @@ typedef enum {
 
 enum { MRQ_BATCHED = 0, MRQ_PER_QUERY = 1 };
 
+/* Search methods over one index (mrq_search_opts.method). */
+enum {
+    MRQ_METHOD_MRQ = 0,  /* Algorithm 2 with the Eq 7 stage (Section 5.2) */
+    MRQ_METHOD_MRSQ = 1  /* MR-SQ (Appendix A.2, Exp-5): 8-bit scalar codes of the leading d_r PCA
+                            coordinates, estimate = Eq 7's projected distance with x_d replaced by its
+                            reconstruction, then exact re-ranking of a fixed number of candidates */
+};
+
 typedef struct {
     uint64_t seed;        /* k-means initialisation and the random rotation P_r; default 4001 */
     int32_t kmeans_iters; /* Lloyd iterations (stops early when no assignment changes); default 25 */
-    int32_t reserved[7];
+    int32_t sq8;          /* 1 = also build the MR-SQ codes (needed by MRQ_METHOD_MRSQ); default 0 */
+    int32_t reserved[6];
 } mrq_build_opts;
 
 typedef struct {
@@ -78,7 +89,12 @@ typedef struct {
     int32_t group;          /* queries per scan work item: 16, 32 or 64 (0 = the index default) */
     int32_t exact_cap;      /* exact-stage buffer entries per phase (0 = automatic); candidates beyond
                                it are finished inside the scan; results do not depend on it */
-    int32_t reserved[4];
+    int32_t method;         /* MRQ_METHOD_MRQ (default) or MRQ_METHOD_MRSQ (index built with sq8) */
+    int32_t rerank;         /* MRQ_METHOD_MRSQ: candidates re-ranked by exact distance per query, R in
+                               [k, 16384]; 0 = 500.  The MRQ fields bq, eps0, m, stage2, use_ext, group
+                               and exact_cap do not apply to MR-SQ; counters [0] and [3] count its
+                               scanned candidates and exact distances */
+    int32_t reserved[2];
 } mrq_search_opts;
 
 /* Defaults for the option structs (pass NULL to any call to use them). */
@@ -97,6 +113,10 @@ void mrq_search_opts_default(mrq_search_opts *o);
  *   X      N x D FP32, host or device, finite values only (checked: MRQ_EINVAL otherwise)
  *   d_r    in [2, min(D, 1536)], or 0 for the Eq 8 choice (mrq_choose_dr on the data's eigenvalues);
  *          bits B in [1, 8];  nlist in [1, min(N, 16384)]
+ *   opts   with sq8 = 1 the index also holds MR-SQ codes (Appendix A.2, Exp-5): per leading coordinate i
+ *          the range [lo_i, hi_i] over the data set, step delta_i = (hi_i - lo_i)/255 (1 when
+ *          hi_i == lo_i) and code u_i = min(255, floor((x_i - lo_i) * (1/delta_i) + 1/2)), each step
+ *          one FP32 rounding; d_r bytes per vector
  *   stream where the device work runs; the call synchronises it before returning
  *   out    receives a new index on MRQ_OK (free with mrq_free); untouched on failure
  */
@@ -112,6 +132,10 @@ mrq_status mrq_build(const float *X, int64_t N, int32_t D, int32_t d_r, int32_t 
  *   Q      nq x D FP32 (host or device);  nq >= 1;  1 <= k <= 1024;  1 <= nprobe <= min(nlist, 1024)
  *   ids    nq x k int64 output (host or device);  dists  nq x k FP32 output (host or device)
  * The result of a query does not depend on the other queries of the batch nor on `mode`.
+ * With opts->method = MRQ_METHOD_MRSQ (index built with sq8, else MRQ_ESTATE): for every candidate of
+ * the probed lists the estimate ||xhat_d - q_d||^2 + ||x_r||^2 + ||q_r||^2 (xhat_i = lo_i + delta_i u_i,
+ * FP32), then per query the R candidates with the smallest (estimate, id) get their exact distance and
+ * the k nearest of them are returned (R = opts->rerank, k <= R).
  */
 mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe,
                       int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
@@ -152,10 +176,10 @@ mrq_status mrq_index_info(const mrq_index *index, int64_t *N, int32_t *D, int32_
  * the vectors in PCA coordinates; the caller keeps the original vectors).  Synchronous. */
 mrq_status mrq_export(const mrq_index *index, const char *path);
 
-/* Persist / restore a complete index: "MRQS0002", the shape (N, padded rows, D, d_r, bits, nlist, code
- * words per row, longest list), the FP64 eigenvalues, the list offsets, then every device array of the
- * index (projection, rotation, centroids, codes, factors, x_d, the vectors in PCA coordinates) in a fixed
- * order.  The format is private to this library version.  mrq_load allocates on the current device.
+/* Persist / restore a complete index: "MRQS0003", the shape (N, padded rows, D, d_r, bits, nlist, code
+ * words per row, longest list, MR-SQ flag), the FP64 eigenvalues, the list offsets, then every device
+ * array of the index (projection, rotation, centroids, codes, factors, x_d, the vectors in PCA
+ * coordinates, the MR-SQ codes when present) in a fixed order.  The format is private to this library version.  mrq_load allocates on the current device.
  * Synchronous. */
 mrq_status mrq_save(const mrq_index *index, const char *path);
 mrq_status mrq_load(const char *path, mrq_index **out);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmrq.so")
 
 MRQ_OK, MRQ_EINVAL, MRQ_ENOMEM, MRQ_EDEVICE, MRQ_ESTATE, MRQ_EIO = range(6)
 MRQ_BATCHED, MRQ_PER_QUERY = 0, 1
+MRQ_METHOD_MRQ, MRQ_METHOD_MRSQ = 0, 1
 
 EXPORTED = [
     "mrq_build_opts_default", "mrq_search_opts_default", "mrq_build", "mrq_search", "mrq_search_mixed",
@@ -33,14 +34,14 @@ class MRQError(RuntimeError):
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("seed", C.c_uint64), ("kmeans_iters", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("seed", C.c_uint64), ("kmeans_iters", C.c_int32), ("sq8", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("bq", C.c_int32), ("eps0", C.c_float), ("m", C.c_float),
                 ("stage2", C.c_int32), ("use_ext", C.c_int32), ("counters", C.c_void_p),
-                ("group", C.c_int32), ("exact_cap", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("group", C.c_int32), ("exact_cap", C.c_int32), ("method", C.c_int32), ("rerank", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -119,12 +120,13 @@ def _stream(stream) -> Optional[int]:
 
 
 def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=True, counters=None,
-                group=0, exact_cap=0) -> SearchOpts:
+                group=0, exact_cap=0, method=MRQ_METHOD_MRQ, rerank=0) -> SearchOpts:
     o = SearchOpts()
     lib().mrq_search_opts_default(C.byref(o))
     o.mode, o.bq, o.eps0, o.m = int(mode), int(bq), float(eps0), float(m)
     o.stage2, o.use_ext, o.group = int(bool(stage2)), int(bool(use_ext)), int(group)
     o.exact_cap = int(exact_cap)
+    o.method, o.rerank = int(method), int(rerank)
     o.counters = _ptr(counters) if counters is not None else None
     return o
 
@@ -148,10 +150,11 @@ class Index:
 
     @classmethod
     def build(cls, X, d_r: int, bits: int, nlist: int, seed: int = 4001, kmeans_iters: int = 25,
-              stream=None) -> "Index":
+              stream=None, sq8: bool = False) -> "Index":
+        """sq8: also build the MR-SQ codes (search with method=MRQ_METHOD_MRSQ)."""
         o = BuildOpts()
         lib().mrq_build_opts_default(C.byref(o))
-        o.seed, o.kmeans_iters = seed, kmeans_iters
+        o.seed, o.kmeans_iters, o.sq8 = seed, kmeans_iters, int(bool(sq8))
         h = C.c_void_p()
         N, D = int(X.shape[0]), int(X.shape[1])
         _check(lib().mrq_build(_ptr(X), N, D, d_r, bits, nlist, C.byref(o), _stream(stream), C.byref(h)))

@@ -452,6 +452,16 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     hip_check(launch_fill_f32(ix->RC, 0.f, (int64_t)nlist * d4, s), "fill");
     hip_check(launch_gemm_nt(ix->C, d4, nullptr, ix->PrT, d4, ix->RC, d4, nlist, d, d, s), "rotate centroids");
     hip_check(launch_encode(*ix, O.as<float>(), Xpp.as<float>(), txr.as<double>(), s), "encode");
+    if (o.sq8) {  // MR-SQ codes of the leading coordinates (Appendix A.2, Exp-5)
+        ix->dq = (d + 15) & ~15;
+        ix->sq_lo = dalloc<float>(ix.get(), ix->dq);
+        ix->sq_delta = dalloc<float>(ix.get(), ix->dq);
+        ix->sq_code = dalloc<uint8_t>(ix.get(), Np * ix->dq);
+        ix->sq_A = dalloc<float>(ix.get(), Np);
+        const int nchunk = 256;
+        DevTemp part(sizeof(float) * 2 * nchunk * (size_t)d);
+        hip_check(launch_sq8_build(*ix, txr.as<double>(), part.as<float>(), nchunk, s), "MR-SQ codes");
+    }
     hip_check(hipStreamSynchronize(s), "build sync");
     hip_check(hipEventCreateWithFlags(&ix->ws_event, hipEventDisableTiming), "event");
     return ix.release();
@@ -495,6 +505,12 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (o.mode != MRQ_BATCHED && o.mode != MRQ_PER_QUERY) throw Fail(MRQ_EINVAL, "unknown mode");
     if (o.group < 0 || o.group > 64) throw Fail(MRQ_EINVAL, "group must be in [0, 64]");
     if (o.exact_cap < 0) throw Fail(MRQ_EINVAL, "exact_cap must be >= 0");
+    if (o.method != MRQ_METHOD_MRQ && o.method != MRQ_METHOD_MRSQ) throw Fail(MRQ_EINVAL, "unknown method");
+    const int rerank = o.rerank == 0 ? 500 : o.rerank;
+    if (o.method == MRQ_METHOD_MRSQ) {
+        if (ix->dq == 0) throw Fail(MRQ_ESTATE, "the index has no MR-SQ codes (build it with sq8 = 1)");
+        if (rerank < 1 || rerank > 16384) throw Fail(MRQ_EINVAL, "rerank must be in [k, 16384]");
+    }
     const int np_cap = std::min(ix->nlist, kMaxProbe);
 
     // per-query k / nprobe on the host (mixed batches)
@@ -505,6 +521,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (uniform_kq) {
         if (k_u < 1 || k_u > kMaxK) throw Fail(MRQ_EINVAL, "k must be in [1, 1024]");
         if (np_u < 1 || np_u > np_cap) throw Fail(MRQ_EINVAL, "nprobe must be in [1, min(nlist, 1024)]");
+        if (o.method == MRQ_METHOD_MRSQ && k_u > rerank) throw Fail(MRQ_EINVAL, "rerank must be in [k, 16384]");
         total_slots = nq * k_u;
         total_pairs = nq * np_u;
         out_total = nq * k_u;
@@ -524,6 +541,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         np_max = 0;
         for (int64_t i = 0; i < nq; i++) {
             if (kh[i] < 1 || kh[i] > kMaxK) throw Fail(MRQ_EINVAL, "k[i] must be in [1, 1024]");
+            if (o.method == MRQ_METHOD_MRSQ && kh[i] > rerank) throw Fail(MRQ_EINVAL, "rerank must be in [k, 16384]");
             if (nph[i] < 1 || nph[i] > np_cap) throw Fail(MRQ_EINVAL, "nprobe[i] must be in [1, min(nlist, 1024)]");
             if (offh[i] < 0) throw Fail(MRQ_EINVAL, "out_off[i] must be >= 0");
             k_max = std::max(k_max, kh[i]);
@@ -554,7 +572,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         *d_s = d_dev ? nullptr : c.take<float>(out_total);
         *cnt_s = cnt_host ? c.take<int64_t>(8) : nullptr;
         *sw = base ? base + c.used : nullptr;
-        *used = c.used + search_workspace_bytes(*ix, nq_run, slots_run, pairs_run, o.bq, np_max);
+        *used = c.used + search_workspace_bytes(*ix, nq_run, slots_run, pairs_run, o.bq, np_max, o.method, rerank);
     };
     int32_t *kq, *npq;
     int64_t *so, *po, *oo, *ids_s, *cnt_s;
@@ -610,6 +628,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.use_ext = o.use_ext;
     a.group = o.group > 0 ? o.group : ix->group_default;
     a.exact_cap = o.exact_cap;
+    a.method = o.method;
+    a.rerank = rerank;
     a.counters = cnt_d;
     if (!per_query) {
         if (uniform_kq) hip_check(launch_uniform_meta(nq, k_u, np_u, kq, npq, so, po, oo, s), "meta");
@@ -705,6 +725,16 @@ std::vector<ArrayRef> device_arrays(Index& ix) {
     };
 }
 
+std::vector<ArrayRef> sq8_arrays(Index& ix) {
+    if (ix.dq == 0) return {};
+    return {
+        {(void**)&ix.sq_lo, sizeof(float) * ix.dq},
+        {(void**)&ix.sq_delta, sizeof(float) * ix.dq},
+        {(void**)&ix.sq_code, (size_t)ix.Npad * ix.dq},
+        {(void**)&ix.sq_A, sizeof(float) * ix.Npad},
+    };
+}
+
 struct File {
     FILE* f;
     explicit File(const char* path, const char* mode) : f(std::fopen(path, mode)) {
@@ -786,6 +816,18 @@ static void export_index(const mrq_index* ix, const char* path) {
         for (int64_t i = 0; i < N; i++) o[i] = v[rows[i]];
         f.w(o.data(), o.size() * 4);
     }
+    if (ix->dq > 0) {  // MR-SQ: grid and codes in natural dimension order
+        const int dq = ix->dq;
+        f.w("SQ8G", 4);
+        f.w(fetch_dev(ix->sq_lo, d).data(), sizeof(float) * d);
+        f.w(fetch_dev(ix->sq_delta, d).data(), sizeof(float) * d);
+        auto code = fetch_dev(ix->sq_code, (size_t)Np * dq);
+        std::vector<uint8_t> u((size_t)N * d);
+        for (int64_t i = 0; i < N; i++)
+            for (int t = 0; t < d; t++)
+                u[(size_t)i * d + t] = code[(size_t)rows[i] * dq + ((t >> 2) & 3) * (dq >> 2) + 4 * (t >> 4) + (t & 3)];
+        f.w(u.data(), u.size());
+    }
 }
 
 }  // namespace mrq
@@ -835,6 +877,7 @@ mrq_status mrq_build(const float* X, int64_t N, int32_t D, int32_t d_r, int32_t 
         mrq_build_opts o;
         mrq_build_opts_default(&o);
         if (opts) o = *opts;
+        if (o.sq8 != 0 && o.sq8 != 1) throw Fail(MRQ_EINVAL, "sq8 must be 0 or 1");
         *out = build_index(X, N, D, d_r, bits, nlist, o, (hipStream_t)stream);
         return MRQ_OK;
     });
@@ -922,15 +965,17 @@ mrq_status mrq_save(const mrq_index* cix, const char* path) {
         mrq_index* ix = const_cast<mrq_index*>(cix);
         hip_check(hipDeviceSynchronize(), "sync");
         File f(path, "wb");
-        f.w("MRQS0002", 8);
+        f.w("MRQS0003", 8);
         int64_t h64[2] = {ix->N, ix->Npad};
-        int32_t h32[6] = {ix->D, ix->d, ix->B, ix->nlist, ix->WP, ix->max_list_len};
+        int32_t h32[7] = {ix->D, ix->d, ix->B, ix->nlist, ix->WP, ix->max_list_len, ix->dq};
         f.w(h64, sizeof(h64));
         f.w(h32, sizeof(h32));
         f.w(ix->lam64.data(), sizeof(double) * ix->D);
         f.w(ix->h_off_real.data(), sizeof(int64_t) * (ix->nlist + 1));
         f.w(ix->h_list_off.data(), sizeof(int64_t) * (ix->nlist + 1));
-        for (auto& a : device_arrays(*ix)) {
+        std::vector<ArrayRef> arrays = device_arrays(*ix), sq = sq8_arrays(*ix);
+        arrays.insert(arrays.end(), sq.begin(), sq.end());
+        for (auto& a : arrays) {
             std::vector<char> h(a.bytes);
             hip_check(hipMemcpy(h.data(), *a.p, a.bytes, hipMemcpyDeviceToHost), "download");
             f.w(h.data(), a.bytes);
@@ -945,11 +990,11 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         File f(path, "rb");
         char magic[8];
         f.r(magic, 8);
-        if (std::memcmp(magic, "MRQS0002", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0002 file");
+        if (std::memcmp(magic, "MRQS0003", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0003 file");
         std::unique_ptr<mrq_index> ix(new mrq_index());
         hip_check(hipGetDevice(&ix->device), "hipGetDevice");
         int64_t h64[2];
-        int32_t h32[6];
+        int32_t h32[7];
         f.r(h64, sizeof(h64));
         f.r(h32, sizeof(h32));
         ix->N = h64[0];
@@ -960,8 +1005,9 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         ix->nlist = h32[3];
         ix->WP = h32[4];
         ix->max_list_len = h32[5];
+        ix->dq = h32[6];
         if (ix->N < 1 || ix->D < 2 || ix->d < 2 || ix->d > ix->D || ix->B < 1 || ix->B > 8 || ix->nlist < 1 ||
-            ix->WP != padded_words(ix->d) || ix->Npad < ix->N)
+            ix->WP != padded_words(ix->d) || ix->Npad < ix->N || (ix->dq != 0 && ix->dq != ((ix->d + 15) & ~15)))
             throw Fail(MRQ_EIO, "corrupt header");
         ix->W = (ix->d + 31) / 32;
         ix->d4 = (ix->d + 3) & ~3;
@@ -972,7 +1018,9 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         ix->h_list_off.resize(ix->nlist + 1);
         f.r(ix->h_off_real.data(), sizeof(int64_t) * (ix->nlist + 1));
         f.r(ix->h_list_off.data(), sizeof(int64_t) * (ix->nlist + 1));
-        for (auto& a : device_arrays(*ix)) {
+        std::vector<ArrayRef> arrays = device_arrays(*ix), sq = sq8_arrays(*ix);
+        arrays.insert(arrays.end(), sq.begin(), sq.end());
+        for (auto& a : arrays) {
             std::vector<char> h(a.bytes);
             f.r(h.data(), a.bytes);
             void* p = nullptr;

@@ -565,6 +565,101 @@ hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, cons
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------------
+// MR-SQ codes (Appendix A.2, Exp-5): 8-bit scalar quantisation of the leading d coordinates of x_p.
+//   grid of coordinate i: [lo_i, hi_i] = min / max of x_{p,i} over the data set, delta_i = (hi_i - lo_i)/255
+//   (1 when hi_i == lo_i); code u_i = min(255, floor((x_i - lo_i) * (1/delta_i) + 1/2)), every step one
+//   IEEE-rounded FP32 operation.  A row's dq = 16 ceil(d / 16) bytes are stored in scan order: dimension
+//   16 t + 4 g + e at byte g (dq / 4) + 4 t + e, so lane group g of the scan reads its bytes contiguously.
+
+// Partial min / max of 64 coordinates over a chunk of rows (real rows only), four row streams per block.
+__global__ __launch_bounds__(256) void k_sq_minmax_part(const float* __restrict__ xd, const int32_t* __restrict__ ids,
+                                                        int64_t Npad, int d, int d4, int64_t rpc,
+                                                        float* __restrict__ plo, float* __restrict__ phi) {
+    __shared__ float slo[4][64], shi[4][64];
+    const int lane = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int64_t r0 = (int64_t)blockIdx.y * rpc, r1 = r0 + rpc < Npad ? r0 + rpc : Npad;
+    float lo = INFINITY, hi = -INFINITY;
+    if (c < d)
+        for (int64_t r = r0 + sub; r < r1; r += 4)
+            if (ids[r] >= 0) {
+                const float v = xd[r * d4 + c];
+                lo = fminf(lo, v);
+                hi = fmaxf(hi, v);
+            }
+    slo[sub][lane] = lo;
+    shi[sub][lane] = hi;
+    __syncthreads();
+    if (sub == 0 && c < d) {
+        for (int t = 1; t < 4; t++) {
+            lo = fminf(lo, slo[t][lane]);
+            hi = fmaxf(hi, shi[t][lane]);
+        }
+        plo[(int64_t)blockIdx.y * d + c] = lo;
+        phi[(int64_t)blockIdx.y * d + c] = hi;
+    }
+}
+
+// The grid of every coordinate from the partials; coordinates d .. dq - 1 get lo 0 and delta 1.
+__global__ void k_sq_grid(const float* __restrict__ plo, const float* __restrict__ phi, int nchunk, int d, int dq,
+                          float* __restrict__ lo, float* __restrict__ delta) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= dq) return;
+    if (c >= d) {
+        lo[c] = 0.f;
+        delta[c] = 1.f;
+        return;
+    }
+    float a = INFINITY, b = -INFINITY;
+    for (int ch = 0; ch < nchunk; ch++) {
+        a = fminf(a, plo[(int64_t)ch * d + c]);
+        b = fmaxf(b, phi[(int64_t)ch * d + c]);
+    }
+    lo[c] = a;
+    delta[c] = b > a ? __fdiv_rn(__fsub_rn(b, a), 255.f) : 1.f;
+}
+
+// One wave per row: the codes, and A = ||xhat_d||^2 + ||x_r||^2 in FP64 (+inf on padding rows, so their
+// estimate is +inf and they are never re-ranked).
+__global__ __launch_bounds__(64) void k_sq_encode(const float* __restrict__ xd, const int32_t* __restrict__ ids,
+                                                  const double* __restrict__ tx64, int d, int d4, int dq,
+                                                  const float* __restrict__ lo, const float* __restrict__ delta,
+                                                  uint8_t* __restrict__ code, float* __restrict__ A) {
+    const int64_t r = blockIdx.x;
+    const int lane = threadIdx.x;
+    const bool real = ids[r] >= 0;
+    double s = 0.0;
+    for (int i = lane; i < dq; i += 64) {
+        int u = 0;
+        if (real && i < d) {
+            const float inv = __fdiv_rn(1.f, delta[i]);
+            const float t = __fadd_rn(__fmul_rn(__fsub_rn(xd[r * d4 + i], lo[i]), inv), 0.5f);
+            u = (int)floorf(t);
+            u = u < 0 ? 0 : (u > 255 ? 255 : u);
+            const double xh = (double)lo[i] + (double)delta[i] * (double)u;
+            s += xh * xh;
+        }
+        code[r * dq + ((i >> 2) & 3) * (dq >> 2) + 4 * (i >> 4) + (i & 3)] = (uint8_t)u;
+    }
+    s = wave_sum_d(s);
+    if (lane == 0) A[r] = real ? (float)(s + tx64[r]) : INFINITY;
+}
+
+hipError_t launch_sq8_build(Index& ix, const double* tx64_rows, float* scratch, int nchunk, hipStream_t s) {
+    const int d = ix.d, dq = ix.dq;
+    const int64_t rpc = (ix.Npad + nchunk - 1) / nchunk;
+    float* plo = scratch;
+    float* phi = scratch + (int64_t)nchunk * d;
+    hipLaunchKernelGGL(k_sq_minmax_part, dim3((unsigned)((d + 63) / 64), (unsigned)nchunk), dim3(256), 0, s, ix.xd,
+                       ix.ids, ix.Npad, d, ix.d4, rpc, plo, phi);
+    hipLaunchKernelGGL(k_sq_grid, dim3((unsigned)((dq + 255) / 256)), dim3(256), 0, s, plo, phi, nchunk, d, dq,
+                       ix.sq_lo, ix.sq_delta);
+    hipLaunchKernelGGL(k_sq_encode, dim3((unsigned)ix.Npad), dim3(64), 0, s, ix.xd, ix.ids, tx64_rows, d, ix.d4, dq,
+                       ix.sq_lo, ix.sq_delta, ix.sq_code, ix.sq_A);
+    return hipGetLastError();
+}
+
 __global__ void k_check_finite(const float* __restrict__ X, int64_t n, int32_t* __restrict__ bad) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         if (!isfinite(X[i])) { atomicOr(bad, 1); return; }

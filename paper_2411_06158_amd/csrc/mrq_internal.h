@@ -96,6 +96,14 @@ struct Index {
     float* X = nullptr;          // Npad x D4 vectors in PCA coordinates x_p = P_p (x - mu), list order
     // export-only per-row summaries (list order)
     float *nx = nullptr, *tx = nullptr, *xi1 = nullptr, *xiB = nullptr, *yn = nullptr;
+    // MR-SQ codes (built on request): dq = 16 ceil(d / 16) (0 = none); per coordinate the grid lo / delta
+    // (dq entries, lo 0 and delta 1 beyond d); per row dq code bytes in scan order; per row
+    // A = ||xhat_d||^2 + ||x_r||^2 (+inf on padding rows)
+    int32_t dq = 0;
+    float* sq_lo = nullptr;
+    float* sq_delta = nullptr;
+    uint8_t* sq_code = nullptr;
+    float* sq_A = nullptr;
 
     // host copies
     std::vector<double> lam64;
@@ -131,6 +139,8 @@ struct SearchArgs {
     float eps0, m;
     int32_t stage2, use_ext, group;
     int64_t exact_cap = 0;  // exact-stage buffer entries per phase (0 = automatic)
+    int32_t method = 0;     // MRQ_METHOD_MRQ or MRQ_METHOD_MRSQ
+    int32_t rerank = 500;   // MR-SQ: candidates re-ranked by exact distance per query
     int64_t* ids;          // device output
     float* dists;          // device output
     int64_t* counters;     // device int64[8] or null
@@ -138,10 +148,13 @@ struct SearchArgs {
 };
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,
-                              int bq, int np_max);
+                              int bq, int np_max, int method, int rerank);
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
 
 // build-side launchers
+// MR-SQ codes of an index whose x_d and ids are in place (tx64_rows: FP64 ||x_r||^2 per row; scratch:
+// 2 nchunk d floats)
+hipError_t launch_sq8_build(Index& ix, const double* tx64_rows, float* scratch, int nchunk, hipStream_t s);
 hipError_t launch_colmean(const float* X, int64_t N, int D, double* part, int nchunk, double* mu64,
                           hipStream_t s);
 hipError_t launch_cov(const float* X, int64_t N, int D, const double* mu64, double* part, int nsplit,

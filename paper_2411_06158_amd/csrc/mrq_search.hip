@@ -1730,6 +1730,288 @@ __global__ void k_finalize(const unsigned long long* __restrict__ slots, const i
 // ------------------------------------------------------------------------------------------------
 // host side: workspace layout and the launch sequence
 
+// ------------------------------------------------------------------------------------------------
+// MR-SQ search (Appendix A.2, Exp-5).  Every candidate of the probed lists gets the estimate
+//   ||xhat_d - q_d||^2 + ||x_r||^2 + ||q_r||^2 = A_x + K_q - 2 <u_x, w_q>,
+//   A_x = ||xhat_d||^2 + ||x_r||^2 (per row, from the build),  K_q = ||q_p||^2 - 2 <lo, q_d>,
+//   w_q = delta (.) q_d  (xhat = lo + delta u, u the 8-bit codes),
+// in FP32; then per query the R candidates with the smallest (estimate, id) get their exact distance.
+// Queries are processed in chunks; a chunk's estimates are written to one buffer, each query's
+// candidates contiguous (its probed lists in probe order, whole 64-row blocks, padding rows +inf).
+
+// One wave per query of the chunk: offsets of its lists in its estimate range, w_q and K_q.
+__global__ __launch_bounds__(64) void k_sq_query(int q0, const int32_t* __restrict__ npq,
+                                                 const int64_t* __restrict__ pair_off,
+                                                 const int32_t* __restrict__ pair_list,
+                                                 const int32_t* __restrict__ list_nb,
+                                                 const int32_t* __restrict__ list_len, const float* __restrict__ qd,
+                                                 int d, int d4, int dq, const float* __restrict__ qn2,
+                                                 const float* __restrict__ lo, const float* __restrict__ delta,
+                                                 float* __restrict__ wq, float* __restrict__ Kq,
+                                                 int32_t* __restrict__ pair_loc, int32_t* __restrict__ qcount,
+                                                 int64_t* __restrict__ counters) {
+    const int qi = blockIdx.x, q = q0 + qi, lane = threadIdx.x;
+    if (lane == 0) {
+        const int64_t pb = pair_off[q];
+        int run = 0;
+        long long real = 0;
+        for (int r = 0; r < npq[q]; r++) {
+            const int j = pair_list[pb + r];
+            pair_loc[pb + r] = run;
+            run += 64 * list_nb[j];
+            real += list_len[j];
+        }
+        qcount[qi] = run;
+        if (counters) atomicAdd((unsigned long long*)&counters[0], (unsigned long long)real);
+    }
+    float s = 0.f;
+    for (int i = lane; i < dq; i += 64) {
+        const float v = i < d ? qd[(int64_t)q * d4 + i] : 0.f;
+        wq[(int64_t)q * dq + i] = i < d ? delta[i] * v : 0.f;
+        s = fmaf(lo[i], v, s);
+    }
+    s = wave_sum(s);
+    if (lane == 0) Kq[q] = fmaf(-2.f, s, qn2[q]);
+}
+
+// Pairs of the chunk bucketed by list (one bucket per list), then placed: sorted pair -> (query, offset of
+// its list in the estimate buffer).
+__global__ void k_sq_pair_count(int q0, const int32_t* __restrict__ npq, const int64_t* __restrict__ pair_off,
+                                const int32_t* __restrict__ pair_list, int32_t* __restrict__ cnt) {
+    const int q = q0 + blockIdx.x;
+    const int64_t pb = pair_off[q];
+    for (int r = threadIdx.x; r < npq[q]; r += blockDim.x) atomicAdd(&cnt[pair_list[pb + r]], 1);
+}
+__global__ void k_sq_pair_place(int q0, const int32_t* __restrict__ npq, const int64_t* __restrict__ pair_off,
+                                const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_loc,
+                                const int32_t* __restrict__ qbase, const int32_t* __restrict__ boff,
+                                int32_t* __restrict__ fill, int32_t* __restrict__ sp_q, int32_t* __restrict__ sp_off) {
+    const int qi = blockIdx.x, q = q0 + qi;
+    const int64_t pb = pair_off[q];
+    for (int r = threadIdx.x; r < npq[q]; r += blockDim.x) {
+        const int j = pair_list[pb + r];
+        const int pos = boff[j] + atomicAdd(&fill[j], 1);
+        sp_q[pos] = q;
+        sp_off[pos] = qbase[qi] + pair_loc[pb + r];
+    }
+}
+
+// The estimates of one work item (64-row block of a list x up to GT of the list's pairs) on the matrix
+// cores: for each 16 x 16 sub-tile a v_mfma_f32_16x16x4_f32 chain over the dq coordinates, A operand the
+// queries' w_q (lane group g feeding coordinates 16 t + 4 g .. + 3 of slice t), B operand the rows' codes
+// converted to FP32 (the bytes of lane group g of a row are contiguous in the scan-order layout).
+// Persistent grid, items dealt round-robin.  TS: 16-coordinate slices per row (0 = any).
+template <int GT, int TS>
+__global__ __launch_bounds__(256) void k_sq_scan(const int32_t* __restrict__ ioff, int nlist, const int4* __restrict__ desc,
+                                                 const int32_t* __restrict__ sp_q, const int32_t* __restrict__ sp_off,
+                                                 const uint8_t* __restrict__ code, const float* __restrict__ A,
+                                                 const int64_t* __restrict__ list_off, const float* __restrict__ wq,
+                                                 const float* __restrict__ Kq, int dq, float* __restrict__ est) {
+    constexpr int NCT = GT / 16;
+    __shared__ int32_t sh_q[4][GT];
+    __shared__ int32_t sh_o[4][GT];
+    __shared__ float sh_k[4][GT];
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    const int li = lane & 15, kg = lane >> 4;
+    const int ts = TS > 0 ? TS : dq >> 4;
+    const int total = (int)const_load((const uint32_t*)(ioff + nlist));
+    const int nwaves = gridDim.x * 4;
+    for (int it = uniform(blockIdx.x * 4 + wv); it < total; it += nwaves) {
+        const int4 dsc = const_load4(desc + it);
+        const int64_t row0 = dsc.x;
+        const int pbeg = dsc.y, ng = dsc.z, j = dsc.w;
+        const int rbase = (int)(row0 - list_off[j]);  // the block's first row within its list
+        if (lane < ng) {
+            const int q = sp_q[pbeg + lane];
+            sh_q[wv][lane] = q;
+            sh_o[wv][lane] = sp_off[pbeg + lane] + rbase;
+            sh_k[wv][lane] = Kq[q];
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int ct = 0; ct < NCT; ct++) {
+            if (16 * ct >= ng) break;
+            // w_q of this lane's query column (slots beyond ng read slot 0; their outputs are not written)
+            const int qs = ct * 16 + li;
+            const float4* wp = reinterpret_cast<const float4*>(wq + (int64_t)sh_q[wv][qs < ng ? qs : 0] * dq + 4 * kg);
+            for (int rt = 0; rt < 4; rt++) {
+                const int64_t row = row0 + 16 * rt + li;
+                const float a = A[row];
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (TS > 0 && TS % 4 == 0) {
+                    const uint4* cp = reinterpret_cast<const uint4*>(code + row * dq + kg * (dq >> 2));
+#pragma unroll
+                    for (int t4 = 0; t4 < TS / 4; t4++) {
+                        const uint4 cw = cp[t4];
+                        const uint32_t w4[4] = {cw.x, cw.y, cw.z, cw.w};
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            const uint32_t c = w4[u];
+                            const float4 x = make_float4((float)(c & 0xFFu), (float)((c >> 8) & 0xFFu),
+                                                         (float)((c >> 16) & 0xFFu), (float)(c >> 24));
+                            mfma4(acc, wp[4 * (4 * t4 + u)], x);
+                        }
+                    }
+                } else {
+                    const uint32_t* cp = reinterpret_cast<const uint32_t*>(code + row * dq + kg * (dq >> 2));
+                    for (int t = 0; t < ts; t++) {
+                        const uint32_t c = cp[t];
+                        const float4 x = make_float4((float)(c & 0xFFu), (float)((c >> 8) & 0xFFu),
+                                                     (float)((c >> 16) & 0xFFu), (float)(c >> 24));
+                        mfma4(acc, wp[4 * t], x);
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int slot = ct * 16 + 4 * kg + v;
+                    if (slot < ng) est[sh_o[wv][slot] + 16 * rt + li] = fmaf(-2.f, acc[v], a + sh_k[wv][slot]);
+                }
+            }
+        }
+        wave_lds_fence();
+    }
+}
+
+// Row of position i of a query's estimate range (its lists' offsets loc[0..np) ascending).
+__device__ __forceinline__ int64_t sq_row_of(int i, const int32_t* loc, const int32_t* lst, int np,
+                                             const int64_t* __restrict__ list_off) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (loc[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return list_off[lst[lo]] + (i - loc[lo]);
+}
+
+// One block per query of the chunk: the R candidates with the smallest (estimate, id) among the finite
+// estimates, found by a radix selection over the order-preserving key bits (8 bits per pass) and, when
+// the boundary estimate is shared, over the ids of those equal to it; their rows are written in any order.
+__global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restrict__ est, const int32_t* __restrict__ qbase,
+                                                   const int32_t* __restrict__ npq, const int64_t* __restrict__ pair_off,
+                                                   const int32_t* __restrict__ pair_list,
+                                                   const int32_t* __restrict__ pair_loc,
+                                                   const int64_t* __restrict__ list_off, const int32_t* __restrict__ ids,
+                                                   int R, int32_t* __restrict__ sel, int32_t* __restrict__ selcnt) {
+    __shared__ int32_t hist[256];
+    __shared__ int32_t s_loc[kMaxProbe], s_lst[kMaxProbe];
+    __shared__ uint32_t s_pre;
+    __shared__ int32_t s_want, s_num, s_eq;
+    const int qi = blockIdx.x, q = q0 + qi, t = threadIdx.x;
+    const int base = qbase[qi], n = qbase[qi + 1] - base;
+    const float* e = est + base;
+    const int np = npq[q];
+    const int64_t pb = pair_off[q];
+    for (int r = t; r < np; r += 256) {
+        s_loc[r] = pair_loc[pb + r];
+        s_lst[r] = pair_list[pb + r];
+    }
+    if (t == 0) s_num = 0;
+    __syncthreads();
+    int fin = 0;
+    for (int i = t; i < n; i += 256) fin += e[i] < INFINITY ? 1 : 0;
+    atomicAdd(&s_num, fin);
+    __syncthreads();
+    const int take = min(R, s_num);
+    __syncthreads();
+    if (take == 0) {
+        if (t == 0) selcnt[qi] = 0;
+        return;
+    }
+    // the take-th smallest key T, and how many of the keys equal to T are taken
+    uint32_t pre = 0, msk = 0;
+    int want = take;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[t] = 0;
+        __syncthreads();
+        for (int i = t; i < n; i += 256) {
+            const float v = e[i];
+            if (!(v < INFINITY)) continue;
+            const uint32_t k = ord_bits(v);
+            if ((k & msk) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1);
+        }
+        __syncthreads();
+        if (t == 0) {
+            int c = 0, b = 0;
+            while (b < 255 && c + hist[b] < want) c += hist[b++];
+            s_want = want - c;
+            s_pre = pre | ((uint32_t)b << shift);
+            s_eq = hist[b];
+        }
+        __syncthreads();
+        want = s_want;
+        pre = s_pre;
+        msk |= 255u << shift;
+        __syncthreads();
+    }
+    const uint32_t T = pre;
+    const bool tie = want < s_eq;  // only some of the keys equal to T are taken: the smallest ids
+    uint32_t idT = 0xFFFFFFFFu;
+    if (tie) {
+        uint32_t ip = 0, im = 0;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            hist[t] = 0;
+            __syncthreads();
+            for (int i = t; i < n; i += 256) {
+                const float v = e[i];
+                if (!(v < INFINITY) || ord_bits(v) != T) continue;
+                const uint32_t id = (uint32_t)ids[sq_row_of(i, s_loc, s_lst, np, list_off)];
+                if ((id & im) == ip) atomicAdd(&hist[(id >> shift) & 255u], 1);
+            }
+            __syncthreads();
+            if (t == 0) {
+                int c = 0, b = 0;
+                while (b < 255 && c + hist[b] < want) c += hist[b++];
+                s_want = want - c;
+                s_pre = ip | ((uint32_t)b << shift);
+            }
+            __syncthreads();
+            want = s_want;
+            ip = s_pre;
+            im |= 255u << shift;
+            __syncthreads();
+        }
+        idT = ip;
+    }
+    if (t == 0) s_num = 0;
+    __syncthreads();
+    int32_t* out = sel + (int64_t)qi * R;
+    for (int i = t; i < n; i += 256) {
+        const float v = e[i];
+        if (!(v < INFINITY)) continue;
+        const uint32_t k = ord_bits(v);
+        if (k > T) continue;
+        const int64_t row = sq_row_of(i, s_loc, s_lst, np, list_off);
+        if (k == T && tie && (uint32_t)ids[row] > idT) continue;
+        const int p = atomicAdd(&s_num, 1);  // exactly `take` positions are taken
+        if (p < R) out[p] = (int32_t)row;
+    }
+    __syncthreads();
+    if (t == 0) selcnt[qi] = min(s_num, R);
+}
+
+// One block per query of the chunk: exact distances ||x_p - q_p||^2 of its re-rank candidates (16 lanes
+// per candidate, as in the exact stage of the MRQ path) into its result slots.
+__global__ __launch_bounds__(256) void k_sq_exact(int q0, const int32_t* __restrict__ sel, const int32_t* __restrict__ selcnt,
+                                                  int R, const float* __restrict__ X, const float* __restrict__ qpad,
+                                                  int D4, const int32_t* __restrict__ ids,
+                                                  const int64_t* __restrict__ slot_off, const int32_t* __restrict__ kq,
+                                                  unsigned long long* __restrict__ slots, int64_t* __restrict__ counters) {
+    const int qi = blockIdx.x, q = q0 + qi, lane = lane_id();
+    const int n = selcnt[qi];
+    const int32_t* rows = sel + (int64_t)qi * R;
+    for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
+        const bool valid = i < n;
+        const int64_t row = rows[valid ? i : 0];
+        const float dist = exact_dist_group(X + row * D4, qpad + (int64_t)q * D4, D4, lane & 15);
+        if (valid && (lane & 15) == 0) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)ids[row];
+            topk_insert(slots + slot_off[q], kq[q], key);
+        }
+    }
+    if (counters && threadIdx.x == 0) atomicAdd((unsigned long long*)&counters[3], (unsigned long long)n);
+}
+
 namespace {
 struct Carve {
     char* p;
@@ -1824,11 +2106,7 @@ struct Timed {
 }  // namespace
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
-                              int np_max) {
-    size_t used = 0;
-    carve(nullptr, ix, nq, total_slots, total_pairs, bq, np_max, &used);
-    return used;
-}
+                              int np_max, int method, int rerank);
 
 template <int WP, int BQT>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
@@ -1943,7 +2221,171 @@ int padded_words(int d) {
         if (e_ != hipSuccess) return e_;        \
     } while (0)
 
+// ---- MR-SQ search (host side) -------------------------------------------------------------------
+
+namespace {
+// A chunk's estimate buffer holds at most this many entries (1 GiB), or one query's worth.
+constexpr int64_t kSqEstCap = (int64_t)1 << 28;
+
+// Estimate entries of one query at most: its probed lists are distinct, each whole 64-row blocks.
+int64_t sq_query_bound(const Index& ix, int np_max) {
+    const int64_t max_nb = (ix.max_list_len + 63) / 64;
+    return std::max<int64_t>(1, std::min<int64_t>(ix.Npad, (int64_t)np_max * 64 * max_nb));
+}
+int64_t sq_chunk(const Index& ix, int64_t nq, int np_max) {
+    return std::max<int64_t>(1, std::min<int64_t>(nq, kSqEstCap / sq_query_bound(ix, np_max)));
+}
+
+struct WsSq {
+    float *qd, *qtail, *qpad, *qn2, *qd2, *Tq, *er, *G, *wq, *Kq, *est;
+    int32_t *pair_list, *pair_q, *pair_loc, *qcount, *qbase, *cnt, *boff, *fill, *items, *ioff, *sp_q, *sp_off;
+    int32_t *sel, *selcnt;
+    int4* desc;
+    unsigned long long* slots;
+};
+
+WsSq carve_sq(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int np_max, int R,
+              size_t* used) {
+    Carve c{reinterpret_cast<char*>(base)};
+    WsSq w;
+    const int64_t ch = sq_chunk(ix, nq, np_max);
+    const int64_t chp = std::min<int64_t>(total_pairs, ch * np_max);  // pairs of one chunk at most
+    const int64_t max_nb = (ix.max_list_len + 63) / 64;
+    const int64_t L = ix.nlist;
+    w.qd = c.take<float>(nq * ix.d4);
+    w.qtail = c.take<float>(nq * (int64_t)(ix.D - ix.d));
+    w.qpad = c.take<float>(nq * ix.D4);
+    w.qn2 = c.take<float>(nq);
+    w.qd2 = c.take<float>(nq);
+    w.Tq = c.take<float>(nq);
+    w.er = c.take<float>(nq);
+    w.G = c.take<float>(nq * L);
+    w.pair_list = c.take<int32_t>(total_pairs);
+    w.pair_q = c.take<int32_t>(total_pairs);
+    w.pair_loc = c.take<int32_t>(total_pairs);
+    w.wq = c.take<float>(nq * ix.dq);
+    w.Kq = c.take<float>(nq);
+    w.qcount = c.take<int32_t>(ch);
+    w.qbase = c.take<int32_t>(ch + 1);
+    w.cnt = c.take<int32_t>(L);
+    w.boff = c.take<int32_t>(L + 1);
+    w.fill = c.take<int32_t>(L);
+    w.items = c.take<int32_t>(L);
+    w.ioff = c.take<int32_t>(L + 1);
+    // work items: sum over lists of blocks * ceil(pairs / G) <= max_nb * pairs / 16 + all blocks (G >= 16)
+    w.desc = c.take<int4>(max_nb * ((chp + 15) / 16) + ix.Npad / 64 + 1);
+    w.sp_q = c.take<int32_t>(chp);
+    w.sp_off = c.take<int32_t>(chp);
+    w.est = c.take<float>(ch * sq_query_bound(ix, np_max));
+    w.sel = c.take<int32_t>(ch * R);
+    w.selcnt = c.take<int32_t>(ch);
+    w.slots = c.take<unsigned long long>(total_slots);
+    *used = c.used;
+    return w;
+}
+}  // namespace
+
+template <int GT, int TS>
+static void launch_sq_scan_t(const WsSq& w, const Index& ix, hipStream_t s, int slot) {
+    const int blocks = std::min(resident_blocks(k_sq_scan<GT, TS>, 256, slot, 0), kMaxScanBlocks);
+    hipLaunchKernelGGL((k_sq_scan<GT, TS>), dim3((unsigned)blocks), dim3(256), 0, s, w.ioff, ix.nlist, w.desc, w.sp_q,
+                       w.sp_off, ix.sq_code, ix.sq_A, ix.list_off, w.wq, w.Kq, ix.dq, w.est);
+}
+template <int GT>
+static void launch_sq_scan_g(const WsSq& w, const Index& ix, hipStream_t s, int slot) {
+    switch (ix.dq) {
+        case 64: launch_sq_scan_t<GT, 4>(w, ix, s, slot); break;
+        case 128: launch_sq_scan_t<GT, 8>(w, ix, s, slot + 1); break;
+        case 256: launch_sq_scan_t<GT, 16>(w, ix, s, slot + 2); break;
+        default: launch_sq_scan_t<GT, 0>(w, ix, s, slot + 3); break;
+    }
+}
+
+size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
+                              int np_max, int method, int rerank) {
+    size_t used = 0;
+    if (method == MRQ_METHOD_MRSQ) carve_sq(nullptr, ix, nq, total_slots, total_pairs, np_max, rerank, &used);
+    else carve(nullptr, ix, nq, total_slots, total_pairs, bq, np_max, &used);
+    return used;
+}
+
+static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
+    const Index& ix = *a.ix;
+    size_t used = 0;
+    WsSq w = carve_sq(ws, ix, a.nq, a.total_slots, a.total_pairs, a.np_max, a.rerank, &used);
+    if (used > ws_bytes) return hipErrorOutOfMemory;
+    KernelTimer* tm = a.timed ? &ix.timer : nullptr;
+    const int64_t nq = a.nq;
+    const int d = ix.d, d4 = ix.d4, D = ix.D, D4 = ix.D4, nlist = ix.nlist, dq = ix.dq;
+    const int G = a.group > 16 ? 32 : 16;
+    {   // the projection and the centroid ranking of the MRQ path
+        Timed t(tm, s, "project");
+        HIP_TRY(launch_fill_f32(w.qd, 0.f, nq * d4, s));
+        HIP_TRY(launch_gemm_mfma<2>(a.Q, D, ix.mu, ix.Pp, D, w.qd, d4, nq, D, D, nullptr, nullptr, w.qtail, D - d, d, s));
+        hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4, w.qtail,
+                           ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
+        HIP_TRY(hipGetLastError());
+    }
+    {
+        Timed t(tm, s, "probe");
+        HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr, 0, 0, s));
+        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, s);
+        HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
+        HIP_TRY(hipGetLastError());
+    }
+    const int64_t ch = sq_chunk(ix, nq, a.np_max);
+    for (int64_t q0 = 0; q0 < nq; q0 += ch) {
+        const int cn = (int)std::min<int64_t>(ch, nq - q0);
+        {   // estimate ranges, w_q, K_q; pairs bucketed by list into work items
+            Timed t(tm, s, "sq_prep");
+            hipLaunchKernelGGL(k_sq_query, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off, w.pair_list,
+                               ix.list_nb, ix.list_len, w.qd, d, d4, dq, w.qn2, ix.sq_lo, ix.sq_delta, w.wq, w.Kq,
+                               w.pair_loc, w.qcount, a.counters);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.qcount, w.qbase, (int64_t)cn);
+            HIP_TRY(launch_fill_i32(w.cnt, 0, nlist, s));
+            HIP_TRY(launch_fill_i32(w.fill, 0, nlist, s));
+            hipLaunchKernelGGL(k_sq_pair_count, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off,
+                               w.pair_list, w.cnt);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, (int64_t)nlist);
+            hipLaunchKernelGGL(k_sq_pair_place, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off,
+                               w.pair_list, w.pair_loc, w.qbase, w.boff, w.fill, w.sp_q, w.sp_off);
+            hipLaunchKernelGGL(k_items, dim3((unsigned)((nlist + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb, nlist,
+                               G, nlist, w.items);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, (int64_t)nlist);
+            hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((nlist + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff,
+                               ix.list_nb, ix.list_off, nlist, G, (int64_t)nlist, w.desc);
+            HIP_TRY(hipGetLastError());
+        }
+        {
+            Timed t(tm, s, "sq_scan");
+            if (G == 16) launch_sq_scan_g<16>(w, ix, s, 24);
+            else launch_sq_scan_g<32>(w, ix, s, 28);
+            HIP_TRY(hipGetLastError());
+        }
+        {
+            Timed t(tm, s, "sq_select");
+            hipLaunchKernelGGL(k_sq_select, dim3((unsigned)cn), dim3(256), 0, s, (int)q0, w.est, w.qbase, a.npq,
+                               a.pair_off, w.pair_list, w.pair_loc, ix.list_off, ix.ids, a.rerank, w.sel, w.selcnt);
+            HIP_TRY(hipGetLastError());
+        }
+        {
+            Timed t(tm, s, "sq_exact");
+            hipLaunchKernelGGL(k_sq_exact, dim3((unsigned)cn), dim3(256), 0, s, (int)q0, w.sel, w.selcnt, a.rerank,
+                               ix.X, w.qpad, D4, ix.ids, a.slot_off, a.kq, w.slots, a.counters);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    {
+        Timed t(tm, s, "finalize");
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)nq), dim3(64), 0, s, w.slots, a.slot_off, a.kq, a.out_off, a.ids,
+                           a.dists);
+        HIP_TRY(hipGetLastError());
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (a.method == MRQ_METHOD_MRSQ) return launch_search_mrsq(a, ws, ws_bytes, s);
     const Index& ix = *a.ix;
     size_t used = 0;
     WsPtrs w = carve(ws, ix, a.nq, a.total_slots, a.total_pairs, a.bq, a.np_max, &used);

@@ -98,10 +98,11 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Device bytes of a batch: metadata, queries, outputs and the search workspace.
-size_t batch_bytes(const mrq::Index& ix, int64_t nq, int64_t slots, int64_t pairs, int np_max, int bq) {
+size_t batch_bytes(const mrq::Index& ix, int64_t nq, int64_t slots, int64_t pairs, int np_max,
+                   const mrq_search_opts& o) {
     size_t b = align256(nq * 4) * 2 + align256((nq + 1) * 8) * 2 + align256(nq * 8);
     b += align256(nq * (size_t)ix.D * 4) + align256(slots * 8) + align256(slots * 4);
-    b += mrq::search_workspace_bytes(ix, nq, slots, pairs, bq, np_max);
+    b += mrq::search_workspace_bytes(ix, nq, slots, pairs, o.bq, np_max, o.method, o.rerank);
     return b;
 }
 
@@ -116,7 +117,7 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
         np_max = std::max(np_max, r.nprobe);
         k_max = std::max(k_max, r.k);
     }
-    const size_t need = batch_bytes(ix, nq, tslots, tpairs, np_max, sv->opts.bq);
+    const size_t need = batch_bytes(ix, nq, tslots, tpairs, np_max, sv->opts);
     if (sl.dev_bytes < need) {
         if (sl.dev) (void)hipFree(sl.dev);
         sl.dev = nullptr;
@@ -187,6 +188,8 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
     a.stage2 = sv->opts.stage2;
     a.use_ext = sv->opts.use_ext;
     a.group = sv->opts.group > 0 ? sv->opts.group : ix.group_default;
+    a.method = sv->opts.method;
+    a.rerank = sv->opts.rerank;
     a.ids = d_ids;
     a.dists = d_d;
     a.counters = nullptr;
@@ -246,7 +249,7 @@ void worker_loop(mrq_server* sv) {
                     const Request& r = sv->queue.front();
                     const int np2 = std::max(np_max, r.nprobe);
                     const size_t need = batch_bytes(*sv->core, (int64_t)sl.reqs.size() + 1, tslots + r.k,
-                                                    tpairs + r.nprobe, np2, sv->opts.bq);
+                                                    tpairs + r.nprobe, np2, sv->opts);
                     if (sv->budget && need + other > sv->budget) break;  // admit later, when memory frees up
                     tslots += r.k;
                     tpairs += r.nprobe;
@@ -311,6 +314,10 @@ mrq_status mrq_server_create(const mrq_index* index, size_t mem_budget, int32_t 
     sv->opts.counters = nullptr;
     sv->opts.mode = MRQ_BATCHED;
     if (sv->opts.bq < 1 || sv->opts.bq > 8) { delete sv; return MRQ_EINVAL; }
+    if (sv->opts.rerank == 0) sv->opts.rerank = 500;
+    if ((sv->opts.method != MRQ_METHOD_MRQ && sv->opts.method != MRQ_METHOD_MRSQ) || sv->opts.rerank < 1 ||
+        sv->opts.rerank > 16384) { delete sv; return MRQ_EINVAL; }
+    if (sv->opts.method == MRQ_METHOD_MRSQ && sv->core->dq == 0) { delete sv; return MRQ_ESTATE; }
     (void)hipSetDevice(sv->core->device);
     for (Slot& sl : sv->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -328,7 +335,8 @@ mrq_status mrq_server_submit(mrq_server* sv, uint64_t req_id, const float* q_hos
     if (!sv || !q_host) return MRQ_EINVAL;
     const mrq::Index& ix = *sv->core;
     if (k < 1 || k > mrq::kMaxK || nprobe < 1 || nprobe > std::min(ix.nlist, mrq::kMaxProbe)) return MRQ_EINVAL;
-    if (sv->budget && batch_bytes(ix, 1, k, nprobe, nprobe, sv->opts.bq) > sv->budget) return MRQ_ENOMEM;
+    if (sv->opts.method == MRQ_METHOD_MRSQ && k > sv->opts.rerank) return MRQ_EINVAL;
+    if (sv->budget && batch_bytes(ix, 1, k, nprobe, nprobe, sv->opts) > sv->budget) return MRQ_ENOMEM;
     Request r;
     r.id = req_id;
     r.k = k;

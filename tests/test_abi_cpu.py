@@ -10,6 +10,8 @@ import pytest
 
 import paper_2411_06158_amd as mrq
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mrq.h")
 
 
@@ -41,6 +43,32 @@ def test_option_defaults():
     mrq.lib().mrq_search_opts_default(C.byref(s))
     assert (s.mode, s.bq, s.stage2, s.use_ext, s.group) == (0, 4, 1, 1, 0)
     assert abs(s.eps0 - 1.9) < 1e-6 and s.m == 3.0
+    assert b.sq8 == 0 and (s.method, s.rerank) == (mrq.MRQ_METHOD_MRQ, 0)
+
+
+def test_option_struct_layout_matches_header(tmp_path):
+    """The binding's option structs have the size and field offsets the C header gives them."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    fields = {"mrq_build_opts": [n for n, _ in mrq.BuildOpts._fields_],
+              "mrq_search_opts": [n for n, _ in mrq.SearchOpts._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mrq.h"', "int main(void) {"]
+    for st, names in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'printf("{st}.{n} %zu\\n", offsetof({st}, {n}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for st, cls in (("mrq_build_opts", mrq.BuildOpts), ("mrq_search_opts", mrq.SearchOpts)):
+        assert int(got[st]) == C.sizeof(cls)
+        for n in fields[st]:
+            assert int(got[f"{st}.{n}"]) == getattr(cls, n).offset, (st, n)
 
 
 def _build(X, N, D, d, B, nlist):
@@ -83,7 +111,7 @@ def test_load_rejects_missing_and_corrupt_files():
         path = f.name
     try:
         assert mrq.lib().mrq_load(path.encode(), C.byref(h)) == mrq.MRQ_EIO
-        assert "MRQS0002" in mrq.lib().mrq_last_error().decode()
+        assert "MRQS0003" in mrq.lib().mrq_last_error().decode()
     finally:
         os.unlink(path)
 

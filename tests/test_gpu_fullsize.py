@@ -23,7 +23,7 @@ import torch  # noqa: E402
 import oracle  # noqa: E402
 import paper_2411_06158_amd as mrq  # noqa: E402
 from paper_2411_06158_amd import synth  # noqa: E402
-from parity import check_rows  # noqa: E402
+from parity import check_mrsq_rows, check_rows  # noqa: E402
 
 SAMPLE = 24
 
@@ -47,7 +47,7 @@ def gist():
 def _index(env, bits):
     if bits not in env["ix"]:
         print(f"[gpu] fullsize: build d=128 B={bits} nlist=4096", flush=True)
-        ix = mrq.Index.build(env["Xd"], d_r=128, bits=bits, nlist=4096)
+        ix = mrq.Index.build(env["Xd"], d_r=128, bits=bits, nlist=4096, sq8=bits == 1)
         with tempfile.TemporaryDirectory(dir=_tmpdir()) as td:
             path = os.path.join(td, "ix.mrqx")
             ix.export(path)
@@ -70,6 +70,21 @@ def test_fullsize_sampled_rows_match_oracle(gist, bits, k, nprobe):
           f"{dict((a, b) for a, b in st.items() if a != 'failures')}", flush=True)
     assert not st["failures"], st["failures"][:5]
     assert st["risk_excused"] + st["tie_excused"] + st["probe_tie"] <= SAMPLE // 4
+
+
+def test_fullsize_mrsq_sampled_rows_match_oracle(gist):
+    """MR-SQ (Appendix A.2, Exp-5) at the same size: 10,000 queries, nprobe 64, R = 500; the estimates of
+    the batch do not fit one buffer, so the queries run in several chunks."""
+    ix, orc = _index(gist, 1)
+    print("[gpu] fullsize: MR-SQ search nq=10000 k=10 nprobe=64 R=500", flush=True)
+    ids, dists = ix.search(gist["Qd"], 10, 64, method=mrq.MRQ_METHOD_MRSQ, rerank=500)
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    rows = np.random.default_rng(3003).choice(ids.shape[0], SAMPLE, replace=False)
+    st = check_mrsq_rows(orc, gist["X"], gist["Q"][rows], ids[rows], dists[rows], 10, 64, 500)
+    print(f"[gpu] fullsize MR-SQ parity: {dict((a, b) for a, b in st.items() if a != 'failures')}", flush=True)
+    assert not st["failures"], st["failures"][:5]
+    assert st["boundary_excused"] + st["probe_tie"] <= SAMPLE // 4
 
 
 def test_fullsize_rows_do_not_depend_on_batch(gist):
