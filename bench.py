@@ -104,6 +104,10 @@ def main():
     ap.add_argument("--requests", type=int, default=20000, help="--serve: requests per rate")
     ap.add_argument("--max-slots", type=int, default=512, help="--serve: queries per batch at most")
     ap.add_argument("--mem-budget", type=float, default=4.0, help="--serve: device GiB for the batch slots")
+    ap.add_argument("--mrsq", default="",
+                    help="comma-separated d_r values: MR-SQ (8-bit scalar codes of the leading d_r dims, exact "
+                         "re-ranking of --rerank candidates; d_r = D is plain SQ) instead of the headline run")
+    ap.add_argument("--rerank", type=int, default=500, help="--mrsq: candidates re-ranked per query")
     ap.add_argument("--sweep-d", default="",
                     help="comma-separated d_r values: QPS at the target recall per projection dimension "
                          "(Exp-4 grid) instead of the headline measurement")
@@ -127,6 +131,9 @@ def main():
         return
     if args.sweep_d:
         sweep_d_main(args, np, torch, mrq, synth, dev)
+        return
+    if args.mrsq:
+        mrsq_main(args, np, torch, mrq, synth, dev)
         return
     t0 = time.time()
     X, Q, spec = synth.workload(args.workload, N=args.N, nq=args.nq)
@@ -381,6 +388,77 @@ def sweep_d_main(args, np, torch, mrq, synth, dev):
                       "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} "
                                              f"bits={args.bits} k={k}", "steps": args.steps},
                       "eq8_d_r": eq8, "grid": rows}), flush=True)
+
+
+def mrsq_main(args, np, torch, mrq, synth, dev):
+    """Exp-5 (Appendix A.2): MR-SQ, the projection and split of MRQ applied to 8-bit scalar quantisation,
+    against plain SQ (d_r = D).  For each d_r of --mrsq: build the index with its MR-SQ codes, find the
+    smallest nprobe whose recall@k reaches --target-recall with --rerank candidates re-ranked per query,
+    and time the batched search there.  Also reports the MRQ search of the same index at its own
+    smallest nprobe for comparison."""
+    X, Q, _ = synth.workload(args.workload, N=args.N, nq=args.nq)
+    N, D = X.shape
+    nq, k, R = Q.shape[0], args.k, args.rerank
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    gt = ground_truth(torch, Xd, Qd, k)
+    ids_buf = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+
+    def measure(ix, opts_kw):
+        chosen, rec = None, None
+        for npb in [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]:
+            if npb > args.nlist:
+                break
+            ix.search(Qd, k, npb, ids=ids_buf, dists=d_buf, **opts_kw)
+            torch.cuda.synchronize()
+            chosen, rec = npb, recall(ids_buf.cpu().numpy(), gt, k)
+            if rec >= args.target_recall:
+                break
+        cnt.zero_()
+        ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf, counters=cnt, **opts_kw)
+        for _ in range(args.warmup):
+            ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf, **opts_kw)
+        ix.timing_enable(True, reset=True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf, **opts_kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - ts
+        ix.timing_enable(False, reset=False)
+        c = cnt.cpu().numpy()
+        return {"nprobe": chosen, "recall_at_k": round(rec, 4), "qps": round(nq * args.steps / el, 1),
+                "ms_per_step": round(1e3 * el / args.steps, 4),
+                "scanned_per_query": round(float(c[0]) / nq, 1), "exact_per_query": round(float(c[3]) / nq, 1),
+                "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in ix.timing().items()}}
+
+    rows = []
+    for d in [int(v) for v in args.mrsq.split(",") if v]:
+        if d < 2 or d > D:
+            continue
+        ix = mrq.Index.build(Xd, d_r=d, bits=args.bits, nlist=args.nlist, sq8=True)
+        r = {"d_r": d, "method": "SQ" if d == D else "MR-SQ", "rerank": R}
+        r.update(measure(ix, dict(method=mrq.MRQ_METHOD_MRSQ, rerank=R)))
+        kt = r["kernel_ms_per_step"]
+        if kt.get("sq_scan"):
+            # estimate scan: per candidate the d_r code bytes + A_x, one FP32 estimate written
+            dq = (d + 15) // 16 * 16
+            r["sq_scan_GBps"] = round(r["scanned_per_query"] * nq * (dq + 4 + 4) / (kt["sq_scan"] * 1e-3) / 1e9, 1)
+        log(f"{r['method']} d_r {d}: nprobe {r['nprobe']} recall {r['recall_at_k']:.4f} {r['qps']:,.0f} QPS")
+        rows.append(r)
+        if d < D:
+            m = {"d_r": d, "method": "MRQ"}
+            m.update(measure(ix, dict(method=mrq.MRQ_METHOD_MRQ)))
+            log(f"MRQ d_r {d}: nprobe {m['nprobe']} recall {m['recall_at_k']:.4f} {m['qps']:,.0f} QPS")
+            rows.append(m)
+        ix.close()
+    print(json.dumps({"metric": f"QPS at recall@{k}={args.target_recall}: MR-SQ vs SQ (1 GPU)", "unit": "queries/s",
+                      "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} k={k}",
+                                 "steps": args.steps, "rerank": R},
+                      "rows": rows}), flush=True)
 
 
 def serve_main(args, np, torch, mrq, synth, dev):
