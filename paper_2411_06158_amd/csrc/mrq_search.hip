@@ -1887,6 +1887,41 @@ __device__ __forceinline__ int64_t sq_row_of(int i, const int32_t* loc, const in
 // One block per query of the chunk: the R candidates with the smallest (estimate, id) among the finite
 // estimates, found by a radix selection over the order-preserving key bits (8 bits per pass) and, when
 // the boundary estimate is shared, over the ids of those equal to it; their rows are written in any order.
+// Every pass reads the query's estimates from global memory (L2), eight loads in flight per thread.
+
+// Radix-selection step (run by the first wave of the block): the bin of hist[256] holding rank `want`
+// (1-based) of the counted keys, by a prefix sum over the lanes (four bins each); the one lane whose
+// range holds the rank writes the rank left within that bin, the extended prefix and the bin's count.
+__device__ __forceinline__ void sq_pick_bin(const int32_t* hist, int want, uint32_t pre, int shift, int lane,
+                                            int32_t* s_want, uint32_t* s_pre, int32_t* s_eq) {
+    const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const int loc = h0 + h1 + h2 + h3;
+    int inc = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    const int exc = inc - loc;
+    if (exc < want && want <= inc) {
+        int c = exc, b = 4 * lane;
+        if (c + h0 < want) {
+            c += h0;
+            b++;
+            if (c + h1 < want) {
+                c += h1;
+                b++;
+                if (c + h2 < want) {
+                    c += h2;
+                    b++;
+                }
+            }
+        }
+        *s_want = want - c;
+        *s_pre = pre | ((uint32_t)b << shift);
+        *s_eq = hist[b];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restrict__ est, const int32_t* __restrict__ qbase,
                                                    const int32_t* __restrict__ npq, const int64_t* __restrict__ pair_off,
                                                    const int32_t* __restrict__ pair_list,
@@ -1900,6 +1935,7 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
     const int qi = blockIdx.x, q = q0 + qi, t = threadIdx.x;
     const int base = qbase[qi], n = qbase[qi + 1] - base;
     const float* e = est + base;
+    const uint32_t kinf = ord_bits(INFINITY);  // keys below it are finite estimates
     const int np = npq[q];
     const int64_t pb = pair_off[q];
     for (int r = t; r < np; r += 256) {
@@ -1908,8 +1944,19 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
     }
     if (t == 0) s_num = 0;
     __syncthreads();
+    // visit every key, eight loads in flight per thread
+    auto each_key = [&](auto&& f) {
+        for (int i0 = t; i0 < n; i0 += 256 * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = i0 + 256 * u < n ? e[i0 + 256 * u] : INFINITY;
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (i0 + 256 * u < n) f(i0 + 256 * u, ord_bits(v[u]));
+        }
+    };
     int fin = 0;
-    for (int i = t; i < n; i += 256) fin += e[i] < INFINITY ? 1 : 0;
+    each_key([&](int, uint32_t k) { fin += k < kinf ? 1 : 0; });
     atomicAdd(&s_num, fin);
     __syncthreads();
     const int take = min(R, s_num);
@@ -1924,20 +1971,11 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
     for (int shift = 24; shift >= 0; shift -= 8) {
         hist[t] = 0;
         __syncthreads();
-        for (int i = t; i < n; i += 256) {
-            const float v = e[i];
-            if (!(v < INFINITY)) continue;
-            const uint32_t k = ord_bits(v);
-            if ((k & msk) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1);
-        }
+        each_key([&](int, uint32_t k) {
+            if (k < kinf && (k & msk) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1);
+        });
         __syncthreads();
-        if (t == 0) {
-            int c = 0, b = 0;
-            while (b < 255 && c + hist[b] < want) c += hist[b++];
-            s_want = want - c;
-            s_pre = pre | ((uint32_t)b << shift);
-            s_eq = hist[b];
-        }
+        if (t < 64) sq_pick_bin(hist, want, pre, shift, t, &s_want, &s_pre, &s_eq);
         __syncthreads();
         want = s_want;
         pre = s_pre;
@@ -1952,19 +1990,13 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
         for (int shift = 24; shift >= 0; shift -= 8) {
             hist[t] = 0;
             __syncthreads();
-            for (int i = t; i < n; i += 256) {
-                const float v = e[i];
-                if (!(v < INFINITY) || ord_bits(v) != T) continue;
+            each_key([&](int i, uint32_t k) {
+                if (k != T) return;
                 const uint32_t id = (uint32_t)ids[sq_row_of(i, s_loc, s_lst, np, list_off)];
                 if ((id & im) == ip) atomicAdd(&hist[(id >> shift) & 255u], 1);
-            }
+            });
             __syncthreads();
-            if (t == 0) {
-                int c = 0, b = 0;
-                while (b < 255 && c + hist[b] < want) c += hist[b++];
-                s_want = want - c;
-                s_pre = ip | ((uint32_t)b << shift);
-            }
+            if (t < 64) sq_pick_bin(hist, want, ip, shift, t, &s_want, &s_pre, &s_eq);
             __syncthreads();
             want = s_want;
             ip = s_pre;
@@ -1976,16 +2008,13 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
     if (t == 0) s_num = 0;
     __syncthreads();
     int32_t* out = sel + (int64_t)qi * R;
-    for (int i = t; i < n; i += 256) {
-        const float v = e[i];
-        if (!(v < INFINITY)) continue;
-        const uint32_t k = ord_bits(v);
-        if (k > T) continue;
+    each_key([&](int i, uint32_t k) {
+        if (k > T) return;  // T < kinf, so the infinite keys are skipped here
         const int64_t row = sq_row_of(i, s_loc, s_lst, np, list_off);
-        if (k == T && tie && (uint32_t)ids[row] > idT) continue;
+        if (k == T && tie && (uint32_t)ids[row] > idT) return;
         const int p = atomicAdd(&s_num, 1);  // exactly `take` positions are taken
         if (p < R) out[p] = (int32_t)row;
-    }
+    });
     __syncthreads();
     if (t == 0) selcnt[qi] = min(s_num, R);
 }
