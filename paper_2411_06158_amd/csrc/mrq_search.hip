@@ -1624,12 +1624,19 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __syncthreads();
     const int s0 = st.k > kSeedFirst ? st.k : kSeedFirst;
     const int s = s0 < nsel ? s0 : nsel;
-    unsigned long long T = 0;  // the s-th smallest key: the largest value with fewer than s keys below it
+    // the s-th smallest key: the largest value with fewer than s keys below it, by a bitwise search over
+    // the keys held in registers (slot u of lane l: key l + 64 u; beyond nsel ~0, never counted); each
+    // step counts with one ballot per slot
+    unsigned long long kr[kSeedMax / 64];
+#pragma unroll
+    for (int u = 0; u < kSeedMax / 64; u++) kr[u] = lane + 64 * u < nsel ? keys[lane + 64 * u] : ~0ull;
+    unsigned long long T = 0;
     for (int b = 63; b >= 0; b--) {
         const unsigned long long t = T | (1ull << b);
         int cnt = 0;
-        for (int i = lane; i < nsel; i += 64) cnt += keys[i] < t;
-        if (wave_sum_i(cnt) < s) T = t;
+#pragma unroll
+        for (int u = 0; u < kSeedMax / 64; u++) cnt += __popcll(__ballot(kr[u] < t));
+        if (cnt < s) T = t;
     }
     // candidates of a round are gathered, in row order, into dense batches of 64 (LDS list `pend`);
     // a batch re-checks each bound against the queue's current tau
