@@ -229,6 +229,12 @@ KernelTimer::~KernelTimer() {
 }
 
 Index::~Index() {
+    if (aux) {
+        (void)hipStreamSynchronize(aux);
+        (void)hipStreamDestroy(aux);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (ws.base) (void)hipFree(ws.base);
     for (void* p : allocations) (void)hipFree(p);
 }

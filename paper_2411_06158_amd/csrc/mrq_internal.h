@@ -119,6 +119,10 @@ struct Index {
     mutable KernelTimer timer;
     mutable std::mutex mu_ws;
     int group_default = 32;
+    // auxiliary stream (default priority) on which the seed pass runs beside the pair preparation, and
+    // the events that fork it from and join it to the search stream; created by the first search
+    mutable hipStream_t aux = nullptr;
+    mutable hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     ~Index();
 };

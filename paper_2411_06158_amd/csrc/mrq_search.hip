@@ -676,32 +676,21 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
     atomicAdd(&cnt[phase_of(r) * nlist + pair_list[pi]], 1);
 }
 
-// One wave per (query, list) pair (Algorithm 2: normalise, rotate and quantise q_d for list j):
+// Query code of one (query, list) pair by one wave (Algorithm 2: normalise, rotate and quantise q_d for
+// list j):
 //   w = P_r^T q_d - P_r^T c_j,  n_q = ||w||,  q' = w / n_q,
 //   v_l = min q', Delta = (max q' - v_l) / (2^bq - 1), u_i = floor((q'_i - v_l) * (1/Delta) + 1/2)
 // (each step one IEEE-rounded FP32 operation, no contraction); bit plane b of u is written as d-bit
-// masks, together with the pair's scalars.
+// masks (planes: bq x WP words), the levels as signed bytes (qbyte: KP bytes, or null), and the pair's
+// scalars (lane 0 writes *rec).  NH: dims per lane (lane l holds l, l + 64, ...); any NH >= ceil(d / 64)
+// gives the same values.
 template <int NH>
-__global__ __launch_bounds__(256) void k_pair_prep(
-    const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
-    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
-    const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
-    const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
-    const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
-    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int8_t* __restrict__ qu8,
-    int32_t* __restrict__ pair_pos) {
-    const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
-    if (pi >= npairs) return;
-    const int lane = threadIdx.x & 63;
-    const int q = pair_q[pi];
-    const int j = pair_list[pi];
-    const int r = (int)(pi - pair_off[q]);
-    const int p = phase_of(r);
-    int pos = 0;
-    if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
-    pos = __shfl(pos, 0);
-    if (lane == 0) pair_pos[pi] = pos;
-    constexpr int nh = NH;  // dims per lane (lane l holds dims l, l + 64, ...)
+__device__ __forceinline__ void pair_code(int lane, int q, int j, const float* __restrict__ rq,
+                                          const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
+                                          const float* __restrict__ Tq, const float* __restrict__ er,
+                                          const float* __restrict__ qn2, int KP, PairRec* rec, uint32_t* pl,
+                                          int8_t* qbyte) {
+    constexpr int nh = NH;
     float wv[NH];
     float n2 = 0.f;
 #pragma unroll
@@ -748,8 +737,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(
         for (int h = 0; h < nh; h++) uv[h] = 0;
     }
     su = wave_sum_i(su);
-    {   // levels as signed bytes for the i8 matrix-core scan (u - 128 when bq = 8), zero beyond d
-        int8_t* qbyte = qu8 + (int64_t)pos * KP;
+    if (qbyte) {  // levels as signed bytes for the i8 matrix-core scan (u - 128 when bq = 8), zero beyond d
         const int ob = bq == 8 ? 128 : 0;
 #pragma unroll
         for (int h = 0; h < NH; h++) {
@@ -757,7 +745,6 @@ __global__ __launch_bounds__(256) void k_pair_prep(
             if (i < KP) qbyte[i] = (int8_t)(i < d ? uv[h] - ob : 0);
         }
     }
-    uint32_t* pl = planes + (int64_t)pos * bq * WP;
     for (int b = 0; b < bq; b++) {
 #pragma unroll
         for (int h = 0; h < (NH > 0 ? NH : 1); h++) {
@@ -784,8 +771,33 @@ __global__ __launch_bounds__(256) void k_pair_prep(
         R.qn2 = qn2[q];
         R.pad = 0.f;
         if (!(hi > lo)) { R.vl = nq > 0.f ? lo : 0.f; }
-        recs[pos] = R;
+        *rec = R;
     }
+}
+
+// One wave per (query, list) pair: its slot in the (phase, list) bucket and its query code.
+template <int NH>
+__global__ __launch_bounds__(256) void k_pair_prep(
+    const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
+    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
+    const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
+    const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
+    const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
+    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int8_t* __restrict__ qu8,
+    int32_t* __restrict__ pair_pos) {
+    const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
+    if (pi >= npairs) return;
+    const int lane = threadIdx.x & 63;
+    const int q = pair_q[pi];
+    const int j = pair_list[pi];
+    const int r = (int)(pi - pair_off[q]);
+    const int p = phase_of(r);
+    int pos = 0;
+    if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
+    pos = __shfl(pos, 0);
+    if (lane == 0) pair_pos[pi] = pos;
+    pair_code<NH>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos,
+                  planes + (int64_t)pos * bq * WP, qu8 + (int64_t)pos * KP);
 }
 
 __global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_nb, int nlist,
@@ -911,6 +923,12 @@ struct ScanCtx {
     int2* surv;          // exact-stage candidates of the current phase: (row, query), rs per scan wave
     int32_t* wcnt;       // candidates produced by each scan wave (the first rs are in its region)
     int64_t* counters;
+    // inputs of the seed pass's own pair code (it runs beside the pair preparation)
+    const int32_t* pair_list;
+    const float* rq;
+    const float* RC;
+    const float* Tq;
+    float eps0;
     int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, rs;
 };
 
@@ -1524,13 +1542,12 @@ struct QueryState {
 // refinement, Eq 7 re-check, exact distances four at a time, then a merge of the new keys into the
 // sorted queue and the new tau.
 template <int WP>
-__device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, int pos, bool pass, int64_t row,
+__device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
                            QueryState& st, unsigned long long* nk, int lane, long long* n1, long long* next,
                            long long* n2) {
     *n1 += __popcll(__ballot(pass));
     const bool open = st.tau == INFINITY;  // every test passes until the queue holds k results
     if (pass && !open && c.B > 1 && c.use_ext) {
-        const uint32_t* U = c.planes + (int64_t)pos * c.bq * WP;
         const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
                                 c.fEB[row], c.fSX[row], R, U, c.bq);
         pass = lb < st.tau;
@@ -1608,10 +1625,15 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     st.have = 0;
     st.tau = INFINITY;
     const float er = c.er[q];
-    const int pos = c.pair_pos[c.pair_off[q]];
-    const PairRec R = c.recs[pos];
-    const uint32_t* U = c.planes + (int64_t)pos * (BQT > 0 ? BQT : c.bq) * WP;
-    const int j = R.list;
+    // the query code of the pair (q, nearest list), computed here into LDS
+    __shared__ PairRec sh_R;
+    __shared__ uint32_t sh_U[8 * WP];
+    const int j = c.pair_list[c.pair_off[q]];
+    pair_code<(WP <= 2 ? 1 : WP / 2)>(lane, q, j, c.rq, c.RC, c.d, c.d4, WP, c.bq, c.eps0, c.Tq, c.er, c.qn2, 0, &sh_R,
+                                     sh_U, nullptr);
+    __syncthreads();
+    const PairRec R = sh_R;
+    const uint32_t* U = sh_U;
     const int n = c.list_len[j];
     const int64_t base = c.list_off[j];
     const int nsel = n < kSeedMax ? n : kSeedMax;
@@ -1646,7 +1668,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         const bool in = lane < cnt;
         const int i = in ? pend_row[lane] : 0;
         const float lb = in ? pend_lb[lane] : INFINITY;
-        seed_batch<WP>(c, q, er, R, pos, in && lb < st.tau, base + i, st, nk, lane, &n1, &next, &n2);
+        seed_batch<WP>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, lane, &n1, &next, &n2);
         const int rest = np - cnt;  // move the remaining entries to the front
         int r_row = 0;
         float r_lb = 0.f;
@@ -2451,6 +2473,38 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, s);
         HIP_TRY(hipGetLastError());
     }
+    ScanCtx c;
+    c.recs = w.recs; c.planes = w.planes; c.qu8 = w.qu8; c.boff = w.boff; c.ioff = w.ioff; c.desc = w.desc;
+    c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.list_len = ix.list_len; c.code = ix.code; c.ext = ix.ext;
+    c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
+    c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
+    c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
+    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.claims = w.claims; c.counters = a.counters;
+    c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0;
+    c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
+    c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
+    c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
+    // persistent scan grid (resident blocks) and each scan wave's share of the exact-stage buffer
+    const int scan_blocks = scan_grid(c);
+    int64_t cap = surv_capacity(ix, a.total_pairs);
+    if (a.exact_cap > 0 && a.exact_cap < cap) cap = a.exact_cap;
+    c.rs = (int)(cap / (4ll * scan_blocks));
+    // The seed pass (each query's nearest list; it computes that pair's query code itself) runs on the
+    // index's auxiliary stream beside the pair preparation; the phases wait for both.
+    HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
+    if (!ix.aux) {
+        HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ix.ev_join, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(ix.ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(ix.aux, ix.ev_fork, 0));
+    {
+        Timed t(tm, ix.aux, "seed");
+        launch_seed(c, nq, ix.aux);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipEventRecord(ix.ev_join, ix.aux));
     {   // per-pair query codes, grouped by (phase, list)
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
@@ -2478,29 +2532,9 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, P);
         hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff, ix.list_nb,
                            ix.list_off, nlist, G, P, w.desc);
-        HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
         HIP_TRY(hipGetLastError());
     }
-    ScanCtx c;
-    c.recs = w.recs; c.planes = w.planes; c.qu8 = w.qu8; c.boff = w.boff; c.ioff = w.ioff; c.desc = w.desc;
-    c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.list_len = ix.list_len; c.code = ix.code; c.ext = ix.ext;
-    c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
-    c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
-    c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
-    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.claims = w.claims; c.counters = a.counters;
-    c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
-    c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
-    c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
-    // persistent scan grid (resident blocks) and each scan wave's share of the exact-stage buffer
-    const int scan_blocks = scan_grid(c);
-    int64_t cap = surv_capacity(ix, a.total_pairs);
-    if (a.exact_cap > 0 && a.exact_cap < cap) cap = a.exact_cap;
-    c.rs = (int)(cap / (4ll * scan_blocks));
-    {
-        Timed t(tm, s, "seed");
-        launch_seed(c, nq, s);
-        HIP_TRY(hipGetLastError());
-    }
+    HIP_TRY(hipStreamWaitEvent(s, ix.ev_join, 0));
     for (int p = 1; p < kPhases; p++) {
         if (a.np_max <= phase_lo(p)) break;
         c.phase = p;
