@@ -164,18 +164,32 @@ def main():
         t2 = time.time()
         gt = ground_truth(torch, Xd, Qd, k)
         log(f"ground truth {time.time() - t2:.1f}s")
+        # the smallest nprobe reaching the target: a coarse grid, then every value between the last one
+        # below the target and the first one reaching it
         cands = [args.nprobe] if args.nprobe else [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
-        for npb in cands:
-            if npb > args.nlist:
-                break
+
+        def try_np(npb):
             run(npb)
             torch.cuda.synchronize()
             r = recall(ids_buf.cpu().numpy(), gt, k)
             sweep.append((npb, r))
             log(f"nprobe {npb}: recall@{k} {r:.4f}")
+            return r
+
+        prev = 0
+        for npb in cands:
+            if npb > args.nlist:
+                break
+            r = try_np(npb)
             chosen, rec_at = npb, r
             if r >= args.target_recall:
+                for fine in range(prev + 1, npb):
+                    rf = try_np(fine)
+                    if rf >= args.target_recall:
+                        chosen, rec_at = fine, rf
+                        break
                 break
+            prev = npb
     if not chosen:
         chosen = 64
 

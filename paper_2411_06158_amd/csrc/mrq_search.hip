@@ -463,16 +463,19 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
 }
 
 // ------------------------------------------------------------------------------------------------
-// Exclusive prefix sum of an int32 array in one workgroup (1024 threads x 16 items per pass).
+// Exclusive prefix sum of an int32 array in one workgroup (256 threads x 16 items per pass).  One wave
+// per SIMD, so it finds room on a CU beside the long-lived waves of a concurrent kernel.
 
-__global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                   int64_t n) {
-    __shared__ int32_t wsum[16];
+constexpr int kScanThreads = 256;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_excl(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                           int64_t n) {
+    __shared__ int32_t wsum[kScanThreads / 64];
     __shared__ int32_t carry_s;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     if (t == 0) carry_s = 0;
     __syncthreads();
-    for (int64_t base = 0; base < n; base += 1024 * 16) {
+    for (int64_t base = 0; base < n; base += kScanThreads * 16) {
         int32_t v[16];
         int32_t tot = 0;
         const int64_t b0 = base + (int64_t)t * 16;
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_scan_excl(const int32_t* __restrict__ 
             run += v[i];
         }
         __syncthreads();
-        if (t == 1023) carry_s = run;
+        if (t == kScanThreads - 1) carry_s = run;
         __syncthreads();
     }
     if (t == 0) out[n] = carry_s;
@@ -2399,17 +2402,17 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
             hipLaunchKernelGGL(k_sq_query, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off, w.pair_list,
                                ix.list_nb, ix.list_len, w.qd, d, d4, dq, w.qn2, ix.sq_lo, ix.sq_delta, w.wq, w.Kq,
                                w.pair_loc, w.qcount, a.counters);
-            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.qcount, w.qbase, (int64_t)cn);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.qcount, w.qbase, (int64_t)cn);
             HIP_TRY(launch_fill_i32(w.cnt, 0, nlist, s));
             HIP_TRY(launch_fill_i32(w.fill, 0, nlist, s));
             hipLaunchKernelGGL(k_sq_pair_count, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off,
                                w.pair_list, w.cnt);
-            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, (int64_t)nlist);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, (int64_t)nlist);
             hipLaunchKernelGGL(k_sq_pair_place, dim3((unsigned)cn), dim3(64), 0, s, (int)q0, a.npq, a.pair_off,
                                w.pair_list, w.pair_loc, w.qbase, w.boff, w.fill, w.sp_q, w.sp_off);
             hipLaunchKernelGGL(k_items, dim3((unsigned)((nlist + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb, nlist,
                                G, nlist, w.items);
-            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, (int64_t)nlist);
+            hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.items, w.ioff, (int64_t)nlist);
             hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((nlist + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff,
                                ix.list_nb, ix.list_off, nlist, G, (int64_t)nlist, w.desc);
             HIP_TRY(hipGetLastError());
@@ -2512,7 +2515,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         HIP_TRY(launch_fill_i32(w.claims, 0, kPhases * kClaimGroups, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.cnt, w.boff, P);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
         const int KP = 64 * nh;
         const dim3 gp((unsigned)((a.total_pairs + 3) / 4));
@@ -2529,7 +2532,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
 #undef PREP
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
                            nlist, G, (int)P, w.items);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, w.items, w.ioff, P);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.items, w.ioff, P);
         hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff, ix.list_nb,
                            ix.list_off, nlist, G, P, w.desc);
         HIP_TRY(hipGetLastError());
