@@ -95,7 +95,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="skip GT/sweep/baselines (profiler runs)")
     ap.add_argument("--group", type=int, default=0,
-                    help="queries per scan work item (16, 32 or 64; 0 = autotune on the batch before timing)")
+                    help="queries per scan work item (16, 32 or 64); with --phase-growth skips the autotuner")
+    ap.add_argument("--phase-growth", type=int, default=0,
+                    help="probe-rank phase growth (2, 4 or 8); with --group skips the autotuner")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--serve", action="store_true",
@@ -153,7 +155,7 @@ def main():
     d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
 
     def run(nprobe, counters=None, mode=mrq.MRQ_BATCHED, Qs=None, ib=None, db=None):
-        o = mrq.search_opts(mode=mode, counters=counters, group=args.group)
+        o = mrq.search_opts(mode=mode, counters=counters, group=args.group, phase_growth=args.phase_growth)
         Qs = Qd if Qs is None else Qs
         return ix.search(Qs, k, nprobe, ids=ids_buf if ib is None else ib, dists=d_buf if db is None else db,
                          opts=o)
@@ -164,8 +166,9 @@ def main():
         t2 = time.time()
         gt = ground_truth(torch, Xd, Qd, k)
         log(f"ground truth {time.time() - t2:.1f}s")
-        # the smallest nprobe reaching the target: a coarse grid, then every value between the last one
-        # below the target and the first one reaching it
+        # the smallest nprobe reaching the target: a coarse grid, the autotuner at its first value reaching
+        # the target, then (with the tuned schedule) every value between the last one below the target and
+        # that one
         cands = [args.nprobe] if args.nprobe else [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
 
         def try_np(npb):
@@ -180,14 +183,8 @@ def main():
         for npb in cands:
             if npb > args.nlist:
                 break
-            r = try_np(npb)
-            chosen, rec_at = npb, r
-            if r >= args.target_recall:
-                for fine in range(prev + 1, npb):
-                    rf = try_np(fine)
-                    if rf >= args.target_recall:
-                        chosen, rec_at = fine, rf
-                        break
+            chosen, rec_at = npb, try_np(npb)
+            if rec_at >= args.target_recall:
                 break
             prev = npb
     if not chosen:
@@ -201,13 +198,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # the autotuner picks the scan schedule (query-group size) on this batch; results do not depend on it
-    if args.group:
-        group = args.group
-        log(f"query group: {group}")
+    # the autotuner picks the scan schedule (query-group size, phase growth) on this batch; the group size
+    # never changes a result, the phase growth only where an error bound fails
+    if args.group and args.phase_growth:
+        group, growth = args.group, args.phase_growth
+        log(f"query group {group}, phase growth {growth}")
     else:
-        group = ix.tune(Qd, k, chosen)
-        log(f"autotuned query group: {group}")
+        group, growth = ix.tune(Qd, k, chosen)
+        log(f"autotuned query group {group}, phase growth {growth}")
+    if not args.profile_only:
+        if chosen is not None and rec_at is not None and rec_at >= args.target_recall:
+            for fine in list(range(prev + 1, chosen)) + [chosen] if not args.nprobe else [chosen]:
+                rf = try_np(fine)
+                if rf >= args.target_recall or fine == chosen:
+                    chosen, rec_at = fine, rf
+                    break
 
     # timed region: W warm-up steps, then K steps with per-kernel HIP events and device counters
     for _ in range(args.warmup):
@@ -326,7 +331,7 @@ def main():
                                f"bits={args.bits} k={k}",
                    "N": N, "D": D, "nq": nq, "nlist": args.nlist, "d_r": args.d, "bits": args.bits, "k": k,
                    "nprobe": chosen, "recall_at_10": None if rec_at is None else round(rec_at, 4),
-                   "query_group": group,
+                   "query_group": group, "phase_growth": growth,
                    "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -378,7 +383,7 @@ def sweep_d_main(args, np, torch, mrq, synth, dev):
             chosen, rec = npb, recall(ids_buf.cpu().numpy(), gt, k)
             if rec >= args.target_recall:
                 break
-        group = ix.tune(Qd, k, chosen)
+        group, growth = ix.tune(Qd, k, chosen)
         for _ in range(args.warmup):
             ix.search(Qd, k, chosen, ids=ids_buf, dists=d_buf)
         ix.timing_enable(True, reset=True)
@@ -391,7 +396,7 @@ def sweep_d_main(args, np, torch, mrq, synth, dev):
         ix.timing_enable(False, reset=False)
         kt = ix.timing()
         row = {"d_r": d, "nprobe": chosen, "recall_at_k": round(rec, 4), "qps": round(nq * args.steps / el, 1),
-               "query_group": group, "build_s": round(build_s, 2),
+               "query_group": group, "phase_growth": growth, "build_s": round(build_s, 2),
                "index_gib": round(ix.device_bytes / 2**30, 3),
                "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in kt.items()}}
         log(f"d_r {d}: nprobe {chosen} recall {rec:.4f} {row['qps']:,.0f} QPS")

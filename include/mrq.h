@@ -94,7 +94,11 @@ typedef struct {
                                [k, 16384]; 0 = 500.  The MRQ fields bq, eps0, m, stage2, use_ext, group
                                and exact_cap do not apply to MR-SQ; counters [0] and [3] count its
                                scanned candidates and exact distances */
-    int32_t reserved[2];
+    int32_t phase_growth;   /* MRQ: probe ranks are scanned in phases [1, g), [g, g^2), ... (after the nearest
+                               list), each against the threshold tau reached before it; g in {2, 4, 8}, 0 =
+                               the index default (4, or what mrq_tune chose).  A result may differ between
+                               values only where an error bound fails */
+    int32_t reserved[1];
 } mrq_search_opts;
 
 /* Defaults for the option structs (pass NULL to any call to use them). */
@@ -142,13 +146,14 @@ mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_
 
 /*
  * mrq_tune — autotuner of the scan schedule: runs mrq_search on Q (nq queries, host or device) with each
- * query-group size of the scan work items (16, 32, 64 queries per 64-vector block), times each on
- * `stream` with HIP events, and makes the fastest the index's default (used when
- * mrq_search_opts.group is 0).  Results do not depend on the schedule.  Synchronous; `group` (may be
- * NULL) receives the choice.  The index must not be in use by another call meanwhile.
+ * query-group size of the scan work items (16, 32, 64 queries per 64-vector block) and each phase growth
+ * (2, 4, 8), times each on `stream` with HIP events, and makes the fastest pair the index's default (used
+ * when mrq_search_opts.group / phase_growth are 0).  The group size never changes a result; the phase
+ * growth can only where an error bound fails.  Synchronous; `group` and `phase_growth` (either may be
+ * NULL) receive the choice.  The index must not be in use by another call meanwhile.
  */
 mrq_status mrq_tune(mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe, mrq_stream stream,
-                    int32_t *group);
+                    int32_t *group, int32_t *phase_growth);
 
 /*
  * mrq_search_mixed — as mrq_search, with a per-query k[i] and nprobe[i] (host or device int32

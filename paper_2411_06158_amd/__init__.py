@@ -41,7 +41,7 @@ class SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("bq", C.c_int32), ("eps0", C.c_float), ("m", C.c_float),
                 ("stage2", C.c_int32), ("use_ext", C.c_int32), ("counters", C.c_void_p),
                 ("group", C.c_int32), ("exact_cap", C.c_int32), ("method", C.c_int32), ("rerank", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("phase_growth", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 _lib = None
@@ -80,7 +80,7 @@ def lib() -> C.CDLL:
             L.mrq_server_destroy.restype = None
         L.mrq_choose_dr.argtypes = [P, I32]
         L.mrq_choose_dr.restype = I32
-        L.mrq_tune.argtypes = [P, P, I64, I32, I32, P, P]
+        L.mrq_tune.argtypes = [P, P, I64, I32, I32, P, P, P]
         _lib = L
     return _lib
 
@@ -120,13 +120,13 @@ def _stream(stream) -> Optional[int]:
 
 
 def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=True, counters=None,
-                group=0, exact_cap=0, method=MRQ_METHOD_MRQ, rerank=0) -> SearchOpts:
+                group=0, exact_cap=0, method=MRQ_METHOD_MRQ, rerank=0, phase_growth=0) -> SearchOpts:
     o = SearchOpts()
     lib().mrq_search_opts_default(C.byref(o))
     o.mode, o.bq, o.eps0, o.m = int(mode), int(bq), float(eps0), float(m)
     o.stage2, o.use_ext, o.group = int(bool(stage2)), int(bool(use_ext)), int(group)
     o.exact_cap = int(exact_cap)
-    o.method, o.rerank = int(method), int(rerank)
+    o.method, o.rerank, o.phase_growth = int(method), int(rerank), int(phase_growth)
     o.counters = _ptr(counters) if counters is not None else None
     return o
 
@@ -206,11 +206,13 @@ class Index:
                                       _ptr(dists), C.byref(o), _stream(stream)))
         return ids, dists, off
 
-    def tune(self, Q, k: int, nprobe: int, stream=None) -> int:
-        """Time the scan schedules on queries Q and keep the fastest as this index's default."""
-        g = C.c_int32(0)
-        _check(lib().mrq_tune(self._h, _ptr(Q), int(Q.shape[0]), k, nprobe, _stream(stream), C.byref(g)))
-        return g.value
+    def tune(self, Q, k: int, nprobe: int, stream=None):
+        """Time the scan schedules (query group, phase growth) on queries Q and keep the fastest as this
+        index's default; returns (group, phase_growth)."""
+        g, p = C.c_int32(0), C.c_int32(0)
+        _check(lib().mrq_tune(self._h, _ptr(Q), int(Q.shape[0]), k, nprobe, _stream(stream), C.byref(g),
+                              C.byref(p)))
+        return g.value, p.value
 
     def timing_enable(self, on: bool = True, reset: bool = True):
         _check(lib().mrq_timing_enable(self._h, int(on), int(reset)))

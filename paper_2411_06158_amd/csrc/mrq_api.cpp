@@ -512,6 +512,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (o.group < 0 || o.group > 64) throw Fail(MRQ_EINVAL, "group must be in [0, 64]");
     if (o.exact_cap < 0) throw Fail(MRQ_EINVAL, "exact_cap must be >= 0");
     if (o.method != MRQ_METHOD_MRQ && o.method != MRQ_METHOD_MRSQ) throw Fail(MRQ_EINVAL, "unknown method");
+    if (o.phase_growth != 0 && o.phase_growth != 2 && o.phase_growth != 4 && o.phase_growth != 8)
+        throw Fail(MRQ_EINVAL, "phase_growth must be 0, 2, 4 or 8");
     const int rerank = o.rerank == 0 ? 500 : o.rerank;
     if (o.method == MRQ_METHOD_MRSQ) {
         if (ix->dq == 0) throw Fail(MRQ_ESTATE, "the index has no MR-SQ codes (build it with sq8 = 1)");
@@ -636,6 +638,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.exact_cap = o.exact_cap;
     a.method = o.method;
     a.rerank = rerank;
+    a.phase_shift = o.phase_growth == 2 ? 1 : (o.phase_growth == 4 ? 2 : (o.phase_growth == 8 ? 3 : ix->phase_shift_default));
     a.counters = cnt_d;
     if (!per_query) {
         if (uniform_kq) hip_check(launch_uniform_meta(nq, k_u, np_u, kq, npq, so, po, oo, s), "meta");
@@ -898,7 +901,7 @@ mrq_status mrq_search(const mrq_index* index, const float* Q, int64_t nq, int32_
 }
 
 mrq_status mrq_tune(mrq_index* index, const float* Q, int64_t nq, int32_t k, int32_t nprobe, mrq_stream stream,
-                    int32_t* group) {
+                    int32_t* group, int32_t* phase_growth) {
     return guarded([&]() {
         if (!index || !Q) throw Fail(MRQ_EINVAL, "index and Q must not be NULL");
         if (nq < 1 || k < 1 || k > kMaxK || nprobe < 1) throw Fail(MRQ_EINVAL, "bad nq, k or nprobe");
@@ -907,31 +910,41 @@ mrq_status mrq_tune(mrq_index* index, const float* Q, int64_t nq, int32_t k, int
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
-        const int cands[3] = {16, 32, 64};
-        int best = index->group_default;
-        float best_ms = 0.f;
+        const int groups[3] = {16, 32, 64}, growths[3] = {2, 4, 8};
+        int best_g = index->group_default, best_p = 1 << index->phase_shift_default;
+        float best_ms = -1.f;
         mrq_search_opts o;
         mrq_search_opts_default(&o);
         mrq_status st = MRQ_OK;
-        for (int g : cands) {
-            o.group = g;
-            for (int rep = 0; rep < 2 && st == MRQ_OK; rep++) {  // the first run warms the workspace
-                if (rep == 1) hip_check(hipEventRecord(e0, s), "event");
-                st = run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids.as<int64_t>(),
-                                dd.as<float>(), &o, s);
-                if (rep == 1) hip_check(hipEventRecord(e1, s), "event");
+        for (int pg : growths) {
+            for (int g : groups) {
+                o.group = g;
+                o.phase_growth = pg;
+                for (int rep = 0; rep < 2 && st == MRQ_OK; rep++) {  // the first run warms the workspace
+                    if (rep == 1) hip_check(hipEventRecord(e0, s), "event");
+                    st = run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids.as<int64_t>(),
+                                    dd.as<float>(), &o, s);
+                    if (rep == 1) hip_check(hipEventRecord(e1, s), "event");
+                }
+                if (st != MRQ_OK) break;
+                hip_check(hipEventSynchronize(e1), "event");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+                if (best_ms < 0.f || ms < best_ms) {
+                    best_ms = ms;
+                    best_g = g;
+                    best_p = pg;
+                }
             }
             if (st != MRQ_OK) break;
-            hip_check(hipEventSynchronize(e1), "event");
-            float ms = 0.f;
-            hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
-            if (g == cands[0] || ms < best_ms) { best_ms = ms; best = g; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st != MRQ_OK) return st;
-        index->group_default = best;
-        if (group) *group = best;
+        index->group_default = best_g;
+        index->phase_shift_default = best_p == 2 ? 1 : (best_p == 4 ? 2 : 3);
+        if (group) *group = best_g;
+        if (phase_growth) *phase_growth = best_p;
         return MRQ_OK;
     });
 }

@@ -119,6 +119,7 @@ struct Index {
     mutable KernelTimer timer;
     mutable std::mutex mu_ws;
     int group_default = 32;
+    int phase_shift_default = 2;  // log2 of the default phase growth
     // auxiliary stream (default priority) on which the seed pass runs beside the pair preparation, and
     // the events that fork it from and join it to the search stream; created by the first search
     mutable hipStream_t aux = nullptr;
@@ -144,6 +145,7 @@ struct SearchArgs {
     int32_t stage2, use_ext, group;
     int64_t exact_cap = 0;  // exact-stage buffer entries per phase (0 = automatic)
     int32_t method = 0;     // MRQ_METHOD_MRQ or MRQ_METHOD_MRSQ
+    int32_t phase_shift = 2;  // phases [1, 2^s), [2^s, 2^2s), ... of the probe ranks
     int32_t rerank = 500;   // MR-SQ: candidates re-ranked by exact distance per query
     int64_t* ids;          // device output
     float* dists;          // device output

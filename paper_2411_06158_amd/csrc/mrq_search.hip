@@ -171,9 +171,10 @@ __device__ void topk_insert(unsigned long long* slots, int k, unsigned long long
     }
 }
 
-// Probe-rank phases: rank 0 (the seed pass), then [1, 2), [2, 4), [4, 8), ... [512, 1024).
-__device__ __forceinline__ int phase_of(int r) { return r == 0 ? 0 : 32 - __clz(r); }
-__host__ __device__ __forceinline__ int phase_lo(int p) { return p == 0 ? 0 : (1 << (p - 1)); }
+// Probe-rank phases for a growth g = 2^sh: rank 0 (the seed pass), then [1, g), [g, g^2), ... up to
+// rank 1023 (at most 10 more phases).
+__device__ __forceinline__ int phase_of(int r, int sh) { return r == 0 ? 0 : (32 - __clz(r) + sh - 1) / sh; }
+__host__ __device__ __forceinline__ int phase_lo(int p, int sh) { return p == 0 ? 0 : (1 << (sh * (p - 1))); }
 
 // ------------------------------------------------------------------------------------------------
 // fill helpers (kernels rather than memset nodes so the sequence can be captured in a graph)
@@ -670,13 +671,13 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
 // Pair bucketing by (phase, list) and per-pair query codes.
 
 __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
-                             const int64_t* __restrict__ pair_off, int64_t npairs, int nlist,
+                             const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh,
                              int32_t* __restrict__ cnt) {
     int64_t pi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (pi >= npairs) return;
     const int q = pair_q[pi];
     const int r = (int)(pi - pair_off[q]);
-    atomicAdd(&cnt[phase_of(r) * nlist + pair_list[pi]], 1);
+    atomicAdd(&cnt[phase_of(r, sh) * nlist + pair_list[pi]], 1);
 }
 
 // Query code of one (query, list) pair by one wave (Algorithm 2: normalise, rotate and quantise q_d for
@@ -782,7 +783,7 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
 template <int NH>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
-    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, const float* __restrict__ rq,
+    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh, const float* __restrict__ rq,
     const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
     const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
     const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
@@ -794,7 +795,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     const int q = pair_q[pi];
     const int j = pair_list[pi];
     const int r = (int)(pi - pair_off[q]);
-    const int p = phase_of(r);
+    const int p = phase_of(r, sh);
     int pos = 0;
     if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
     pos = __shfl(pos, 0);
@@ -2514,14 +2515,14 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
         HIP_TRY(launch_fill_i32(w.claims, 0, kPhases * kClaimGroups, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
-                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, w.cnt);
+                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
         const int KP = 64 * nh;
         const dim3 gp((unsigned)((a.total_pairs + 3) / 4));
 #define PREP(NHV)                                                                                          \
     hipLaunchKernelGGL(k_pair_prep<NHV>, gp, dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, \
-                       nlist, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP,   \
+                       nlist, a.phase_shift, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP,   \
                        w.recs, w.planes, w.qu8, w.pair_pos)
         if (nh <= 1) PREP(1);
         else if (nh <= 2) PREP(2);
@@ -2539,7 +2540,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     }
     HIP_TRY(hipStreamWaitEvent(s, ix.ev_join, 0));
     for (int p = 1; p < kPhases; p++) {
-        if (a.np_max <= phase_lo(p)) break;
+        if (a.np_max <= phase_lo(p, a.phase_shift)) break;
         c.phase = p;
         {
             Timed t(tm, s, "tau");

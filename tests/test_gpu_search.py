@@ -253,13 +253,27 @@ def test_exact_buffer_overflow_gives_same_results(small, small_ext):
         assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
 
 
+@pytest.mark.parametrize("growth", [2, 4, 8])
 @pytest.mark.parametrize("group", [16, 32, 64])
-def test_group_size_does_not_change_results(small, group):
+def test_group_size_does_not_change_results(small, group, growth):
     ix, Q = small["ix"], small["Q"]
-    a_ids, a_d = ix.search(Q, 10, 16)
-    b_ids, b_d = ix.search(Q, 10, 16, opts=mrq.search_opts(group=group))
+    a_ids, a_d = ix.search(Q, 10, 16, opts=mrq.search_opts(group=16, phase_growth=growth))
+    b_ids, b_d = ix.search(Q, 10, 16, opts=mrq.search_opts(group=group, phase_growth=growth))
     assert np.array_equal(a_ids, b_ids)
     assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+
+
+@pytest.mark.parametrize("growth", [2, 4, 8])
+def test_phase_growth_rows_match_oracle(small, growth):
+    """Phases [1, g), [g, g^2), ...: any growth gives the oracle's result wherever the bounds hold."""
+    ids, dists = _search(small, 10, 32, phase_growth=growth)
+    _assert_parity(small, ids, dists, 10, 32)
+
+
+def test_phase_growth_rejects_other_values(small):
+    with pytest.raises(mrq.MRQError) as e:
+        small["ix"].search(small["Q"][:2], 10, 8, phase_growth=3)
+    assert e.value.status == mrq.MRQ_EINVAL
 
 
 def test_eight_bit_codes_and_query_levels():
@@ -302,9 +316,9 @@ def test_automatic_dr_follows_eq8():
 
 def test_tuner_picks_a_schedule_and_keeps_results(small):
     ix, Q = small["ix"], small["Q"]
-    a_ids, a_d = ix.search(Q, 10, 16)
-    g = ix.tune(Q, 10, 16)
-    assert g in (16, 32, 64)
-    b_ids, b_d = ix.search(Q, 10, 16)
+    g, p = ix.tune(Q, 10, 16)
+    assert g in (16, 32, 64) and p in (2, 4, 8)
+    a_ids, a_d = ix.search(Q, 10, 16, opts=mrq.search_opts(group=16, phase_growth=p))
+    b_ids, b_d = ix.search(Q, 10, 16)  # the tuned defaults
     assert np.array_equal(a_ids, b_ids)
     assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
