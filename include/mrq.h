@@ -136,6 +136,11 @@ mrq_status mrq_build(const float *X, int64_t N, int32_t D, int32_t d_r, int32_t 
  *   Q      nq x D FP32 (host or device);  nq >= 1;  1 <= k <= 1024;  1 <= nprobe <= min(nlist, 1024)
  *   ids    nq x k int64 output (host or device);  dists  nq x k FP32 output (host or device)
  * The result of a query does not depend on the other queries of the batch nor on `mode`.
+ * The call may be recorded into a HIP graph (stream capture on `stream`) when Q, ids, dists and counters
+ * are device buffers, kernel timing is off and the same search (same nq, k, nprobe, options) ran once
+ * before on this index, which sizes its workspace; otherwise MRQ_ESTATE.  Replays use the index's
+ * workspace and must not overlap other searches on the index; a later search that needs a larger
+ * workspace keeps the captured one allocated until mrq_free.
  * With opts->method = MRQ_METHOD_MRSQ (index built with sq8, else MRQ_ESTATE): for every candidate of
  * the probed lists the estimate ||xhat_d - q_d||^2 + ||x_r||^2 + ||q_r||^2 (xhat_i = lo_i + delta_i u_i,
  * FP32), then per query the R candidates with the smallest (estimate, id) get their exact distance and

@@ -236,6 +236,7 @@ Index::~Index() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ws.base) (void)hipFree(ws.base);
+    for (void* p : ws.retired) (void)hipFree(p);
     for (void* p : allocations) (void)hipFree(p);
 }
 
@@ -520,6 +521,19 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         if (rerank < 1 || rerank > 16384) throw Fail(MRQ_EINVAL, "rerank must be in [k, 16384]");
     }
     const int np_cap = std::min(ix->nlist, kMaxProbe);
+    // Stream capture (a HIP graph of the search): only device-side work may be recorded, so a captured
+    // search takes device buffers, a uniform k / nprobe, no kernel timing, and the workspace sized by an
+    // earlier search of the same shape; it is not ordered against other searches on the index.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(s, &cap), "capture status");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    if (capturing) {
+        if (!uniform_kq) throw Fail(MRQ_ESTATE, "a search with per-query k / nprobe cannot be captured");
+        if (!is_device_ptr(Q) || !is_device_ptr(ids) || !is_device_ptr(dists) ||
+            (o.counters && !is_device_ptr(o.counters)))
+            throw Fail(MRQ_ESTATE, "a captured search needs device Q, ids, dists and counters");
+        if (ix->timer.on) throw Fail(MRQ_ESTATE, "turn kernel timing off before capturing a search");
+    }
 
     // per-query k / nprobe on the host (mixed batches)
     std::vector<int32_t> kh, nph;
@@ -589,13 +603,17 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     size_t need = 0;
     layout(nullptr, &need, &kq, &npq, &so, &po, &oo, &qs, &ids_s, &d_s, &cnt_s, &sw);
     std::lock_guard<std::mutex> lock(ix->mu_ws);
-    if (ix->ws_event_recorded) hip_check(hipStreamWaitEvent(s, ix->ws_event, 0), "order workspace");
+    if (capturing && ix->ws.bytes < need)
+        throw Fail(MRQ_ESTATE, "run the same search once before capturing it (its workspace cannot grow during capture)");
+    if (ix->ws_event_recorded && !capturing) hip_check(hipStreamWaitEvent(s, ix->ws_event, 0), "order workspace");
     if (ix->ws.bytes < need) {
         if (ix->ws.base) {
             hip_check(hipDeviceSynchronize(), "sync before workspace growth");
-            (void)hipFree(ix->ws.base);
+            if (ix->ws.captured) ix->ws.retired.push_back(ix->ws.base);  // graphs may still replay on it
+            else (void)hipFree(ix->ws.base);
             ix->ws.base = nullptr;
             ix->ws.bytes = 0;
+            ix->ws.captured = false;
         }
         size_t grow = need + need / 4;
         hip_check(hipMalloc(&ix->ws.base, grow), "hipMalloc (search workspace)");
@@ -679,8 +697,12 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
             hip_check(launch_search(a, sw, sw_bytes, s), "search");
         }
     }
-    hip_check(hipEventRecord(ix->ws_event, s), "record");
-    ix->ws_event_recorded = true;
+    if (!capturing) {
+        hip_check(hipEventRecord(ix->ws_event, s), "record");
+        ix->ws_event_recorded = true;
+    } else {
+        ix->ws.captured = true;
+    }
     if (!ids_dev || !d_dev || cnt_host) {
         if (!ids_dev) hip_check(hipMemcpyAsync(ids, ids_s, out_total * 8, hipMemcpyDeviceToHost, s), "copy ids");
         if (!d_dev) hip_check(hipMemcpyAsync(dists, d_s, out_total * 4, hipMemcpyDeviceToHost, s), "copy dists");

@@ -59,6 +59,8 @@ struct Workspace {
     // grow-only device scratch for one search call
     void* base = nullptr;
     size_t bytes = 0;
+    bool captured = false;       // a captured graph refers to `base`: growth must not free it
+    std::vector<void*> retired;  // earlier buffers kept for captured graphs, freed with the index
 };
 
 struct Index {

@@ -322,3 +322,46 @@ def test_tuner_picks_a_schedule_and_keeps_results(small):
     b_ids, b_d = ix.search(Q, 10, 16)  # the tuned defaults
     assert np.array_equal(a_ids, b_ids)
     assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
+
+
+def test_search_replays_from_a_captured_graph(small):
+    """The search recorded into a HIP graph (stream capture) gives the eager result on every replay, with
+    eager searches on the same index and synchronisations between the replays; a later search that grows
+    the workspace keeps the captured one valid."""
+    ix, Qd = small["ix"], small["Qd"]
+    opts = mrq.search_opts(group=16, phase_growth=4)
+    ids = torch.empty((Qd.shape[0], 10), dtype=torch.int64, device="cuda")
+    dd = torch.empty((Qd.shape[0], 10), dtype=torch.float32, device="cuda")
+    s = torch.cuda.Stream()
+    ix.search(Qd, 10, 16, ids=ids, dists=dd, opts=opts, stream=s)  # sizes the workspace
+    torch.cuda.synchronize()
+    ref_i, ref_d = ids.clone(), dd.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        ix.search(Qd, 10, 16, ids=ids, dists=dd, opts=opts, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        ids.fill_(-7)
+        dd.fill_(-1.0)
+        ix.search(Qd[:5 + rep].contiguous(), 5, 4, opts=opts)  # eager work on the index between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ids, ref_i), rep
+        assert torch.equal(dd.view(torch.int32), ref_d.view(torch.int32)), rep
+    ix.search(torch.cat([Qd, Qd, Qd]).contiguous(), 20, 32, opts=opts)  # grows the workspace
+    torch.cuda.synchronize()
+    ids.fill_(-7)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ref_i)
+
+
+def test_capture_refuses_host_buffers(small):
+    ix, Q = small["ix"], small["Q"]
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(mrq.MRQError) as e:
+        with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+            ix.search(Q, 10, 8, stream=s)  # host Q and outputs need copies: not capturable
+    assert e.value.status == mrq.MRQ_ESTATE
