@@ -623,7 +623,8 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         int taken = 0;
         for (int u = 0; u < V && taken < np - nless; u++) {
             const int j = t + 256 * u;
-            const bool eq = j < nlist && v[u] == T;
+            // re-read rather than index v (a runtime index would move v out of registers)
+            const bool eq = j < nlist && __float_as_uint(g[j]) == T;
             const unsigned long long bm = __ballot(eq);
             if (lane == 0) s_wt[w] = __popcll(bm);
             __syncthreads();
@@ -685,8 +686,8 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
 //   w = P_r^T q_d - P_r^T c_j,  n_q = ||w||,  q' = w / n_q,
 //   v_l = min q', Delta = (max q' - v_l) / (2^bq - 1), u_i = floor((q'_i - v_l) * (1/Delta) + 1/2)
 // (each step one IEEE-rounded FP32 operation, no contraction); bit plane b of u is written as d-bit
-// masks (planes: bq x WP words), the levels as signed bytes (qbyte: KP bytes, or null), and the pair's
-// scalars (lane 0 writes *rec).  NH: dims per lane (lane l holds l, l + 64, ...); any NH >= ceil(d / 64)
+// masks (pl: bq x WP words, or null), the levels as signed bytes (qbyte: KP bytes, or null), and the
+// pair's scalars (lane 0 writes *rec).  NH: dims per lane (lane l holds l, l + 64, ...); any NH >= ceil(d / 64)
 // gives the same values.
 template <int NH>
 __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* __restrict__ rq,
@@ -749,7 +750,7 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
             if (i < KP) qbyte[i] = (int8_t)(i < d ? uv[h] - ob : 0);
         }
     }
-    for (int b = 0; b < bq; b++) {
+    for (int b = 0; pl && b < bq; b++) {
 #pragma unroll
         for (int h = 0; h < (NH > 0 ? NH : 1); h++) {
             unsigned long long bm = __ballot(((uv[h] >> b) & 1) != 0);
@@ -779,7 +780,8 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
     }
 }
 
-// One wave per (query, list) pair: its slot in the (phase, list) bucket and its query code.
+// One wave per (query, list) pair: its slot in the (phase, list) bucket and its query code (the level
+// bytes the scan multiplies; the seed pass builds the bit planes of its own pairs).
 template <int NH>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
@@ -787,8 +789,7 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
     const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
     const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
-    PairRec* __restrict__ recs, uint32_t* __restrict__ planes, int8_t* __restrict__ qu8,
-    int32_t* __restrict__ pair_pos) {
+    PairRec* __restrict__ recs, int8_t* __restrict__ qu8, int32_t* __restrict__ pair_pos) {
     const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
     if (pi >= npairs) return;
     const int lane = threadIdx.x & 63;
@@ -800,8 +801,8 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
     pos = __shfl(pos, 0);
     if (lane == 0) pair_pos[pi] = pos;
-    pair_code<NH>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos,
-                  planes + (int64_t)pos * bq * WP, qu8 + (int64_t)pos * KP);
+    pair_code<NH>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
+                  qu8 + (int64_t)pos * KP);
 }
 
 __global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_nb, int nlist,
@@ -898,7 +899,6 @@ __device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const
 
 struct ScanCtx {
     const PairRec* recs;
-    const uint32_t* planes;
     const int8_t* qu8;   // per pair: KP signed bytes u_i - ob (0 beyond d), i8 matrix-core operand
     const int32_t* boff;
     const int32_t* ioff;
@@ -923,7 +923,6 @@ struct ScanCtx {
     const int64_t* pair_off;
     const int32_t* pair_pos;
     unsigned long long* slots;
-    int32_t* claims;     // per (phase, claim group): items of the group's range taken so far
     int2* surv;          // exact-stage candidates of the current phase: (row, query), rs per scan wave
     int32_t* wcnt;       // candidates produced by each scan wave (the first rs are in its region)
     int64_t* counters;
@@ -1081,7 +1080,6 @@ __device__ __forceinline__ f32x4 dot_tile_x(const float4 (&xa)[SU], const float*
 // keeps the compiler from moving them).
 __device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-constexpr int kClaimGroups = 64;
 
 // LDS staging of an item's q_d rows for stage 2 (QL): rows of d4 floats, d4 a multiple of 64, float4
 // column f of pair slot s stored at f ^ (s & 15), so the 16 lanes of a lane group read 16 different banks.
@@ -1540,13 +1538,16 @@ struct QueryState {
     unsigned long long* tk[2];
     int cur, have, k;
     float tau;
+    // the current / other queue, selected without indexing the pointer pair (which would put it in scratch)
+    __device__ __forceinline__ unsigned long long* now() const { return cur ? tk[1] : tk[0]; }
+    __device__ __forceinline__ unsigned long long* other() const { return cur ? tk[0] : tk[1]; }
 };
 
 // One batch of at most 64 candidates (one per lane; `pass` = passed stage 1 against st.tau): B-bit
 // refinement, Eq 7 re-check, exact distances four at a time, then a merge of the new keys into the
 // sorted queue and the new tau.
 template <int WP>
-__device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
+__device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
                            QueryState& st, unsigned long long* nk, int lane, long long* n1, long long* next,
                            long long* n2) {
     *n1 += __popcll(__ballot(pass));
@@ -1584,8 +1585,8 @@ __device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, 
     const int mnew = __popcll(__ballot(sv != kEmptyKey));
     nk[lane] = sv;
     __syncthreads();
-    const unsigned long long* src = st.tk[st.cur];
-    unsigned long long* dst = st.tk[st.cur ^ 1];
+    const unsigned long long* src = st.now();
+    unsigned long long* dst = st.other();
     for (int i = lane; i < st.have; i += 64) {  // existing key: rank among the new keys
         const unsigned long long e = src[i];
         int lo = 0, hi = mnew;
@@ -1600,7 +1601,7 @@ __device__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, 
     __syncthreads();
     st.cur ^= 1;
     st.have = st.have + mnew < st.k ? st.have + mnew : st.k;
-    if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.tk[st.cur][st.k - 1] >> 32));
+    if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.now()[st.k - 1] >> 32));
 }
 
 template <int WP, int BQT>
@@ -1668,7 +1669,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     // a batch re-checks each bound against the queue's current tau
     const unsigned long long lt = (1ull << lane) - 1ull;
     int np = 0;
-    auto flush = [&](int cnt) {
+    auto flush = [&](int cnt) __attribute__((always_inline)) {
         const bool in = lane < cnt;
         const int i = in ? pend_row[lane] : 0;
         const float lb = in ? pend_lb[lane] : INFINITY;
@@ -1682,7 +1683,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         __syncthreads();
         np = rest;
     };
-    auto append = [&](bool take, int i, float lb) {
+    auto append = [&](bool take, int i, float lb) __attribute__((always_inline)) {
         const unsigned long long m = __ballot(take);
         if (take) {
             const int at = np + __popcll(m & lt);
@@ -1719,7 +1720,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     }
     if (np > 0) flush(np);
     unsigned long long* slots = c.slots + c.slot_off[q];
-    for (int i = lane; i < st.k; i += 64) slots[i] = i < st.have ? st.tk[st.cur][i] : kEmptyKey;
+    for (int i = lane; i < st.k; i += 64) slots[i] = i < st.have ? st.now()[i] : kEmptyKey;
     if (c.counters && lane == 0) {
         atomicAdd((unsigned long long*)&c.counters[4], (unsigned long long)n);
         atomicAdd((unsigned long long*)&c.counters[5], (unsigned long long)n1);
@@ -2089,10 +2090,9 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
-    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt, *claims;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt;
     int4* desc;
     PairRec* recs;
-    uint32_t* planes;
     int8_t* qu8;
     unsigned long long* slots;
     int2* surv;
@@ -2142,11 +2142,9 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.ioff = c.take<int32_t>(P + 1);
     w.desc = c.take<int4>(max_items(ix, total_pairs));
     w.recs = c.take<PairRec>(total_pairs);
-    w.planes = c.take<uint32_t>(total_pairs * bq * ix.WP);
     w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
     w.slots = c.take<unsigned long long>(total_slots);
     w.wcnt = c.take<int32_t>(4 * kMaxScanBlocks);
-    w.claims = c.take<int32_t>(kPhases * kClaimGroups);
     const int64_t cap = surv_capacity(ix, total_pairs);
     w.surv = c.take<int2>(cap);
     *used = c.used;
@@ -2478,12 +2476,12 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         HIP_TRY(hipGetLastError());
     }
     ScanCtx c;
-    c.recs = w.recs; c.planes = w.planes; c.qu8 = w.qu8; c.boff = w.boff; c.ioff = w.ioff; c.desc = w.desc;
+    c.recs = w.recs; c.qu8 = w.qu8; c.boff = w.boff; c.ioff = w.ioff; c.desc = w.desc;
     c.list_off = ix.list_off; c.list_nb = ix.list_nb; c.list_len = ix.list_len; c.code = ix.code; c.ext = ix.ext;
     c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
     c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
-    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.claims = w.claims; c.counters = a.counters;
+    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.counters = a.counters;
     c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
@@ -2513,7 +2511,6 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
-        HIP_TRY(launch_fill_i32(w.claims, 0, kPhases * kClaimGroups, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
@@ -2523,7 +2520,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
 #define PREP(NHV)                                                                                          \
     hipLaunchKernelGGL(k_pair_prep<NHV>, gp, dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, \
                        nlist, a.phase_shift, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP,   \
-                       w.recs, w.planes, w.qu8, w.pair_pos)
+                       w.recs, w.qu8, w.pair_pos)
         if (nh <= 1) PREP(1);
         else if (nh <= 2) PREP(2);
         else if (nh <= 4) PREP(4);
