@@ -464,28 +464,38 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
 }
 
 // ------------------------------------------------------------------------------------------------
-// Exclusive prefix sum of an int32 array in one workgroup (256 threads x 16 items per pass).  One wave
-// per SIMD, so it finds room on a CU beside the long-lived waves of a concurrent kernel.
+// Exclusive prefix sum of an int32 array in one workgroup (256 threads x 64 items per pass, so the
+// (phase, list) buckets of the phases a search uses take one pass).  One wave per SIMD, so it finds room
+// on a CU beside the long-lived waves of a concurrent kernel.
 
 constexpr int kScanThreads = 256;
+constexpr int kScanItems = 64;
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const int32_t* __restrict__ in, int32_t* __restrict__ out,
                                                            int64_t n) {
     __shared__ int32_t wsum[kScanThreads / 64];
     __shared__ int32_t carry_s;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     if (t == 0) carry_s = 0;
     __syncthreads();
-    for (int64_t base = 0; base < n; base += kScanThreads * 16) {
-        int32_t v[16];
+    for (int64_t base = 0; base < n; base += kScanThreads * kScanItems) {
+        int32_t v[kScanItems];
         int32_t tot = 0;
-        const int64_t b0 = base + (int64_t)t * 16;
+        const int64_t b0 = base + (int64_t)t * kScanItems;
+        const bool full = vec && b0 + kScanItems <= n;
+        if (full) {
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
-            int64_t idx = b0 + i;
-            v[i] = idx < n ? in[idx] : 0;
-            tot += v[i];
+            for (int i = 0; i < kScanItems / 4; i++) {
+                const int4 x = reinterpret_cast<const int4*>(in + b0)[i];
+                v[4 * i] = x.x; v[4 * i + 1] = x.y; v[4 * i + 2] = x.z; v[4 * i + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanItems; i++) v[i] = b0 + i < n ? in[b0 + i] : 0;
         }
+#pragma unroll
+        for (int i = 0; i < kScanItems; i++) tot += v[i];
         int32_t incl = tot;
         for (int o = 1; o < 64; o <<= 1) {
             int32_t y = __shfl_up(incl, o);
@@ -497,10 +507,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const int32_t* __res
         for (int i = 0; i < w; i++) woff += wsum[i];
         int32_t run = carry_s + woff + incl - tot;
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
-            int64_t idx = b0 + i;
-            if (idx < n) out[idx] = run;
-            run += v[i];
+        for (int i = 0; i < kScanItems; i++) {
+            const int32_t x = v[i];
+            v[i] = run;
+            run += x;
+        }
+        if (full) {
+#pragma unroll
+            for (int i = 0; i < kScanItems / 4; i++)
+                reinterpret_cast<int4*>(out + b0)[i] = make_int4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kScanItems; i++)
+                if (b0 + i < n) out[b0 + i] = v[i];
         }
         __syncthreads();
         if (t == kScanThreads - 1) carry_s = run;
@@ -681,87 +700,123 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
     atomicAdd(&cnt[phase_of(r, sh) * nlist + pair_list[pi]], 1);
 }
 
-// Query code of one (query, list) pair by one wave (Algorithm 2: normalise, rotate and quantise q_d for
-// list j):
+// Query code of one (query, list) pair by a group of L lanes (Algorithm 2: normalise, rotate and quantise
+// q_d for list j):
 //   w = P_r^T q_d - P_r^T c_j,  n_q = ||w||,  q' = w / n_q,
 //   v_l = min q', Delta = (max q' - v_l) / (2^bq - 1), u_i = floor((q'_i - v_l) * (1/Delta) + 1/2)
 // (each step one IEEE-rounded FP32 operation, no contraction); bit plane b of u is written as d-bit
-// masks (pl: bq x WP words, or null), the levels as signed bytes (qbyte: KP bytes, or null), and the
-// pair's scalars (lane 0 writes *rec).  NH: dims per lane (lane l holds l, l + 64, ...); any NH >= ceil(d / 64)
-// gives the same values.
-template <int NH>
+// masks (pl: bq x WP words, or null; L = 64 only), the levels as signed bytes (qbyte: KP bytes, or null),
+// and the pair's scalars (the group's first lane writes *rec).
+// The dims follow a 64-lane layout (virtual lane v holds v, v + 64, ..., NH of them; any NH >= ceil(d / 64)
+// gives the same values); lane g of the group holds virtual lanes g, g + L, ....  ||w||^2 is summed per
+// virtual lane, then by the xor butterfly of wave_sum (steps 32, 16, ..., 1), its steps o >= L inside the
+// lane, so every L gives the same bits.
+template <int NH, int L>
 __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* __restrict__ rq,
                                           const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
                                           const float* __restrict__ Tq, const float* __restrict__ er,
                                           const float* __restrict__ qn2, int KP, PairRec* rec, uint32_t* pl,
                                           int8_t* qbyte) {
-    constexpr int nh = NH;
-    float wv[NH];
-    float n2 = 0.f;
+    static_assert(L == 16 || L == 32 || L == 64, "lanes per pair");
+    constexpr int V = 64 / L;
+    const int g = lane & (L - 1);
+    float wv[V][NH];
+    float pv[V];
 #pragma unroll
-    for (int h = 0; h < nh; h++) {
-        int i = lane + 64 * h;
-        float v = 0.f;
-        if (i < d) v = __fsub_rn(rq[(int64_t)q * d4 + i], RC[(int64_t)j * d4 + i]);
-        wv[h] = v;
-        n2 = fmaf(v, v, n2);
+    for (int t = 0; t < V; t++) {
+        pv[t] = 0.f;
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int i = g + L * t + 64 * h;
+            float v = 0.f;
+            if (i < d) v = __fsub_rn(rq[(int64_t)q * d4 + i], RC[(int64_t)j * d4 + i]);
+            wv[t][h] = v;
+            pv[t] = fmaf(v, v, pv[t]);
+        }
     }
-    n2 = wave_sum(n2);
+#pragma unroll
+    for (int o = 32; o >= L; o >>= 1) {  // butterfly steps between virtual lanes of one lane
+        float nv[V];
+#pragma unroll
+        for (int t = 0; t < V; t++) nv[t] = pv[t] + pv[t ^ (o / L)];
+#pragma unroll
+        for (int t = 0; t < V; t++) pv[t] = nv[t];
+    }
+    float n2 = pv[0];
+#pragma unroll
+    for (int o = L / 2; o >= 1; o >>= 1) n2 += __shfl_xor(n2, o);
     const float nq = sqrtf(n2);
     float lo = FLT_MAX, hi = -FLT_MAX;
 #pragma unroll
-    for (int h = 0; h < nh; h++) {
-        int i = lane + 64 * h;
-        float v = nq > 0.f ? __fdiv_rn(wv[h], nq) : 0.f;
-        wv[h] = v;
-        if (i < d) { lo = fminf(lo, v); hi = fmaxf(hi, v); }
+    for (int t = 0; t < V; t++) {
+#pragma unroll
+        for (int h = 0; h < NH; h++) {
+            const int i = g + L * t + 64 * h;
+            const float v = nq > 0.f ? __fdiv_rn(wv[t][h], nq) : 0.f;
+            wv[t][h] = v;
+            if (i < d) { lo = fminf(lo, v); hi = fmaxf(hi, v); }
+        }
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
+#pragma unroll
+    for (int o = L / 2; o >= 1; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o));
+        hi = fmaxf(hi, __shfl_xor(hi, o));
+    }
     const int levels = (1 << bq) - 1;
     float delta = 1.f;
     int su = 0;
-    int uv[NH];
+    int uv[V][NH];
     if (hi > lo) {
         delta = __fdiv_rn(__fsub_rn(hi, lo), (float)levels);
         const float inv = __fdiv_rn(1.f, delta);
 #pragma unroll
-        for (int h = 0; h < nh; h++) {
-            int i = lane + 64 * h;
-            int u = 0;
-            if (i < d) {
-                float tt = __fadd_rn(__fmul_rn(__fsub_rn(wv[h], lo), inv), 0.5f);
-                u = (int)floorf(tt);
-                u = u < 0 ? 0 : (u > levels ? levels : u);
+        for (int t = 0; t < V; t++) {
+#pragma unroll
+            for (int h = 0; h < NH; h++) {
+                const int i = g + L * t + 64 * h;
+                int u = 0;
+                if (i < d) {
+                    float tt = __fadd_rn(__fmul_rn(__fsub_rn(wv[t][h], lo), inv), 0.5f);
+                    u = (int)floorf(tt);
+                    u = u < 0 ? 0 : (u > levels ? levels : u);
+                }
+                uv[t][h] = u;
+                su += u;
             }
-            uv[h] = u;
-            su += u;
         }
     } else {
 #pragma unroll
-        for (int h = 0; h < nh; h++) uv[h] = 0;
+        for (int t = 0; t < V; t++)
+#pragma unroll
+            for (int h = 0; h < NH; h++) uv[t][h] = 0;
     }
-    su = wave_sum_i(su);
+#pragma unroll
+    for (int o = L / 2; o >= 1; o >>= 1) su += __shfl_xor(su, o);
     if (qbyte) {  // levels as signed bytes for the i8 matrix-core scan (u - 128 when bq = 8), zero beyond d
         const int ob = bq == 8 ? 128 : 0;
 #pragma unroll
-        for (int h = 0; h < NH; h++) {
-            const int i = lane + 64 * h;
-            if (i < KP) qbyte[i] = (int8_t)(i < d ? uv[h] - ob : 0);
-        }
-    }
-    for (int b = 0; pl && b < bq; b++) {
+        for (int t = 0; t < V; t++) {
 #pragma unroll
-        for (int h = 0; h < (NH > 0 ? NH : 1); h++) {
-            unsigned long long bm = __ballot(((uv[h] >> b) & 1) != 0);
-            if (lane == 0) {
-                if (2 * h < WP) pl[b * WP + 2 * h] = (uint32_t)bm;
-                if (2 * h + 1 < WP) pl[b * WP + 2 * h + 1] = (uint32_t)(bm >> 32);
+            for (int h = 0; h < NH; h++) {
+                const int i = g + L * t + 64 * h;
+                if (i < KP) qbyte[i] = (int8_t)(i < d ? uv[t][h] - ob : 0);
             }
         }
-        for (int w = 2 * NH + lane; w < WP; w += 64) pl[b * WP + w] = 0u;  // words beyond the last lane dim
     }
-    if (lane == 0) {
+    if constexpr (L == 64) {
+        for (int b = 0; pl && b < bq; b++) {
+#pragma unroll
+            for (int h = 0; h < (NH > 0 ? NH : 1); h++) {
+                unsigned long long bm = __ballot(((uv[0][h] >> b) & 1) != 0);
+                if (lane == 0) {
+                    if (2 * h < WP) pl[b * WP + 2 * h] = (uint32_t)bm;
+                    if (2 * h + 1 < WP) pl[b * WP + 2 * h + 1] = (uint32_t)(bm >> 32);
+                }
+            }
+            for (int w = 2 * NH + lane; w < WP; w += 64) pl[b * WP + w] = 0u;  // words beyond the last lane dim
+        }
+    }
+    if (g == 0) {
         PairRec R;
         R.q = q;
         R.list = j;
@@ -780,9 +835,10 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
     }
 }
 
-// One wave per (query, list) pair: its slot in the (phase, list) bucket and its query code (the level
-// bytes the scan multiplies; the seed pass builds the bit planes of its own pairs).
-template <int NH>
+// One group of L lanes per (query, list) pair (256 / L pairs per block): its slot in the (phase, list)
+// bucket and its query code (the level bytes the scan multiplies; the seed pass builds the bit planes of
+// its own pairs).
+template <int NH, int L>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
     const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh, const float* __restrict__ rq,
@@ -790,19 +846,20 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
     const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
     PairRec* __restrict__ recs, int8_t* __restrict__ qu8, int32_t* __restrict__ pair_pos) {
-    const int64_t pi = blockIdx.x * 4ll + (threadIdx.x >> 6);
-    if (pi >= npairs) return;
+    const int64_t pi = blockIdx.x * (int64_t)(256 / L) + threadIdx.x / L;
+    if (pi >= npairs) return;  // whole groups: the group's shuffles stay among active lanes
     const int lane = threadIdx.x & 63;
     const int q = pair_q[pi];
     const int j = pair_list[pi];
     const int r = (int)(pi - pair_off[q]);
     const int p = phase_of(r, sh);
+    const int first = lane & ~(L - 1);
     int pos = 0;
-    if (lane == 0) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
-    pos = __shfl(pos, 0);
-    if (lane == 0) pair_pos[pi] = pos;
-    pair_code<NH>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
-                  qu8 + (int64_t)pos * KP);
+    if (lane == first) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
+    pos = __shfl(pos, first);
+    if (lane == first) pair_pos[pi] = pos;
+    pair_code<NH, L>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
+                     qu8 + (int64_t)pos * KP);
 }
 
 __global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_nb, int nlist,
@@ -1634,7 +1691,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ PairRec sh_R;
     __shared__ uint32_t sh_U[8 * WP];
     const int j = c.pair_list[c.pair_off[q]];
-    pair_code<(WP <= 2 ? 1 : WP / 2)>(lane, q, j, c.rq, c.RC, c.d, c.d4, WP, c.bq, c.eps0, c.Tq, c.er, c.qn2, 0, &sh_R,
+    pair_code<(WP <= 2 ? 1 : WP / 2), 64>(lane, q, j, c.rq, c.RC, c.d, c.d4, WP, c.bq, c.eps0, c.Tq, c.er, c.qn2, 0, &sh_R,
                                      sh_U, nullptr);
     __syncthreads();
     const PairRec R = sh_R;
@@ -2453,7 +2510,10 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     KernelTimer* tm = a.timed ? &ix.timer : nullptr;
     const int64_t nq = a.nq;
     const int d = ix.d, d4 = ix.d4, D = ix.D, D4 = ix.D4, nlist = ix.nlist;
-    const int64_t P = (int64_t)kPhases * nlist;
+    // the (phase, list) buckets of the phases this search reaches (phase p starts at probe rank phase_lo(p))
+    int nph = 1;
+    while (nph < kPhases && phase_lo(nph, a.phase_shift) < a.np_max) nph++;
+    const int64_t P = (int64_t)nph * nlist;
     const int G = a.group <= 16 ? 16 : (a.group <= 32 ? 32 : 64);  // queries per scan work item
 
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
@@ -2516,17 +2576,19 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
         const int KP = 64 * nh;
-        const dim3 gp((unsigned)((a.total_pairs + 3) / 4));
-#define PREP(NHV)                                                                                          \
-    hipLaunchKernelGGL(k_pair_prep<NHV>, gp, dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, \
-                       nlist, a.phase_shift, w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP,   \
-                       w.recs, w.qu8, w.pair_pos)
-        if (nh <= 1) PREP(1);
-        else if (nh <= 2) PREP(2);
-        else if (nh <= 4) PREP(4);
-        else if (nh <= 8) PREP(8);
-        else if (nh <= 16) PREP(16);
-        else PREP(24);
+        // 16 lanes per pair up to d = 256 (4 pairs per wave: the kernel is bound by the latency of its loads
+        // and atomic), a whole wave beyond
+#define PREP(NHV, LV)                                                                                      \
+    hipLaunchKernelGGL((k_pair_prep<NHV, LV>), dim3((unsigned)((a.total_pairs + 256 / LV - 1) / (256 / LV))), \
+                       dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift,  \
+                       w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP, w.recs,  \
+                       w.qu8, w.pair_pos)
+        if (nh <= 1) PREP(1, 16);
+        else if (nh <= 2) PREP(2, 16);
+        else if (nh <= 4) PREP(4, 16);
+        else if (nh <= 8) PREP(8, 64);
+        else if (nh <= 16) PREP(16, 64);
+        else PREP(24, 64);
 #undef PREP
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
                            nlist, G, (int)P, w.items);
