@@ -87,8 +87,9 @@ typedef struct {
                                survivors, exact distances; [4..7] the same for the seed pass over
                                each query's nearest list */
     int32_t group;          /* queries per scan work item: 16, 32 or 64 (0 = the index default) */
-    int32_t exact_cap;      /* exact-stage buffer entries per phase (0 = automatic); candidates beyond
-                               it are finished inside the scan; results do not depend on it */
+    int32_t exact_cap;      /* exact-stage buffer entries per phase (0 = automatic), split evenly into
+                               one bin per query; candidates beyond a bin are finished inside the
+                               scan; results do not depend on it */
     int32_t method;         /* MRQ_METHOD_MRQ (default) or MRQ_METHOD_MRSQ (index built with sq8) */
     int32_t rerank;         /* MRQ_METHOD_MRSQ: candidates re-ranked by exact distance per query, R in
                                [k, 16384]; 0 = 500.  The MRQ fields bq, eps0, m, stage2, use_ext, group

@@ -102,6 +102,30 @@ __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, c
     for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     return s;
 }
+// The same with the query row in LDS and up to 16 chunks per lane in flight (one round for D <= 1024);
+// same operation order, hence the same results.
+__device__ __forceinline__ float exact_dist_group_lds(const float* __restrict__ x, const float4* qs, int D4,
+                                                      int l16) {
+    const int nc = D4 >> 2;
+    const float4* __restrict__ xa = reinterpret_cast<const float4*>(x);
+    float s = 0.f;
+    for (int base = 0; base < nc; base += 256) {
+        float4 a[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int ci = base + 16 * u + l16;
+            a[u] = ci < nc ? xa[ci] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) {
+            const int ci = base + 16 * u + l16;
+            if (ci >= nc) break;
+            acc_sqdiff(s, a[u], qs[ci]);
+        }
+    }
+    for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
 // Low-register form with the same operation order (hence the same results), for the rarely taken
 // in-place path of the scan kernel.
 __device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
@@ -980,8 +1004,8 @@ struct ScanCtx {
     const int64_t* pair_off;
     const int32_t* pair_pos;
     unsigned long long* slots;
-    int2* surv;          // exact-stage candidates of the current phase: (row, query), rs per scan wave
-    int32_t* wcnt;       // candidates produced by each scan wave (the first rs are in its region)
+    int32_t* surv;       // exact-stage candidates of the current phase: rows, in a bin of cq entries per query
+    int32_t* qcnt;       // candidates offered to each query's bin (the first cq are in it); zero between phases
     int64_t* counters;
     // inputs of the seed pass's own pair code (it runs beside the pair preparation)
     const int32_t* pair_list;
@@ -989,7 +1013,7 @@ struct ScanCtx {
     const float* RC;
     const float* Tq;
     float eps0;
-    int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, rs;
+    int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, cq;
 };
 
 __device__ __forceinline__ float ord_to_float(uint32_t o) {
@@ -1010,8 +1034,9 @@ __device__ __forceinline__ float ord_to_float(uint32_t o) {
 //             and the Eq 7 test.
 // Integer products are exact; the FP32 chain rounds every element in the fixed order of dot_lane, so an
 // entry's values do not depend on its position in the tile, i.e. on the other queries of the batch.
-// Survivors go to the phase's exact-stage buffer with one atomic per item; entries beyond its capacity
-// get their exact distance inside this kernel, with the same arithmetic as k_exact.  Every decision of a
+// Survivors go to their query's bin of the phase's exact-stage buffer (one atomic per sub-tile and query
+// with survivors); entries beyond a bin's capacity get their exact distance inside this kernel, with the
+// same arithmetic as k_exact.  Every decision of a
 // phase uses the phase threshold stored in the pair record, so the set of candidates reaching each
 // stage does not depend on the order in which items run.
 
@@ -1178,11 +1203,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     unsigned long long* msk = sh_m[wv];
     uint4* pf = sh_pf[wv];
     float4* qsh = qsh_dyn + (QL ? wv * GT * nf4 : 0);
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    // this wave's region of the exact-stage buffer
     const int wid = uniform(blockIdx.x * 4 + wv);
-    int2* region = c.surv + (int64_t)wid * c.rs;
-    int nreg = 0;  // candidates this wave produced (may exceed rs; the rest is finished in place)
+    int nreg = 0;  // candidates this wave passed to the exact stage (bins or in place)
     long long nscan = 0, n1 = 0, next = 0;
     // Items are dealt to the waves round-robin (neighbouring waves take neighbouring blocks of a list).
     // Descriptors are read two items ahead; the pair records of the next item travel in registers (three
@@ -1512,18 +1534,38 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             wave_lds_fence();
         }
 
-        // ---- exact-stage candidates into this wave's region ----
+        // ---- exact-stage candidates into their queries' bins: lane t < ng counts the survivors of query
+        // column t (column tile t / 16, lane group t / 4 % 4, v = t % 4) over the item's masks and reserves
+        // room for them with one atomic, one instruction for the whole item; a column's entries follow in
+        // (row tile, row) order ----
         if (cnt > 0) {
+            int base = 0;
+            if (lane < ng) {
+                const int tc = lane >> 4, tg = (lane >> 2) & 3, tv = lane & 3;
+                int n = 0;
+                for (int rt = 0; rt < 4; rt++)
+                    n += __popcll((msk[(tc * 4 + rt) * 4 + tv] >> (16 * tg)) & 0xFFFFull);
+                if (n) base = atomicAdd(&c.qcnt[rec[lane].q], n);
+            }
             for (int ct = 0; ct < nct; ct++) {
+                int bb[4], off[4];
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    bb[v] = __shfl(base, ct * 16 + 4 * kg + v);
+                    off[v] = 0;
+                }
                 for (int rt = 0; rt < 4; rt++) {
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
                         const unsigned long long mv = msk[(ct * 4 + rt) * 4 + v];
                         if (!mv) continue;
                         const bool mine = (mv >> lane) & 1ull;
-                        const int pos = nreg + __popcll(mv & lt);
-                        const bool fits = mine && pos < c.rs;
-                        if (fits) region[pos] = make_int2((int)(row0 + 16 * rt + li), rec[ct * 16 + 4 * kg + v].q);
+                        const uint32_t gm = (uint32_t)(mv >> (lane & 48)) & 0xFFFFu;
+                        const int pos = bb[v] + off[v] + __popc(gm & ((1u << li) - 1u));
+                        off[v] += __popc(gm);
+                        const bool fits = mine && pos < c.cq;
+                        if (fits)
+                            c.surv[(int64_t)rec[ct * 16 + 4 * kg + v].q * c.cq + pos] = (int)(row0 + 16 * rt + li);
                         const unsigned long long rest = __ballot(mine && !fits);
                         if (rest) finish_inline(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane);
                         nreg += __popcll(mv);
@@ -1535,7 +1577,6 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         dcur = dnext;
         dnext = dnn;
     }
-    if (lane == 0) c.wcnt[wid] = nreg;
     if (c.counters && lane == 0) {  // the counts are wave-uniform
         atomicAdd((unsigned long long*)&c.counters[0], (unsigned long long)nscan);
         atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
@@ -1544,23 +1585,46 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     }
 }
 
-// Exact stage of a phase: the candidates in region r of the buffer (written by scan wave r) are shared by
-// blocks r * split .. r * split + split - 1 (block part j takes groups of 16 candidates j, j + split, ...),
-// 16 lanes per candidate, four per wave, into the result queues.
-__global__ __launch_bounds__(256) void k_exact(ScanCtx c, int split) {
+// Exact stage of a phase: block q takes the candidates in query q's bin, 16 lanes per candidate (16 at a
+// time).  The block is the only writer of the query's result queue during the launch, so the queue is
+// copied to LDS, updated there with the same insertion as in global memory, and written back.  QL: the
+// query row is staged in LDS too and read from memory once per block.  Dynamic shared memory: D4 floats
+// (QL, D4 <= kExactLdsFloats), then k_max keys.  The bin's count is cleared for the next phase.
+constexpr int kExactLdsFloats = 8192;
+
+template <bool QL>
+__global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
+    extern __shared__ float4 dyn_x[];
+    __shared__ int n_s;
+    float4* qs = dyn_x;
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(dyn_x + (QL ? (c.D4 >> 2) : 0));
+    const int q = blockIdx.x;
     const int lane = lane_id();
-    const int r = blockIdx.x / split, part = blockIdx.x - r * split;
-    const int n = min(c.wcnt[r], c.rs);
-    const int2* region = c.surv + (int64_t)r * c.rs;
-    for (int i = 16 * part + (threadIdx.x >> 4); i - (lane >> 4) < n; i += 16 * split) {
+    if (threadIdx.x == 0) n_s = c.qcnt[q];
+    __syncthreads();
+    const int n = min(n_s, c.cq);
+    if (n == 0) return;
+    if (threadIdx.x == 0) c.qcnt[q] = 0;
+    const float* qrow = c.qpad + (int64_t)q * c.D4;
+    if (QL)
+        for (int i = threadIdx.x; i < (c.D4 >> 2); i += 256) qs[i] = reinterpret_cast<const float4*>(qrow)[i];
+    unsigned long long* slots = c.slots + c.slot_off[q];
+    const int k = c.kq[q];
+    for (int i = threadIdx.x; i < k; i += 256) queue[i] = slots[i];
+    __syncthreads();
+    const int32_t* bin = c.surv + (int64_t)q * c.cq;
+    for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
         const bool valid = i < n;
-        const int2 e = region[valid ? i : 0];
-        const float dist = exact_dist_group(c.X + (int64_t)e.x * c.D4, c.qpad + (int64_t)e.y * c.D4, c.D4, lane & 15);
+        const int64_t row = bin[valid ? i : 0];
+        const float dist = QL ? exact_dist_group_lds(c.X + row * c.D4, qs, c.D4, lane & 15)
+                              : exact_dist_group(c.X + row * c.D4, qrow, c.D4, lane & 15);
         if (valid && (lane & 15) == 0) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[e.x];
-            topk_insert(c.slots + c.slot_off[e.y], c.kq[e.y], key);
+            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
+            topk_insert(queue, k, key);
         }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += 256) slots[i] = queue[i];
 }
 
 // Seed pass: each query's nearest list (probe rank 0), one wave per query, before the batched phases,
@@ -2147,12 +2211,12 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
-    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *wcnt;
+    int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *qcnt;
     int4* desc;
     PairRec* recs;
     int8_t* qu8;
     unsigned long long* slots;
-    int2* surv;
+    int32_t* surv;
 };
 
 // Exact-stage buffer capacity of a phase (entries): 1/16 of the candidates the search can scan, within
@@ -2201,9 +2265,9 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.recs = c.take<PairRec>(total_pairs);
     w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
     w.slots = c.take<unsigned long long>(total_slots);
-    w.wcnt = c.take<int32_t>(4 * kMaxScanBlocks);
+    w.qcnt = c.take<int32_t>(nq);
     const int64_t cap = surv_capacity(ix, total_pairs);
-    w.surv = c.take<int2>(cap);
+    w.surv = c.take<int32_t>(cap);
     *used = c.used;
     return w;
 }
@@ -2541,19 +2605,20 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.fA = ix.fA; c.fF = ix.fF; c.fE = ix.fE; c.fFB = ix.fFB; c.fEB = ix.fEB; c.fSX = ix.fSX;
     c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
-    c.slots = w.slots; c.surv = w.surv; c.wcnt = w.wcnt; c.counters = a.counters;
+    c.slots = w.slots; c.surv = w.surv; c.qcnt = w.qcnt; c.counters = a.counters;
     c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
-    // persistent scan grid (resident blocks) and each scan wave's share of the exact-stage buffer
+    // persistent scan grid (resident blocks) and each query's bin of the exact-stage buffer
     const int scan_blocks = scan_grid(c);
     int64_t cap = surv_capacity(ix, a.total_pairs);
     if (a.exact_cap > 0 && a.exact_cap < cap) cap = a.exact_cap;
-    c.rs = (int)(cap / (4ll * scan_blocks));
+    c.cq = (int)(cap / nq);
     // The seed pass (each query's nearest list; it computes that pair's query code itself) runs on the
     // index's auxiliary stream beside the pair preparation; the phases wait for both.
     HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
+    HIP_TRY(launch_fill_i32(w.qcnt, 0, nq, s));
     if (!ix.aux) {
         HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
@@ -2613,9 +2678,11 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         }
         {
             Timed t(tm, s, "exact");
-            // at least about 4096 blocks, however many scan waves wrote the regions
-            const int split = std::max(1, 4096 / (4 * scan_blocks));
-            hipLaunchKernelGGL(k_exact, dim3((unsigned)(4 * scan_blocks * split)), dim3(256), 0, s, c, split);
+            const size_t qk = (size_t)a.k_max * sizeof(unsigned long long);
+            if (D4 <= kExactLdsFloats)
+                hipLaunchKernelGGL(k_exact<true>, dim3((unsigned)nq), dim3(256), (size_t)D4 * sizeof(float) + qk, s, c);
+            else
+                hipLaunchKernelGGL(k_exact<false>, dim3((unsigned)nq), dim3(256), qk, s, c);
             HIP_TRY(hipGetLastError());
         }
     }
