@@ -1640,6 +1640,7 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 
 constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
 constexpr int kSeedFirst = 32;  // round 1 takes at least this many best-bound candidates
+constexpr int kSeedLdsFloats = 2048;  // query rows up to this length are staged in LDS
 
 // sort 64 keys held one per lane, ascending (bitonic network over shuffles)
 __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
@@ -1669,8 +1670,8 @@ struct QueryState {
 // sorted queue and the new tau.
 template <int WP>
 __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
-                           QueryState& st, unsigned long long* nk, int lane, long long* n1, long long* next,
-                           long long* n2) {
+                           QueryState& st, unsigned long long* nk, const float4* qs, bool qlds, int lane,
+                           long long* n1, long long* next, long long* n2) {
     *n1 += __popcll(__ballot(pass));
     const bool open = st.tau == INFINITY;  // every test passes until the queue holds k results
     if (pass && !open && c.B > 1 && c.use_ext) {
@@ -1693,7 +1694,8 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     while (mm) {
         const int src = take4(&mm, lane);
         const int64_t rs = __shfl(row, src < 0 ? first : src);
-        const float dist = exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
+        const float dist = qlds ? exact_dist_group_lds(c.X + rs * c.D4, qs, c.D4, lane & 15)
+                                : exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
         for (int g = 0; g < 4; g++) {
             const int sg = __shfl(src, g * 16);
@@ -1739,13 +1741,18 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
     __shared__ int32_t pend_row[128];
     __shared__ float pend_lb[128];
-    extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, then kSeedMax candidate keys
+    extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, kSeedMax candidate keys, the query row
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
     QueryState st;
     st.tk[0] = dyn;
     st.tk[1] = dyn + c.k_max;
     unsigned long long* keys = dyn + 2 * c.k_max;
+    // the query row in LDS for the exact distances (D4 <= kSeedLdsFloats)
+    const bool qlds = c.D4 <= kSeedLdsFloats;
+    float4* qs = reinterpret_cast<float4*>(keys + kSeedMax);
+    if (qlds)
+        for (int i = lane; i < (c.D4 >> 2); i += 64) qs[i] = reinterpret_cast<const float4*>(c.qpad + (int64_t)q * c.D4)[i];
     st.cur = 0;
     st.k = c.kq[q];
     st.have = 0;
@@ -1794,7 +1801,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         const bool in = lane < cnt;
         const int i = in ? pend_row[lane] : 0;
         const float lb = in ? pend_lb[lane] : INFINITY;
-        seed_batch<WP>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, lane, &n1, &next, &n2);
+        seed_batch<WP>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, qs, qlds, lane, &n1, &next, &n2);
         const int rest = np - cnt;  // move the remaining entries to the front
         int r_row = 0;
         float r_lb = 0.f;
@@ -2292,7 +2299,9 @@ size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, 
 template <int WP, int BQT>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
     hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64),
-                       sizeof(unsigned long long) * (2 * c.k_max + kSeedMax), s, c);
+                       sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
+                           (c.D4 <= kSeedLdsFloats ? sizeof(float) * c.D4 : 0),
+                       s, c);
 }
 
 // Blocks of a persistent kernel that are resident at once on the current device (cached per device).
