@@ -46,6 +46,9 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v;
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Ordering of LDS accesses between the lanes of one wave (they execute in program order; this only
+// keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 // Read data that no kernel of the current launch writes through the constant address space, so a
 // wave-uniform address becomes a scalar load.
@@ -703,8 +706,123 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     }
 }
 
+// sort 64 keys held one per lane, ascending (bitonic network over shuffles)
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
+    for (int size = 2; size <= 64; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            unsigned long long o = __shfl_xor(v, stride);
+            bool up = (lane & size) == 0;
+            bool lower = (lane & stride) == 0;
+            unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (lower == up) ? mn : mx;
+        }
+    }
+    return v;
+}
+
+// The same selection for np <= 64 and nlist <= 64 V, one wave per query (four per block, no barriers):
+// lane l holds the patterns of lists j = l + 64 u.  The np-th smallest of the 64 lane minima is a
+// threshold t with at least np patterns <= t, so the lists with g_j <= t hold the np smallest keys
+// (g_j, j); when there are at most 64 of them they are gathered one per lane and sorted, and the first np
+// are taken.  Otherwise the np-th smallest key is found bitwise: 32 wave-wide counting rounds give its
+// pattern T, then, among the ties at T, rounds over the list id give the last one taken (unless every tie
+// is taken), and the np lists are gathered and sorted.  Either way the lists and their order are those
+// of k_select.
+template <int V>
+__global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, int nlist,
+                                                 const int32_t* __restrict__ npq,
+                                                 const int64_t* __restrict__ pair_off,
+                                                 int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q,
+                                                 int64_t nq) {
+    __shared__ unsigned long long sel_s[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = blockIdx.x * 4ll + w;
+    if (q >= nq) return;
+    const float* g = G + q * nlist;
+    const int np = npq[q];
+    uint32_t v[V];
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+        const int j = lane + 64 * u;
+        v[u] = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
+    }
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < V; u++) mn = min(mn, v[u]);
+    const uint32_t t = (uint32_t)__shfl(wave_sort64(mn, lane), np - 1);
+    int cc = 0;
+#pragma unroll
+    for (int u = 0; u < V; u++) cc += v[u] <= t;
+    if (wave_sum_i(cc) <= 64) {
+        int at = 0;
+#pragma unroll
+        for (int u = 0; u < V; u++) {
+            const bool sel = v[u] <= t;
+            const unsigned long long m = __ballot(sel);
+            if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v[u] << 32) | (uint32_t)(lane + 64 * u);
+            at += __popcll(m);
+        }
+        wave_lds_fence();
+        const unsigned long long key = wave_sort64(lane < at ? sel_s[w][lane] : kEmptyKey, lane);
+        if (lane < np) {
+            const int64_t o = pair_off[q];
+            pair_list[o + lane] = (int32_t)(key & 0xFFFFFFFFull);
+            pair_q[o + lane] = (int32_t)q;
+        }
+        return;
+    }
+    uint32_t T = 0;  // the np-th smallest pattern
+    for (int b = 31; b >= 0; b--) {
+        const uint32_t cand = T | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < V; u++) c += v[u] < cand;
+        if (wave_sum_i(c) < np) T = cand;
+    }
+    int cl = 0, ce = 0;
+#pragma unroll
+    for (int u = 0; u < V; u++) { cl += v[u] < T; ce += v[u] == T; }
+    const int need = np - wave_sum_i(cl);  // ties at T to take, smallest list ids first (>= 1)
+    int J = 64 * V;                        // lists j < J among the ties are taken
+    if (wave_sum_i(ce) > need) {
+        uint32_t Jb = 0;  // the need-th smallest tied list id
+        for (int b = 31 - __clz(64 * V - 1); b >= 0; b--) {
+            const uint32_t cand = Jb | (1u << b);
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < V; u++) c += v[u] == T && (uint32_t)(lane + 64 * u) < cand;
+            if (wave_sum_i(c) < need) Jb = cand;
+        }
+        J = (int)Jb + 1;
+    }
+    int at = 0;
+#pragma unroll
+    for (int u = 0; u < V; u++) {
+        const int j = lane + 64 * u;
+        const bool sel = v[u] < T || (v[u] == T && j < J);
+        const unsigned long long m = __ballot(sel);
+        if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v[u] << 32) | (uint32_t)j;
+        at += __popcll(m);
+    }
+    wave_lds_fence();
+    const unsigned long long key = wave_sort64(lane < np ? sel_s[w][lane] : kEmptyKey, lane);
+    if (lane < np) {
+        const int64_t o = pair_off[q];
+        pair_list[o + lane] = (int32_t)(key & 0xFFFFFFFFull);
+        pair_q[o + lane] = (int32_t)q;
+    }
+}
+
 static void launch_select(const float* G, int nlist, const int32_t* npq, const int64_t* pair_off, int32_t* pair_list,
-                          int32_t* pair_q, int64_t nq, hipStream_t s) {
+                          int32_t* pair_q, int64_t nq, int np_max, hipStream_t s) {
+    if (np_max <= 64 && nlist <= 64 * 64) {
+        const dim3 gw((unsigned)((nq + 3) / 4)), bw(256);
+        if (nlist <= 64 * 16) hipLaunchKernelGGL(k_select_w<16>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
+        else if (nlist <= 64 * 32) hipLaunchKernelGGL(k_select_w<32>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
+        else hipLaunchKernelGGL(k_select_w<64>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
+        return;
+    }
     const dim3 grid((unsigned)nq), blk(256);
     if (nlist <= 256 * 16) hipLaunchKernelGGL(k_select<16>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
     else if (nlist <= 256 * 32) hipLaunchKernelGGL(k_select<32>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
@@ -1157,11 +1275,6 @@ __device__ __forceinline__ f32x4 dot_tile_x(const float4 (&xa)[SU], const float*
     for (int t = 0; t < SU; t++) mfma4(acc, qa[t], xa[t]);
     return acc;
 }
-
-// Ordering of LDS accesses between the lanes of one wave (they execute in program order; this only
-// keeps the compiler from moving them).
-__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
-
 
 // LDS staging of an item's q_d rows for stage 2 (QL): rows of d4 floats, d4 a multiple of 64, float4
 // column f of pair slot s stored at f ^ (s & 15), so the 16 lanes of a lane group read 16 different banks.
@@ -1641,20 +1754,6 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
 constexpr int kSeedFirst = 32;  // round 1 takes at least this many best-bound candidates
 constexpr int kSeedLdsFloats = 2048;  // query rows up to this length are staged in LDS
-
-// sort 64 keys held one per lane, ascending (bitonic network over shuffles)
-__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
-    for (int size = 2; size <= 64; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            unsigned long long o = __shfl_xor(v, stride);
-            bool up = (lane & size) == 0;
-            bool lower = (lane & stride) == 0;
-            unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
-            v = (lower == up) ? mn : mx;
-        }
-    }
-    return v;
-}
 
 struct QueryState {
     unsigned long long* tk[2];
@@ -2519,7 +2618,7 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
     {
         Timed t(tm, s, "probe");
         HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr, 0, 0, s));
-        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, s);
+        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, a.np_max, s);
         HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
         HIP_TRY(hipGetLastError());
     }
@@ -2605,7 +2704,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         Timed t(tm, s, "probe");
         HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr,
                                     0, 0, s));
-        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, s);
+        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, a.np_max, s);
         HIP_TRY(hipGetLastError());
     }
     ScanCtx c;

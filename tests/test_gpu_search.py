@@ -179,6 +179,26 @@ def test_mixed_k_nprobe(small):
     assert not st["failures"], st["failures"][:5]
 
 
+def test_probe_selection_kernels_agree():
+    """Batches whose largest nprobe is at most 64 rank the lists one wave per query, larger ones one block
+    per query; both take the np smallest (g_j, j), so a row is the same under either."""
+    X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=256)
+    try:
+        Qd = torch.from_numpy(Q).cuda()
+        for np_small in (1, 7, 20, 64):
+            ks = np.full(60, 10, np.int32)
+            nps = np.full(60, np_small, np.int32)
+            nps[-1] = 100                                   # np_max 100: the block kernel for every row
+            ids, dists, off = ix.search_mixed(Qd, ks, nps)
+            a, b = ix.search(Qd[:59].contiguous(), 10, np_small)  # np_max <= 64: the wave kernel
+            torch.cuda.synchronize()
+            assert np.array_equal(ids[:590].reshape(59, 10), a.cpu().numpy())
+            assert np.array_equal(dists[:590].reshape(59, 10).view(np.uint32), b.cpu().numpy().view(np.uint32))
+    finally:
+        ix.close()
+
+
 def test_counters_monotone(small):
     cnt = np.zeros(8, dtype=np.int64)
     small["ix"].search(small["Q"][:20].copy(), 10, 8, counters=cnt)
