@@ -167,6 +167,43 @@ __device__ __forceinline__ float dot_lane(const float* __restrict__ a, const flo
     return s;
 }
 
+// The same chain with q_d in LDS and two 16-dimension slices of the row in flight per round (the seed
+// pass); float4s beyond d4 are read at a valid index and zeroed, which adds nothing to the chain.
+__device__ __forceinline__ float dot_lane_lds(const float* __restrict__ a, const float4* yq, int d4) {
+    const float4* __restrict__ xa = reinterpret_cast<const float4*>(a);
+    const int n4 = d4 >> 2;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    float s = 0.f;
+    for (int t4 = 0; t4 < n4; t4 += 8) {
+        float4 x[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int f = t4 + i;
+            x[i] = xa[f < n4 ? f : n4 - 1];
+            if (f >= n4) x[i] = z;
+        }
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++) {
+            float4 y[4];
+#pragma unroll
+            for (int g = 0; g < 4; g++) {
+                const int f = t4 + 4 * sl + g;
+                y[g] = yq[f < n4 ? f : n4 - 1];
+                if (f >= n4) y[g] = z;
+            }
+#pragma unroll
+            for (int g = 0; g < 4; g++) s = fmaf(x[4 * sl + g].x, y[g].x, s);
+#pragma unroll
+            for (int g = 0; g < 4; g++) s = fmaf(x[4 * sl + g].y, y[g].y, s);
+#pragma unroll
+            for (int g = 0; g < 4; g++) s = fmaf(x[4 * sl + g].z, y[g].z, s);
+#pragma unroll
+            for (int g = 0; g < 4; g++) s = fmaf(x[4 * sl + g].w, y[g].w, s);
+        }
+    }
+    return s;
+}
+
 // Take up to four set lanes of *mask (lowest first) and give each 16-lane group one of them: returns
 // the source lane of this lane's group, or -1.
 __device__ __forceinline__ int take4(unsigned long long* mask, int lane) {
@@ -1780,7 +1817,8 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     }
     *next += __popcll(__ballot(pass));
     if (pass && !open && c.stage2) {
-        const float dot = dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
+        const float dot = qlds ? dot_lane_lds(c.xd + row * c.d4, qs + (c.D4 >> 2), c.d4)
+                               : dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
         pass = fmaf(-2.f, dot, c.ax[row] + R.qn2) - er < st.tau;
     }
     const unsigned long long m2 = __ballot(pass);
@@ -1840,18 +1878,21 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
     __shared__ int32_t pend_row[128];
     __shared__ float pend_lb[128];
-    extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, kSeedMax candidate keys, the query row
+    extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, kSeedMax candidate keys, query rows
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
     QueryState st;
     st.tk[0] = dyn;
     st.tk[1] = dyn + c.k_max;
     unsigned long long* keys = dyn + 2 * c.k_max;
-    // the query row in LDS for the exact distances (D4 <= kSeedLdsFloats)
+    // the query row (exact distances) and q_d (stage 2) in LDS, D4 + d4 floats (D4 <= kSeedLdsFloats)
     const bool qlds = c.D4 <= kSeedLdsFloats;
     float4* qs = reinterpret_cast<float4*>(keys + kSeedMax);
-    if (qlds)
+    if (qlds) {
         for (int i = lane; i < (c.D4 >> 2); i += 64) qs[i] = reinterpret_cast<const float4*>(c.qpad + (int64_t)q * c.D4)[i];
+        for (int i = lane; i < (c.d4 >> 2); i += 64)
+            qs[(c.D4 >> 2) + i] = reinterpret_cast<const float4*>(c.qd + (int64_t)q * c.d4)[i];
+    }
     st.cur = 0;
     st.k = c.kq[q];
     st.have = 0;
@@ -1880,12 +1921,14 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     const int s = s0 < nsel ? s0 : nsel;
     // the s-th smallest key: the largest value with fewer than s keys below it, by a bitwise search over
     // the keys held in registers (slot u of lane l: key l + 64 u; beyond nsel ~0, never counted); each
-    // step counts with one ballot per slot
+    // step counts with one ballot per slot.  Bits 31..9 are zero in every key (row index < kSeedMax), so
+    // they are zero in the s-th smallest and are not searched.
+    static_assert(kSeedMax <= 512, "row index of a seed key fits in 9 bits");
     unsigned long long kr[kSeedMax / 64];
 #pragma unroll
     for (int u = 0; u < kSeedMax / 64; u++) kr[u] = lane + 64 * u < nsel ? keys[lane + 64 * u] : ~0ull;
     unsigned long long T = 0;
-    for (int b = 63; b >= 0; b--) {
+    for (int b = 63; b >= 0; b = b == 32 ? 8 : b - 1) {
         const unsigned long long t = T | (1ull << b);
         int cnt = 0;
 #pragma unroll
@@ -2399,7 +2442,7 @@ template <int WP, int BQT>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
     hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64),
                        sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
-                           (c.D4 <= kSeedLdsFloats ? sizeof(float) * c.D4 : 0),
+                           (c.D4 <= kSeedLdsFloats ? sizeof(float) * (c.D4 + c.d4) : 0),
                        s, c);
 }
 
