@@ -432,13 +432,18 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
             const int k = k0 + 4 * kg;
             const int kc = k < K ? k : 0;  // in-row offset actually read (always valid)
             const bool e0 = k < K, e1 = k + 1 < K, e2 = k + 2 < K, e3 = k + 3 < K;
+            // every load of the step is issued before any is used (the subtraction used to wait on each)
             float4 av[4], bv[4];
-            float4 sub = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (asub) sub = *reinterpret_cast<const float4*>(asub + kc);
+            const float4 sub = *reinterpret_cast<const float4*>((asub ? asub : ar[0]) + kc);
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                float4 a = *reinterpret_cast<const float4*>(ar[i] + kc);
-                float4 b = *reinterpret_cast<const float4*>(br[i] + kc);
+                av[i] = *reinterpret_cast<const float4*>(ar[i] + kc);
+                bv[i] = *reinterpret_cast<const float4*>(br[i] + kc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                float4 a = av[i];
+                const float4 b = bv[i];
                 if (asub) { a.x -= sub.x; a.y -= sub.y; a.z -= sub.z; a.w -= sub.w; }
                 av[i] = make_float4(e0 ? a.x : 0.f, e1 ? a.y : 0.f, e2 ? a.z : 0.f, e3 ? a.w : 0.f);
                 bv[i] = make_float4(e0 ? b.x : 0.f, e1 ? b.y : 0.f, e2 ? b.z : 0.f, e3 ? b.w : 0.f);
