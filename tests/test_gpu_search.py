@@ -179,11 +179,14 @@ def test_mixed_k_nprobe(small):
     assert not st["failures"], st["failures"][:5]
 
 
-def test_probe_selection_kernels_agree():
+@pytest.mark.parametrize("nlist", [256, 1500])
+def test_probe_selection_kernels_agree(nlist):
     """Batches whose largest nprobe is at most 64 rank the lists one wave per query, larger ones one block
-    per query; both take the np smallest (g_j, j), so a row is the same under either."""
+    per query; both take the np smallest (g_j, j), so a row is the same under either (nlist 256 and 1500:
+    16 and 32 lists per lane in the wave kernel)."""
+    print(f"\n[gpu] selection kernels agree: nlist={nlist}", flush=True)
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
-    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=256)
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
     try:
         Qd = torch.from_numpy(Q).cuda()
         for np_small in (1, 7, 20, 64):
