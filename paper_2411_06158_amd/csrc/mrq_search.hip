@@ -856,6 +856,104 @@ __global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, i
     }
 }
 
+// The same selection for np <= 64 and any nlist, one wave per query streaming its row of g twice (no
+// values held in registers): pass 1 takes the minimum of each lane's lists j = l + 64 u, whose np-th
+// smallest is a threshold t with at least np patterns <= t; pass 2 gathers the lists with g_j <= t in list
+// order into LDS (up to kSelStreamCap) and each gathered key (g_j, j) finds its rank by counting the
+// smaller ones; ranks below np are the output positions.  With more lists at or below t than fit, the
+// np-th smallest key is found bitwise, counting over the row in each round (pattern, then list id among
+// the ties), and the np lists are gathered and sorted.  The lists and their order are those of k_select.
+constexpr int kSelStreamCap = 512;
+
+__global__ __launch_bounds__(256) void k_select_s(const float* __restrict__ G, int nlist,
+                                                  const int32_t* __restrict__ npq,
+                                                  const int64_t* __restrict__ pair_off,
+                                                  int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q,
+                                                  int64_t nq) {
+    __shared__ unsigned long long sel_s[4][kSelStreamCap];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = blockIdx.x * 4ll + w;
+    if (q >= nq) return;
+    const uint32_t* g = reinterpret_cast<const uint32_t*>(G + q * nlist);  // non-negative: patterns order like values
+    const int np = npq[q];
+    const int64_t o = pair_off[q];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    uint32_t mn = 0xFFFFFFFFu;
+    for (int j0 = 0; j0 < nlist; j0 += 512) {
+        uint32_t x[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int j = j0 + 64 * t + lane;
+            x[t] = j < nlist ? g[j] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) mn = min(mn, x[t]);
+    }
+    const uint32_t thr = (uint32_t)__shfl(wave_sort64(mn, lane), np - 1);
+    int at = 0;
+    for (int j0 = 0; j0 < nlist; j0 += 512) {
+        uint32_t x[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int j = j0 + 64 * t + lane;
+            x[t] = j < nlist ? g[j] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int j = j0 + 64 * t + lane;
+            const bool sel = j < nlist && x[t] <= thr;
+            const unsigned long long m = __ballot(sel);
+            const int pos = at + __popcll(m & lt);
+            if (sel && pos < kSelStreamCap) sel_s[w][pos] = ((unsigned long long)x[t] << 32) | (uint32_t)j;
+            at += __popcll(m);
+        }
+    }
+    wave_lds_fence();
+    if (at <= kSelStreamCap) {
+        for (int i = lane; i < at; i += 64) {
+            const unsigned long long key = sel_s[w][i];
+            int r = 0;
+            for (int x = 0; x < at; x++) r += sel_s[w][x] < key;
+            if (r < np) {
+                pair_list[o + r] = (int32_t)(key & 0xFFFFFFFFull);
+                pair_q[o + r] = (int32_t)q;
+            }
+        }
+        return;
+    }
+    auto count_row = [&](auto pred) __attribute__((always_inline)) {
+        int c = 0;
+        for (int j = lane; j < nlist; j += 64) c += pred(g[j], j);
+        return wave_sum_i(c);
+    };
+    uint32_t T = 0;  // the np-th smallest pattern
+    for (int b = 31; b >= 0; b--) {
+        const uint32_t cand = T | (1u << b);
+        if (count_row([&](uint32_t v, int) { return v < cand; }) < np) T = cand;
+    }
+    const int need = np - count_row([&](uint32_t v, int) { return v < T; });  // ties at T to take (>= 1)
+    uint32_t Jb = 0;  // the need-th smallest tied list id
+    for (int b = 31 - __clz(nlist - 1 > 0 ? nlist - 1 : 1); b >= 0; b--) {
+        const uint32_t cand = Jb | (1u << b);
+        if (count_row([&](uint32_t v, int j) { return v == T && (uint32_t)j < cand; }) < need) Jb = cand;
+    }
+    at = 0;
+    for (int j0 = 0; j0 < nlist; j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t v = j < nlist ? g[j] : 0xFFFFFFFFu;
+        const bool sel = j < nlist && (v < T || (v == T && (uint32_t)j <= Jb));
+        const unsigned long long m = __ballot(sel);
+        if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v << 32) | (uint32_t)j;
+        at += __popcll(m);
+    }
+    wave_lds_fence();
+    const unsigned long long key = wave_sort64(lane < np ? sel_s[w][lane] : kEmptyKey, lane);
+    if (lane < np) {
+        pair_list[o + lane] = (int32_t)(key & 0xFFFFFFFFull);
+        pair_q[o + lane] = (int32_t)q;
+    }
+}
+
 static void launch_select(const float* G, int nlist, const int32_t* npq, const int64_t* pair_off, int32_t* pair_list,
                           int32_t* pair_q, int64_t nq, int np_max, hipStream_t s) {
     if (np_max <= 64 && nlist <= 64 * 64) {
@@ -863,6 +961,11 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
         if (nlist <= 64 * 16) hipLaunchKernelGGL(k_select_w<16>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
         else if (nlist <= 64 * 32) hipLaunchKernelGGL(k_select_w<32>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
         else hipLaunchKernelGGL(k_select_w<64>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
+        return;
+    }
+    if (np_max <= 64) {
+        hipLaunchKernelGGL(k_select_s, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, G, nlist, npq, pair_off,
+                           pair_list, pair_q, nq);
         return;
     }
     const dim3 grid((unsigned)nq), blk(256);

@@ -179,11 +179,12 @@ def test_mixed_k_nprobe(small):
     assert not st["failures"], st["failures"][:5]
 
 
-@pytest.mark.parametrize("nlist", [256, 1500])
+@pytest.mark.parametrize("nlist", [256, 1500, 5000])
 def test_probe_selection_kernels_agree(nlist):
     """Batches whose largest nprobe is at most 64 rank the lists one wave per query, larger ones one block
     per query; both take the np smallest (g_j, j), so a row is the same under either (nlist 256 and 1500:
-    16 and 32 lists per lane in the wave kernel)."""
+    16 and 32 lists per lane held in registers; 5000: the streaming form, whose gathered set exceeds its
+    LDS capacity for some queries at nprobe 64, so its bitwise fallback runs too)."""
     print(f"\n[gpu] selection kernels agree: nlist={nlist}", flush=True)
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
     ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
