@@ -1,8 +1,12 @@
 // Query-time kernels of the MRQ search path (Algorithm 2 with Eq 4-7 of arXiv 2411.06158), written
-// for gfx950: 64-wide wavefronts, one candidate vector per lane in the bit-code scan, per-(query, list)
-// query codes read through the scalar unit, survivors compacted by ballot into a per-wave LDS queue,
-// and per-query top-k kept in global memory as a sorted array of 64-bit (distance, id) keys updated
-// with atomicMin chains.
+// for gfx950: the projection and probe distances on the FP32 matrix cores; the probe ranking one wave
+// per query; per-(query, list) query codes; a persistent scan in which a wave takes a 64-vector list
+// block against a group of queries as 16 x 16 tiles (stage 1 and the B-bit refinement as int8
+// matrix-core products of sign bits and query levels, stage 2 as an FP32 matrix-core chain), with its
+// operands staged in LDS by direct global-to-LDS loads; survivors binned per query and their exact
+// distances computed one block per query, whose result queue (a sorted array of 64-bit (distance, id)
+// keys) is updated in LDS; and a seed pass over each query's nearest list, one wave per query, that
+// gives the first batched phase its threshold.
 //
 // Batch independence: every value a query's result depends on (projection, probe ranking, query
 // codes, stage values, exact distances, the pruning thresholds) is computed by a fixed sequence of
@@ -401,7 +405,7 @@ static hipError_t launch_gemm_dist(const float* A, int64_t lda, const float* Bm,
 // order that depends only on K and VEC, so a row's result does not depend on the other rows.
 // EPI 0: C[m][n];  EPI 1: max(0, rowv[m] + colv[n] - 2 C) (squared distances);  EPI 2: columns below
 // nsplit go to C (ldc), the others to C2 (ldc2) at column n - nsplit.
-template <int VEC, int EPI>
+template <int VEC, int EPI, int MI>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, int64_t lda,
                                                    const float* __restrict__ asub,
                                                    const float* __restrict__ Bm, int64_t ldb,
@@ -410,21 +414,24 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
                                                    float* __restrict__ C2, int64_t ldc2, int nsplit) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, kg = lane >> 4;
-    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * MI);
     const int n0 = blockIdx.y * 64;
     if (m0 >= M) return;
-    const float* ar[4];
+    const float* ar[MI];
     const float* br[4];
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < MI; i++) {
         const int64_t m = m0 + 16 * i + li;
         ar[i] = A + (m < M ? m : M - 1) * lda;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
         const int n = n0 + 16 * i + li;
         br[i] = Bm + (int64_t)(n < N ? n : N - 1) * ldb;
     }
-    f32x4 acc[4][4];
+    f32x4 acc[MI][4];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (VEC == 4) {
@@ -433,35 +440,37 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
             const int kc = k < K ? k : 0;  // in-row offset actually read (always valid)
             const bool e0 = k < K, e1 = k + 1 < K, e2 = k + 2 < K, e3 = k + 3 < K;
             // every load of the step is issued before any is used (the subtraction used to wait on each)
-            float4 av[4], bv[4];
+            float4 av[MI], bv[4];
             const float4 sub = *reinterpret_cast<const float4*>((asub ? asub : ar[0]) + kc);
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                av[i] = *reinterpret_cast<const float4*>(ar[i] + kc);
-                bv[i] = *reinterpret_cast<const float4*>(br[i] + kc);
-            }
+            for (int i = 0; i < MI; i++) av[i] = *reinterpret_cast<const float4*>(ar[i] + kc);
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
+            for (int j = 0; j < 4; j++) bv[j] = *reinterpret_cast<const float4*>(br[j] + kc);
+#pragma unroll
+            for (int i = 0; i < MI; i++) {
                 float4 a = av[i];
-                const float4 b = bv[i];
                 if (asub) { a.x -= sub.x; a.y -= sub.y; a.z -= sub.z; a.w -= sub.w; }
                 av[i] = make_float4(e0 ? a.x : 0.f, e1 ? a.y : 0.f, e2 ? a.z : 0.f, e3 ? a.w : 0.f);
-                bv[i] = make_float4(e0 ? b.x : 0.f, e1 ? b.y : 0.f, e2 ? b.z : 0.f, e3 ? b.w : 0.f);
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) {
+                const float4 b = bv[j];
+                bv[j] = make_float4(e0 ? b.x : 0.f, e1 ? b.y : 0.f, e2 ? b.z : 0.f, e3 ? b.w : 0.f);
+            }
+#pragma unroll
+            for (int i = 0; i < MI; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].x, bv[j].x, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; i++)
+            for (int i = 0; i < MI; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].y, bv[j].y, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; i++)
+            for (int i = 0; i < MI; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].z, bv[j].z, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; i++)
+            for (int i = 0; i < MI; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i].w, bv[j].w, acc[i][j], 0, 0, 0);
         }
@@ -471,15 +480,16 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
             const bool in = k < K;
             const int kc = in ? k : 0;
             const float sub = asub ? asub[kc] : 0.f;
-            float av[4], bv[4];
+            float av[MI], bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
+            for (int i = 0; i < MI; i++) {
                 const float a = ar[i][kc] - sub;
                 av[i] = in ? a : 0.f;
-                bv[i] = in ? br[i][kc] : 0.f;
             }
 #pragma unroll
-            for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) bv[j] = in ? br[j][kc] : 0.f;
+#pragma unroll
+            for (int i = 0; i < MI; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
@@ -491,7 +501,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
         if (n >= N) continue;
         const float cv = EPI == 1 ? colv[n] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
+        for (int i = 0; i < MI; i++) {
 #pragma unroll
             for (int v = 0; v < 4; v++) {
                 const int64_t m = m0 + 16 * i + 4 * kg + v;
@@ -522,13 +532,19 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
                                    float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
                                    const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 63) / 64));
-    if (vec4_ok(A, lda) && vec4_ok(Bm, ldb) && (!asub || vec4_ok(asub, 0)))
-        hipLaunchKernelGGL((k_gemm_mfma<4, EPI>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K,
-                           rowv, colv, C2, ldc2, nsplit);
-    else
-        hipLaunchKernelGGL((k_gemm_mfma<1, EPI>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K,
-                           rowv, colv, C2, ldc2, nsplit);
+    // 64 x 64 output tiles per wave, or 32 x 64 when that gives fewer than about 4 waves per SIMD (the
+    // projection): the products of an output element are the same chain either way
+    const bool v4 = vec4_ok(A, lda) && vec4_ok(Bm, ldb) && (!asub || vec4_ok(asub, 0));
+    const bool half = ((M + 63) / 64) * ((N + 63) / 64) < 4096;
+    const dim3 grid((unsigned)((M + (half ? 127 : 255)) / (half ? 128 : 256)), (unsigned)((N + 63) / 64));
+#define GEMM_LAUNCH(V, MIV) \
+    hipLaunchKernelGGL((k_gemm_mfma<V, EPI, MIV>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K, \
+                       rowv, colv, C2, ldc2, nsplit)
+    if (v4 && half) GEMM_LAUNCH(4, 2);
+    else if (v4) GEMM_LAUNCH(4, 4);
+    else if (half) GEMM_LAUNCH(1, 2);
+    else GEMM_LAUNCH(1, 4);
+#undef GEMM_LAUNCH
     return hipGetLastError();
 }
 
