@@ -112,9 +112,8 @@ void mrq_search_opts_default(mrq_search_opts *o);
  * trained on the leading d_r coordinates x_d, and the per-vector code of (x_d - c)/||x_d - c|| under
  * a random orthogonal P_r (Section 4.2) with B bits per leading dimension (B = 1: sign code; B > 1:
  * extended code whose top bit is the sign bit), plus the normalisation factors ||x_d - c||,
- * ||x_r||, <xbar, x_b>.  Every vector is also kept in PCA coordinates x_p = P_p (x - mu) (FP32) for
- * the exact stage, which computes ||x_p - q_p||^2 (= ||x - q||^2, Eq 1) over the axes in descending
- * variance order.
+ * ||x_r||, <xbar, x_b>.  Every original vector is also kept (FP32, list order) for the exact stage,
+ * which computes ||x - q||^2 (= ||x_p - q_p||^2, Eq 1).
  *   X      N x D FP32, host or device, finite values only (checked: MRQ_EINVAL otherwise)
  *   d_r    in [2, min(D, 1536)], or 0 for the Eq 8 choice (mrq_choose_dr on the data's eigenvalues);
  *          bits B in [1, 8];  nlist in [1, min(N, 16384)]
@@ -184,10 +183,10 @@ mrq_status mrq_index_info(const mrq_index *index, int64_t *N, int32_t *D, int32_
                           int32_t *nlist, int64_t *device_bytes);
 
 /* Write the index in the "MRQX0001" layout above (lossless for everything the search reads except
- * the vectors in PCA coordinates; the caller keeps the original vectors).  Synchronous. */
+ * the original vectors, which the caller keeps).  Synchronous. */
 mrq_status mrq_export(const mrq_index *index, const char *path);
 
-/* Persist / restore a complete index: "MRQS0003", the shape (N, padded rows, D, d_r, bits, nlist, code
+/* Persist / restore a complete index: "MRQS0004", the shape (N, padded rows, D, d_r, bits, nlist, code
  * words per row, longest list, MR-SQ flag), the FP64 eigenvalues, the list offsets, then every device
  * array of the index (projection, rotation, centroids, codes, factors, x_d, the vectors in PCA
  * coordinates, the MR-SQ codes when present) in a fixed order.  The format is private to this library version.  mrq_load allocates on the current device.

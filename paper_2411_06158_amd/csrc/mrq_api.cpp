@@ -440,7 +440,7 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     ix->yn = dalloc<float>(ix.get(), Np);
     DevTemp O(sizeof(float) * Np * d4), Xpp(sizeof(float) * Np * d4), txr(sizeof(double) * Np),
         rowl(sizeof(int32_t) * Np);
-    hip_check(launch_gather_layout(*ix, xt_id.as<float>(), permd.as<int32_t>(), xd_id.as<float>(), ax64.as<double>(),
+    hip_check(launch_gather_layout(*ix, Xd, permd.as<int32_t>(), xd_id.as<float>(), ax64.as<double>(),
                                    tx64.as<double>(), txr.as<double>(), rowl.as<int32_t>(), O.as<float>(), s),
               "layout");
 
@@ -1006,7 +1006,7 @@ mrq_status mrq_save(const mrq_index* cix, const char* path) {
         mrq_index* ix = const_cast<mrq_index*>(cix);
         hip_check(hipDeviceSynchronize(), "sync");
         File f(path, "wb");
-        f.w("MRQS0003", 8);
+        f.w("MRQS0004", 8);
         int64_t h64[2] = {ix->N, ix->Npad};
         int32_t h32[7] = {ix->D, ix->d, ix->B, ix->nlist, ix->WP, ix->max_list_len, ix->dq};
         f.w(h64, sizeof(h64));
@@ -1031,7 +1031,7 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         File f(path, "rb");
         char magic[8];
         f.r(magic, 8);
-        if (std::memcmp(magic, "MRQS0003", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0003 file");
+        if (std::memcmp(magic, "MRQS0004", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0004 file");
         std::unique_ptr<mrq_index> ix(new mrq_index());
         hip_check(hipGetDevice(&ix->device), "hipGetDevice");
         int64_t h64[2];

@@ -321,7 +321,7 @@ hipError_t launch_kmeans_centroids(const double* sums, const int32_t* cnt, int k
 // List-major layout: row r of the index holds vector perm[r] (or padding when perm[r] < 0).
 
 __global__ __launch_bounds__(256) void k_gather_layout(
-    const float* __restrict__ xt_id, int D, int D4, const int32_t* __restrict__ perm, int64_t Npad,
+    const float* __restrict__ Xraw, int D, int D4, const int32_t* __restrict__ perm, int64_t Npad,
     const float* __restrict__ xd_id, int d, int d4, const double* __restrict__ ax64,
     const double* __restrict__ tx64, const int64_t* __restrict__ list_off, int nlist,
     const float* __restrict__ C, float* __restrict__ Xl, float* __restrict__ xdl, float* __restrict__ axl,
@@ -336,12 +336,9 @@ __global__ __launch_bounds__(256) void k_gather_layout(
         if (list_off[mid] <= r) lo = mid; else hi = mid - 1;
     }
     const int j = lo;
-    // x_p = (x_d, x_r) in PCA coordinates, zero padded to D4
-    for (int i = lane; i < D4; i += 64) {
-        float v = 0.f;
-        if (id >= 0 && i < D) v = i < d ? xd_id[(int64_t)id * d4 + i] : xt_id[(int64_t)id * (D - d) + (i - d)];
-        Xl[r * D4 + i] = v;
-    }
+    // the original vector, zero padded to D4 (the exact stage computes ||x - q||^2 = ||x_p - q_p||^2 from
+    // it, so no projection rounding enters the exact distances)
+    for (int i = lane; i < D4; i += 64) Xl[r * D4 + i] = (id >= 0 && i < D) ? Xraw[(int64_t)id * D + i] : 0.f;
     for (int i = lane; i < d4; i += 64) {
         float v = (id >= 0 && i < d) ? xd_id[(int64_t)id * d4 + i] : 0.f;
         xdl[r * d4 + i] = v;
@@ -355,10 +352,10 @@ __global__ __launch_bounds__(256) void k_gather_layout(
     }
 }
 
-hipError_t launch_gather_layout(const Index& ix, const float* xt_id, const int32_t* perm, const float* xd_id,
+hipError_t launch_gather_layout(const Index& ix, const float* Xraw, const int32_t* perm, const float* xd_id,
                                 const double* ax64, const double* tx64, double* txr, int32_t* row_list, float* O,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_layout, dim3((unsigned)((ix.Npad + 3) / 4)), dim3(256), 0, s, xt_id, ix.D, ix.D4,
+    hipLaunchKernelGGL(k_gather_layout, dim3((unsigned)((ix.Npad + 3) / 4)), dim3(256), 0, s, Xraw, ix.D, ix.D4,
                        perm, ix.Npad, xd_id, ix.d, ix.d4, ax64, tx64, ix.list_off, ix.nlist, ix.C, ix.X, ix.xd,
                        ix.ax, txr, ix.ids, row_list, O);
     return hipGetLastError();

@@ -95,7 +95,7 @@ struct Index {
     float* fSX = nullptr;        // Npad: 2 sum_i u_i - (2^B - 1) d
     float* xd = nullptr;         // Npad x d4 leading coordinates of x_p
     float* ax = nullptr;         // Npad: ||x - mu||^2
-    float* X = nullptr;          // Npad x D4 vectors in PCA coordinates x_p = P_p (x - mu), list order
+    float* X = nullptr;          // Npad x D4 original vectors (zero padded), list order: the exact stage
     // export-only per-row summaries (list order)
     float *nx = nullptr, *tx = nullptr, *xi1 = nullptr, *xiB = nullptr, *yn = nullptr;
     // MR-SQ codes (built on request): dq = 16 ceil(d / 16) (0 = none); per coordinate the grid lo / delta
@@ -185,7 +185,7 @@ hipError_t launch_kmeans_accum(const float* P, int64_t n, int ldp, int dim, cons
 hipError_t launch_kmeans_centroids(const double* sums, const int32_t* cnt, int k, int dim, float* C,
                                    int ldc, float* cn2, hipStream_t s);
 hipError_t launch_sqnorms(const float* A, int64_t n, int lda, int dim, float* out, hipStream_t s);
-hipError_t launch_gather_layout(const Index& ix, const float* xt_id, const int32_t* perm,
+hipError_t launch_gather_layout(const Index& ix, const float* Xraw, const int32_t* perm,
                                 const float* xd_id, const double* ax64, const double* tx64, double* txr,
                                 int32_t* row_list, float* O, hipStream_t s);
 hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, const double* tx64_rows,

@@ -75,8 +75,8 @@ __device__ __forceinline__ uint32_t ord_bits(float f) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Exact squared distance (Algorithm 2, exact stage) ||x_p - q_p||^2 (= ||x - q||^2, Eq 1) of two
-// zero-padded rows of D4 floats in PCA coordinates, computed by a group of 16 lanes: lane l of the group
+// Exact squared distance (Algorithm 2, exact stage) ||x - q||^2 (= ||x_p - q_p||^2, Eq 1) of two
+// zero-padded rows of D4 floats (the original vectors), computed by a group of 16 lanes: lane l of the group
 // accumulates the float4 chunks l, l + 16, l + 32, ... in ascending order, then a butterfly over the
 // group.  A wave evaluates four pairs at once; the value of a pair depends only on its two rows.
 __device__ __forceinline__ void acc_sqdiff(float& s, const float4& a, const float4& b) {
@@ -632,8 +632,8 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
     const int r = D - d;
     float s = 0.f;
     for (int i = lane; i < D4; i += 64) {
-        // q_p = P_p (q - mu) padded to D4: the leading d coordinates, then the tail
-        qpad[q * D4 + i] = i < d ? qd[q * d4 + i] : (i < D ? qtail[q * (int64_t)r + (i - d)] : 0.f);
+        // the query as given, padded to D4, for the exact stage (||x - q||^2 from the original vectors)
+        qpad[q * D4 + i] = i < D ? qr[i] : 0.f;
         if (i < D) {
             float c = qr[i] - mu[i];
             s = fmaf(c, c, s);
@@ -2447,7 +2447,7 @@ __global__ __launch_bounds__(256) void k_sq_select(int q0, const float* __restri
     if (t == 0) selcnt[qi] = min(s_num, R);
 }
 
-// One block per query of the chunk: exact distances ||x_p - q_p||^2 of its re-rank candidates (16 lanes
+// One block per query of the chunk: exact distances ||x - q||^2 of its re-rank candidates (16 lanes
 // per candidate, as in the exact stage of the MRQ path) into its result slots.
 __global__ __launch_bounds__(256) void k_sq_exact(int q0, const int32_t* __restrict__ sel, const int32_t* __restrict__ selcnt,
                                                   int R, const float* __restrict__ X, const float* __restrict__ qpad,
