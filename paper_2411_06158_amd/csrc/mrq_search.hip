@@ -548,6 +548,105 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
     return hipGetLastError();
 }
 
+// The query's tail coordinates (axes d .. D-1 of q_p = P_p (q - mu)) on the BF16 matrix cores.  They only
+// feed sigma and eps_r (Eq 6): the exact stage reads the original vectors and q_d comes from the FP32
+// product.  The operands are first converted once per search into BF16 rows of Kp = 32 ceil(K / 32)
+// elements, zero beyond K: bf16(q - mu) per query and bf16(P_p row) per tail axis.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// out[r][k] = bf16(src[r][k] - sub[k]) for k < K (sub may be null), 0 for K <= k < Kp; one thread per element
+__global__ void k_to_bf16(const float* __restrict__ src, int64_t lds, const float* __restrict__ sub, int K, int Kp,
+                          int64_t rows, __bf16* __restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= rows * Kp) return;
+    const int64_t r = t / Kp;
+    const int k = (int)(t - r * Kp);
+    out[t] = (__bf16)(k < K ? src[r * lds + k] - (sub ? sub[k] : 0.f) : 0.f);
+}
+
+// C[m][n] = sum_{k < Kp} A[m][k] B[n][k] for BF16 rows of Kp elements (Kp a multiple of 32), FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l feeds row l % 16 of both operands with k = 8 (l / 16) .. + 7 of the step and
+// holds C[16 i + 4 (l / 16) + v][16 j + l % 16]), one wave per 64 x 64 tile.
+__global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, const __bf16* __restrict__ Bm, int Kp,
+                                                   float* __restrict__ Cm, int64_t ldc, int64_t M, int N) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, kg = lane >> 4;
+    const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
+    const int n0 = blockIdx.y * 64;
+    if (m0 >= M) return;
+    const bf16x8* ar[4];
+    const bf16x8* br[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t m = m0 + 16 * i + li;
+        ar[i] = reinterpret_cast<const bf16x8*>(A + (m < M ? m : M - 1) * Kp) + kg;
+        const int n = n0 + 16 * i + li;
+        br[i] = reinterpret_cast<const bf16x8*>(Bm + (int64_t)(n < N ? n : N - 1) * Kp) + kg;
+    }
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int s4 = 0; s4 < Kp / 8; s4 += 4) {  // K step of 32: bf16x8 index s4 + kg
+        bf16x8 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            av[i] = ar[i][s4];
+            bv[i] = br[i][s4];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int n = n0 + 16 * j + li;
+        if (n >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int64_t m = m0 + 16 * i + 4 * kg + v;
+                if (m < M) Cm[m * ldc + n] = acc[i][j][v];
+            }
+        }
+    }
+}
+
+// BF16 staging for the tail product of nq queries: nq + D - d rows of 32 ceil(D / 32) elements
+static int64_t bf16_stage_elems(const Index& ix, int64_t nq) {
+    return (nq + (ix.D - ix.d)) * (int64_t)((ix.D + 31) / 32 * 32);
+}
+
+// Algorithm 2, projection of a query batch: q_d = P_p[:d] (q - mu) (FP32 matrix cores; zero padded to d4)
+// and the tail coordinates for Eq 6 (BF16 matrix cores when a staging buffer of bf16_stage_elems is given,
+// else FP32 with q_d in the same product).
+static hipError_t launch_query_projection(const Index& ix, const float* Q, int64_t nq, float* qd, float* qtail,
+                                          __bf16* stage, hipStream_t s) {
+    const int D = ix.D, d = ix.d, d4 = ix.d4;
+    hipError_t e = launch_fill_f32(qd, 0.f, nq * d4, s);
+    if (e != hipSuccess) return e;
+    if (stage && D > d) {
+        e = launch_gemm_mfma<0>(Q, D, ix.mu, ix.Pp, D, qd, d4, nq, d, D, nullptr, nullptr, nullptr, 0, 0, s);
+        if (e != hipSuccess) return e;
+        const int Kp = (D + 31) / 32 * 32;
+        __bf16* qb = stage;
+        __bf16* pb = stage + nq * (int64_t)Kp;
+        const int64_t nqe = nq * (int64_t)Kp, npe = (int64_t)(D - d) * Kp;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nqe + 255) / 256)), dim3(256), 0, s, Q, (int64_t)D, ix.mu, D,
+                           Kp, nq, qb);
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((npe + 255) / 256)), dim3(256), 0, s, ix.Pp + (size_t)d * D,
+                           (int64_t)D, (const float*)nullptr, D, Kp, (int64_t)(D - d), pb);
+        const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)((D - d + 63) / 64));
+        hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, qb, pb, Kp, qtail, (int64_t)(D - d), nq, D - d);
+        return hipGetLastError();
+    }
+    // all D axes in one product: columns < d are q_d, the rest the tail coordinates
+    return launch_gemm_mfma<2>(Q, D, ix.mu, ix.Pp, D, qd, d4, nq, D, D, nullptr, nullptr, qtail, D - d, d, s);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Exclusive prefix sum of an int32 array in one workgroup (256 threads x 64 items per pass, so the
 // (phase, list) buckets of the phases a search uses take one pass).  One wave per SIMD, so it finds room
@@ -2485,6 +2584,7 @@ struct Carve {
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
     int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *qcnt;
+    __bf16* qbf;  // BF16 staging of the tail product
     int4* desc;
     PairRec* recs;
     int8_t* qu8;
@@ -2539,6 +2639,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
     w.slots = c.take<unsigned long long>(total_slots);
     w.qcnt = c.take<int32_t>(nq);
+    w.qbf = c.take<__bf16>(bf16_stage_elems(ix, nq));
     const int64_t cap = surv_capacity(ix, total_pairs);
     w.surv = c.take<int32_t>(cap);
     *used = c.used;
@@ -2776,8 +2877,7 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
     const int G = a.group > 16 ? 32 : 16;
     {   // the projection and the centroid ranking of the MRQ path
         Timed t(tm, s, "project");
-        HIP_TRY(launch_fill_f32(w.qd, 0.f, nq * d4, s));
-        HIP_TRY(launch_gemm_mfma<2>(a.Q, D, ix.mu, ix.Pp, D, w.qd, d4, nq, D, D, nullptr, nullptr, w.qtail, D - d, d, s));
+        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, nullptr, s));
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4, w.qtail,
                            ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
         HIP_TRY(hipGetLastError());
@@ -2857,10 +2957,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
 
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
         Timed t(tm, s, "project");
-        HIP_TRY(launch_fill_f32(w.qd, 0.f, nq * d4, s));
-        // all D axes in one product: columns < d are q_d, the rest the tail coordinates of Eq 6
-        HIP_TRY(launch_gemm_mfma<2>(a.Q, D, ix.mu, ix.Pp, D, w.qd, d4, nq, D, D, nullptr, nullptr, w.qtail,
-                                    D - d, d, s));
+        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, w.qbf, s));
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4,
                            w.qtail, ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
         HIP_TRY(hipGetLastError());
