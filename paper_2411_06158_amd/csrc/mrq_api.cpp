@@ -200,7 +200,9 @@ void KernelTimer::begin(hipStream_t s, const char* name, Pending* p) {
         if (!pool.empty()) {
             *e = pool.back();
             pool.pop_back();
-        } else if (hipEventCreate(e) != hipSuccess) {
+        } else if (hipEventCreateWithFlags(e, hipEventDisableSystemFence) != hipSuccess) {
+            // timing markers only (read after a synchronisation): no system-scope fence, which would write
+            // back the caches between the kernels being timed
             p->slot = -1;
             return;
         }
