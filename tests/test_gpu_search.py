@@ -203,6 +203,26 @@ def test_probe_selection_kernels_agree(nlist):
         ix.close()
 
 
+@pytest.mark.parametrize("D", [100, 102])
+def test_dimensions_off_the_tiles(D):
+    """D = 100 (float4-aligned rows, not a multiple of 32: the query's tail coordinates come from the BF16
+    product on zero-padded rows) and D = 102 (rows not float4-aligned: the FP32 product of every axis) both
+    give the oracle's results."""
+    print(f"\n[gpu] build N=8000 D={D} d=32 B=1 nlist=32", flush=True)
+    m = synth.build_model(synth.MixtureSpec(D=D, n_comp=32, decay=1.0, cluster_dims=8, model_seed=5))
+    X, Q = synth.sample(m, 8000, 1), synth.sample(m, 40, 2)
+    Xd = torch.from_numpy(X).cuda()
+    ix = mrq.Index.build(Xd, d_r=32, bits=1, nlist=32)
+    try:
+        path = os.path.join(tempfile.mkdtemp(), "ix.mrqx")
+        ix.export(path)
+        env = dict(X=X, Q=Q, ix=ix, Qd=torch.from_numpy(Q).cuda(), orc=oracle.Index.load_export(path, X))
+        ids, dists = _search(env, 10, 8)
+        _assert_parity(env, ids, dists, 10, 8)
+    finally:
+        ix.close()
+
+
 def test_counters_monotone(small):
     cnt = np.zeros(8, dtype=np.int64)
     small["ix"].search(small["Q"][:20].copy(), 10, 8, counters=cnt)
