@@ -978,7 +978,7 @@ __global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, i
 // smaller ones; ranks below np are the output positions.  With more lists at or below t than fit, the
 // np-th smallest key is found bitwise, counting over the row in each round (pattern, then list id among
 // the ties), and the np lists are gathered and sorted.  The lists and their order are those of k_select.
-constexpr int kSelStreamCap = 512;
+constexpr int kSelStreamCap = 256;  // about 64 ln 65 ~ 267 lists fall at or below the threshold at np = 64
 
 __global__ __launch_bounds__(256) void k_select_s(const float* __restrict__ G, int nlist,
                                                   const int32_t* __restrict__ npq,

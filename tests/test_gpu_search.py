@@ -189,6 +189,19 @@ def test_probe_selection_kernels_agree(nlist):
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
     ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
     try:
+        if nlist > 4096:
+            # the streaming form's fallback runs where more than 256 lists fall at or below the np-th smallest
+            # lane minimum (lane l: lists l + 64 u): check on the exported centroids that some query does
+            path = os.path.join(tempfile.mkdtemp(), "ix.mrqx")
+            ix.export(path)
+            raw = oracle.Index.load_export(path)
+            mu, Pp, C = raw.get("mu"), raw.get("Pp"), raw.get("C").astype(np.float64)
+            qd = (Q.astype(np.float64) - mu) @ Pp[:C.shape[1]].T
+            g = ((qd[:, None, :] - C[None, :, :]) ** 2).sum(-1)
+            pad = np.full((g.shape[0], (-nlist) % 64), np.inf)
+            mins = np.concatenate([g, pad], 1).reshape(g.shape[0], -1, 64).min(1)
+            thr = np.sort(mins, 1)[:, 63]
+            assert ((g <= thr[:, None]).sum(1) > 256).any()
         Qd = torch.from_numpy(Q).cuda()
         for np_small in (1, 7, 20, 64):
             ks = np.full(60, 10, np.int32)
