@@ -216,14 +216,16 @@ def test_probe_selection_kernels_agree(nlist):
         ix.close()
 
 
-@pytest.mark.parametrize("D", [100, 102])
+@pytest.mark.parametrize("D", [100, 102, 2112])
 def test_dimensions_off_the_tiles(D):
     """D = 100 (float4-aligned rows, not a multiple of 32: the query's tail coordinates come from the BF16
-    product on zero-padded rows) and D = 102 (rows not float4-aligned: the FP32 product of every axis) both
-    give the oracle's results."""
-    print(f"\n[gpu] build N=8000 D={D} d=32 B=1 nlist=32", flush=True)
+    product on zero-padded rows), D = 102 (rows not float4-aligned: the FP32 product of every axis) and
+    D = 2112 (query rows too long to stage in the seed pass's LDS: its global-memory form) all give the
+    oracle's results."""
+    N = 8000 if D < 1000 else 3000
+    print(f"\n[gpu] build N={N} D={D} d=32 B=1 nlist=32", flush=True)
     m = synth.build_model(synth.MixtureSpec(D=D, n_comp=32, decay=1.0, cluster_dims=8, model_seed=5))
-    X, Q = synth.sample(m, 8000, 1), synth.sample(m, 40, 2)
+    X, Q = synth.sample(m, N, 1), synth.sample(m, 40, 2)
     Xd = torch.from_numpy(X).cuda()
     ix = mrq.Index.build(Xd, d_r=32, bits=1, nlist=32)
     try:
