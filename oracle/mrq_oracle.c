@@ -373,6 +373,7 @@ struct orc_index {
     int32_t D, d, B, nlist;
     double *mu, *Pp, *lam, *Pr, *C;  /* D, D*D (row i = axis i), D, d*d, nlist*d */
     int64_t *off, *lid;               /* list boundaries; ids in list order */
+    int64_t *pos;                     /* per id: its list position (inverse of lid), or -1 */
     uint8_t *code;                    /* per list position: d level indices */
     float *sq_lo, *sq_delta;          /* MR-SQ grid (S1, S2): d each, or NULL */
     uint8_t *sq_code;                 /* MR-SQ codes per list position: d bytes each */
@@ -384,7 +385,7 @@ struct orc_index {
 void orc_free(orc_index *ix) {
     if (!ix) return;
     free(ix->mu); free(ix->Pp); free(ix->lam); free(ix->Pr); free(ix->C);
-    free(ix->off); free(ix->lid); free(ix->code); free(ix->xd);
+    free(ix->off); free(ix->lid); free(ix->pos); free(ix->code); free(ix->xd);
     free(ix->nx); free(ix->tx); free(ix->ax); free(ix->xi1); free(ix->xiB); free(ix->yn);
     free(ix->sq_lo); free(ix->sq_delta); free(ix->sq_code);
     free(ix);
@@ -401,17 +402,25 @@ static orc_index *alloc_index(int64_t N, int32_t D, int32_t d, int32_t B, int32_
     ix->C = calloc((size_t)nlist * d, sizeof(double));
     ix->off = calloc(nlist + 1, sizeof(int64_t));
     ix->lid = calloc(N, sizeof(int64_t));
+    ix->pos = calloc(N, sizeof(int64_t));
     ix->code = calloc((size_t)N * d, 1);
     ix->xd = calloc((size_t)N * d, sizeof(double));
     ix->nx = calloc(N, sizeof(double)); ix->tx = calloc(N, sizeof(double));
     ix->ax = calloc(N, sizeof(double)); ix->xi1 = calloc(N, sizeof(double));
     ix->xiB = calloc(N, sizeof(double)); ix->yn = calloc(N, sizeof(double));
-    if (!ix->mu || !ix->Pp || !ix->lam || !ix->Pr || !ix->C || !ix->off || !ix->lid || !ix->code ||
+    if (!ix->mu || !ix->Pp || !ix->lam || !ix->Pr || !ix->C || !ix->off || !ix->lid || !ix->pos || !ix->code ||
         !ix->xd || !ix->nx || !ix->tx || !ix->ax || !ix->xi1 || !ix->xiB || !ix->yn) {
         orc_free(ix);
         return NULL;
     }
     return ix;
+}
+
+/* pos[id] = list position of id (ids outside [0, N) are ignored; an id listed twice keeps its last). */
+static void index_positions(orc_index *ix) {
+    for (int64_t n = 0; n < ix->N; n++) ix->pos[n] = -1;
+    for (int64_t p = 0; p < ix->N; p++)
+        if (ix->lid[p] >= 0 && ix->lid[p] < ix->N) ix->pos[ix->lid[p]] = p;
 }
 
 /* Encode list position p from its x_d and centroid (Algorithm 1, normalise-and-quantise step). */
@@ -495,6 +504,7 @@ orc_index *orc_build(const float *X, int64_t N, int32_t D, int32_t d, int32_t B,
     for (int j = 0; j < nlist; j++) fill[j] = ix->off[j];
     for (int64_t n = 0; n < N; n++) ix->lid[fill[assign[n]]++] = n; /* ascending id per list */
     free(fill);
+    index_positions(ix);
     /* random rotation and codes (Algorithm 1, last two steps) */
     orc_haar(d, seed ^ 0x524F54415445ULL, ix->Pr);
     for (int j = 0; j < nlist; j++) {
@@ -569,6 +579,7 @@ orc_index *orc_import(const char *path, const float *X, int64_t Nx, int32_t Dx) 
     }
     fclose(f);
     if (!ok) { orc_free(ix); return NULL; }
+    index_positions(ix);
     if (X) {
         double *xc = malloc(sizeof(double) * D), *o = malloc(sizeof(double) * d);
         double *xp = malloc(sizeof(double) * d);
@@ -909,11 +920,14 @@ int orc_topk_risk(const orc_index *ix, const float *q, int32_t k, int32_t nprobe
     for (int i = 0; i < k; i++) {
         risk[i] = 0;
         if (ids[i] < 0) continue;
-        int64_t pos = -1;
-        int32_t list = -1;
-        for (int j = 0; j < ix->nlist && pos < 0; j++)
-            for (int64_t t = ix->off[j]; t < ix->off[j + 1]; t++)
-                if (ix->lid[t] == ids[i]) { pos = t; list = j; break; }
+        const int64_t pos = ix->pos[ids[i]];
+        /* the list holding position pos: the largest j with off[j] <= pos (every earlier list, empty or
+         * not, also has off[j] <= pos, at a smaller index; a later list starts beyond pos) */
+        int32_t list = 0;
+        for (int32_t lo = 0, hi = ix->nlist - 1; lo <= hi;) {
+            const int32_t mid = lo + (hi - lo) / 2;
+            if (ix->off[mid] <= pos) { list = mid; lo = mid + 1; } else hi = mid - 1;
+        }
         pair_state(ix, qs.qp, list, p->bq, &ps);
         cstate cs;
         cand_state(ix, pos, &qs, &ps, p->eps0, &cs);
