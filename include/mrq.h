@@ -150,6 +150,25 @@ mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_
                       int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
 
 /*
+ * mrq_search_noalloc — mrq_search for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and results as
+ * mrq_search, with the search's workspace taken from a fixed device buffer of MRQ_NOALLOC_BYTES that the
+ * library holds on each device it runs on until the process ends.  The call makes no device or host
+ * allocation: no hipMalloc / hipFree, no stream or event creation (the seed pass runs on `stream` itself,
+ * before the pair preparation), no kernel-timing events (timing is ignored).
+ *   Q, ids, dists (and opts->counters, if set) must be device pointers; otherwise MRQ_EINVAL.
+ *   A search whose workspace (metadata, projected queries, probe distances nq x nlist, pair records and
+ *   query levels, the exact-stage buffer) exceeds MRQ_NOALLOC_BYTES fails with MRQ_EINVAL before any
+ *   device work; split the batch.  Other arguments and errors as for mrq_search.
+ * Every call on a device shares that device's buffer and leaves its contents behind (the search clears
+ * what it needs with its own fill kernels), so calls that overlap on one device — on different streams or
+ * host threads, on any index — race and must be serialised by the caller.
+ */
+#define MRQ_NOALLOC_BYTES ((size_t)128 << 20)
+mrq_status mrq_search_noalloc(const mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe,
+                              int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
+
+/*
  * mrq_tune — autotuner of the scan schedule: runs mrq_search on Q (nq queries, host or device) with each
  * query-group size of the scan work items (16, 32, 64 queries per 64-vector block) and each phase growth
  * (2, 4, 8), times each on `stream` with HIP events, and makes the fastest pair the index's default (used

@@ -23,8 +23,9 @@ EXPORTED = [
     "mrq_build_opts_default", "mrq_search_opts_default", "mrq_build", "mrq_search", "mrq_search_mixed",
     "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
     "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
-    "mrq_server_destroy", "mrq_choose_dr", "mrq_tune",
+    "mrq_server_destroy", "mrq_choose_dr", "mrq_tune", "mrq_search_noalloc",
 ]
+NOALLOC_BYTES = 128 << 20  # MRQ_NOALLOC_BYTES
 
 
 class MRQError(RuntimeError):
@@ -60,6 +61,7 @@ def lib() -> C.CDLL:
         L.mrq_build.argtypes = [P, I64, I32, I32, I32, I32, C.POINTER(BuildOpts), P, C.POINTER(P)]
         L.mrq_search.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_mixed.argtypes = [P, P, I64, P, P, P, P, P, C.POINTER(SearchOpts), P]
+        L.mrq_search_noalloc.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
         L.mrq_index_info.argtypes = [P, P, P, P, P, P, P]
         L.mrq_export.argtypes = [P, C.c_char_p]
         L.mrq_save.argtypes = [P, C.c_char_p]
@@ -190,6 +192,15 @@ class Index:
         o = opts if opts is not None else search_opts(**kw)
         _check(lib().mrq_search(self._h, _ptr(Q), nq, k, nprobe, _ptr(ids), _ptr(dists), C.byref(o),
                                 _stream(stream)))
+        return ids, dists
+
+    def search_noalloc(self, Q, k: int, nprobe: int, ids, dists, opts: Optional[SearchOpts] = None, stream=None,
+                       **kw):
+        """mrq_search_noalloc: the search into caller-allocated device tensors ids (nq x k int64) and dists
+        (nq x k float32), with the workspace in the library's fixed device buffer (no allocation)."""
+        o = opts if opts is not None else search_opts(**kw)
+        _check(lib().mrq_search_noalloc(self._h, _ptr(Q), int(Q.shape[0]), k, nprobe, _ptr(ids), _ptr(dists),
+                                        C.byref(o), _stream(stream)))
         return ids, dists
 
     def search_mixed(self, Q, k, nprobe, opts: Optional[SearchOpts] = None, stream=None, **kw):

@@ -503,8 +503,10 @@ void resolve_opts(const mrq_search_opts* in, mrq_search_opts* o) {
 
 mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uniform_kq, int32_t k_u, int32_t np_u,
                       const int32_t* k_arr, const int32_t* np_arr, const int64_t* out_off_arr, int64_t* ids,
-                      float* dists, const mrq_search_opts* opts_in, hipStream_t s) {
+                      float* dists, const mrq_search_opts* opts_in, hipStream_t s, void* fixed_ws = nullptr,
+                      size_t fixed_bytes = 0) {
     mrq_index* ix = const_cast<mrq_index*>(cix);
+    const bool fixed = fixed_ws != nullptr;  // the allocation-free search: caller buffers plus a fixed workspace
     if (!ix) throw Fail(MRQ_EINVAL, "index is NULL");
     if (!Q || !ids || !dists) throw Fail(MRQ_EINVAL, "Q, ids and dists must not be NULL");
     if (nq < 1 || nq > (int64_t)1 << 28) throw Fail(MRQ_EINVAL, "nq must be in [1, 2^28]");
@@ -581,6 +583,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     const int64_t pairs_run = per_query ? np_max : total_pairs;
     const bool q_dev = is_device_ptr(Q), ids_dev = is_device_ptr(ids), d_dev = is_device_ptr(dists);
     const bool cnt_host = o.counters && !is_device_ptr(o.counters);
+    if (fixed && (!uniform_kq || !q_dev || !ids_dev || !d_dev || cnt_host))
+        throw Fail(MRQ_EINVAL, "the allocation-free search takes device Q, ids, dists and counters and a uniform k / nprobe");
 
     // workspace: metadata, staging copies, then the search scratch
     auto layout = [&](char* base, size_t* used, int32_t** kq, int32_t** npq, int64_t** so, int64_t** po, int64_t** oo,
@@ -604,7 +608,17 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     void* sw;
     size_t need = 0;
     layout(nullptr, &need, &kq, &npq, &so, &po, &oo, &qs, &ids_s, &d_s, &cnt_s, &sw);
-    std::lock_guard<std::mutex> lock(ix->mu_ws);
+    if (fixed) {
+        if (need > fixed_bytes)
+            throw Fail(MRQ_EINVAL, "this search needs " + std::to_string(need) + " bytes of workspace; the allocation-free "
+                       "search has " + std::to_string(fixed_bytes) + " (split the batch, or use mrq_search)");
+        layout(reinterpret_cast<char*>(fixed_ws), &need, &kq, &npq, &so, &po, &oo, &qs, &ids_s, &d_s, &cnt_s, &sw);
+    }
+    std::unique_lock<std::mutex> lock(ix->mu_ws, std::defer_lock);
+    if (!fixed) lock.lock();
+    if (fixed) {
+        // nothing of the index's own workspace is touched: no growth, no ordering event
+    } else {
     if (capturing && ix->ws.bytes < need)
         throw Fail(MRQ_ESTATE, "run the same search once before capturing it (its workspace cannot grow during capture)");
     if (ix->ws_event_recorded && !capturing) hip_check(hipStreamWaitEvent(s, ix->ws_event, 0), "order workspace");
@@ -622,7 +636,10 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         ix->ws.bytes = grow;
     }
     layout(reinterpret_cast<char*>(ix->ws.base), &need, &kq, &npq, &so, &po, &oo, &qs, &ids_s, &d_s, &cnt_s, &sw);
-    const size_t sw_bytes = ix->ws.bytes - (size_t)(reinterpret_cast<char*>(sw) - reinterpret_cast<char*>(ix->ws.base));
+    }
+    char* const ws_base = fixed ? reinterpret_cast<char*>(fixed_ws) : reinterpret_cast<char*>(ix->ws.base);
+    const size_t ws_total = fixed ? fixed_bytes : ix->ws.bytes;
+    const size_t sw_bytes = ws_total - (size_t)(reinterpret_cast<char*>(sw) - ws_base);
 
     const float* Qd = Q;
     if (!q_dev) {
@@ -660,6 +677,10 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.rerank = rerank;
     a.phase_shift = o.phase_growth == 2 ? 1 : (o.phase_growth == 4 ? 2 : (o.phase_growth == 8 ? 3 : ix->phase_shift_default));
     a.counters = cnt_d;
+    if (fixed) {
+        a.timed = false;      // timing events would be created on demand
+        a.fork_seed = false;  // no auxiliary stream or events to create
+    }
     if (!per_query) {
         if (uniform_kq) hip_check(launch_uniform_meta(nq, k_u, np_u, kq, npq, so, po, oo, s), "meta");
         a.Q = Qd;
@@ -699,7 +720,9 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
             hip_check(launch_search(a, sw, sw_bytes, s), "search");
         }
     }
-    if (!capturing) {
+    if (fixed) {
+        // the fixed buffer is not the index's workspace
+    } else if (!capturing) {
         hip_check(hipEventRecord(ix->ws_event, s), "record");
         ix->ws_event_recorded = true;
     } else {
@@ -921,6 +944,17 @@ mrq_status mrq_search(const mrq_index* index, const float* Q, int64_t nq, int32_
     return guarded([&]() {
         return run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts,
                           (hipStream_t)stream);
+    });
+}
+
+mrq_status mrq_search_noalloc(const mrq_index* index, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                              int64_t* ids, float* dists, const mrq_search_opts* opts, mrq_stream stream) {
+    return guarded([&]() {
+        void* buf = nullptr;
+        size_t bytes = 0;
+        hip_check(noalloc_scratch(&buf, &bytes), "fixed search buffer");
+        return run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts,
+                          (hipStream_t)stream, buf, bytes);
     });
 }
 

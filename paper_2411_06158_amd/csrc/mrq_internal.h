@@ -153,11 +153,17 @@ struct SearchArgs {
     float* dists;          // device output
     int64_t* counters;     // device int64[8] or null
     bool timed = true;     // record per-kernel events when the index timer is on
+    bool fork_seed = true; // run the seed pass on the index's auxiliary stream beside the pair preparation
 };
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,
                               int bq, int np_max, int method, int rerank);
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s);
+
+// The allocation-free search's fixed device buffer on the current device (a file-scope device array of
+// kNoAllocBytes, its address looked up once per device).
+constexpr size_t kNoAllocBytes = MRQ_NOALLOC_BYTES;
+hipError_t noalloc_scratch(void** p, size_t* bytes);
 
 // build-side launchers
 // MR-SQ codes of an index whose x_d and ids are in place (tx64_rows: FP64 ||x_r||^2 per row; scratch:

@@ -2940,6 +2940,32 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
     return hipSuccess;
 }
 
+// ---- fixed device buffer of the allocation-free search ---------------------------------------------
+// One array per device, held for the life of the process.  Host code must not pass `scratch` itself to a
+// kernel (in host code the name stands for a host-side shadow, not a device address): its device address
+// is looked up once per device with hipGetSymbolAddress and only that address is used.
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(void** p, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* a = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));  // with `dev` current
+        if (!a) return hipErrorInvalidSymbol;
+        addr[dev] = a;
+    }
+    *p = addr[dev];
+    *bytes = kNoAllocBytes;
+    return hipSuccess;
+}
+
 hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStream_t s) {
     if (a.method == MRQ_METHOD_MRSQ) return launch_search_mrsq(a, ws, ws_bytes, s);
     const Index& ix = *a.ix;
@@ -2989,21 +3015,25 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.cq = (int)(cap / nq);
     // The seed pass (each query's nearest list; it computes that pair's query code itself) runs on the
     // index's auxiliary stream beside the pair preparation; the phases wait for both.
+    // Without a fork (the allocation-free search) the seed pass runs first on the search stream.
     HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
     HIP_TRY(launch_fill_i32(w.qcnt, 0, nq, s));
-    if (!ix.aux) {
-        HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&ix.ev_join, hipEventDisableTiming));
+    if (a.fork_seed) {
+        if (!ix.aux) {
+            HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&ix.ev_join, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(ix.ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(ix.aux, ix.ev_fork, 0));
     }
-    HIP_TRY(hipEventRecord(ix.ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(ix.aux, ix.ev_fork, 0));
+    const hipStream_t seed_s = a.fork_seed ? ix.aux : s;
     {
-        Timed t(tm, ix.aux, "seed");
-        launch_seed(c, nq, ix.aux);
+        Timed t(tm, seed_s, "seed");
+        launch_seed(c, nq, seed_s);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(ix.ev_join, ix.aux));
+    if (a.fork_seed) HIP_TRY(hipEventRecord(ix.ev_join, ix.aux));
     {   // per-pair query codes, grouped by (phase, list)
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
@@ -3034,7 +3064,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
                            ix.list_off, nlist, G, P, w.desc);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipStreamWaitEvent(s, ix.ev_join, 0));
+    if (a.fork_seed) HIP_TRY(hipStreamWaitEvent(s, ix.ev_join, 0));
     for (int p = 1; p < kPhases; p++) {
         if (a.np_max <= phase_lo(p, a.phase_shift)) break;
         c.phase = p;
