@@ -2568,6 +2568,14 @@ __global__ __launch_bounds__(256) void k_sq_exact(int q0, const int32_t* __restr
     if (counters && threadIdx.x == 0) atomicAdd((unsigned long long*)&counters[3], (unsigned long long)n);
 }
 
+// Query-level bytes stored per pair: the K slices the scan multiplies, 64 dimensions each (zero beyond d).
+// d in (128, 192] takes the 4-slice scan, so its rows are padded to 256 bytes and the fourth slice's
+// loads stay inside the pair's own row.
+static int level_bytes(int d) {
+    const int ki = (d + 63) / 64;
+    return 64 * (ki == 3 ? 4 : ki);
+}
+
 namespace {
 struct Carve {
     char* p;
@@ -2636,7 +2644,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.ioff = c.take<int32_t>(P + 1);
     w.desc = c.take<int4>(max_items(ix, total_pairs));
     w.recs = c.take<PairRec>(total_pairs);
-    w.qu8 = c.take<int8_t>(total_pairs * 64 * (int64_t)((ix.d + 63) / 64));
+    w.qu8 = c.take<int8_t>(total_pairs * (int64_t)level_bytes(ix.d));
     w.slots = c.take<unsigned long long>(total_slots);
     w.qcnt = c.take<int32_t>(nq);
     w.qbf = c.take<__bf16>(bf16_stage_elems(ix, nq));
@@ -3006,7 +3014,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.slots = w.slots; c.surv = w.surv; c.qcnt = w.qcnt; c.counters = a.counters;
     c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
-    c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = 64 * c.KI;
+    c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = level_bytes(d);
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
     // persistent scan grid (resident blocks) and each query's bin of the exact-stage buffer
     const int scan_blocks = scan_grid(c);
@@ -3042,7 +3050,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
                            w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
-        const int KP = 64 * nh;
+        const int KP = level_bytes(d);
         // 16 lanes per pair up to d = 256 (4 pairs per wave: the kernel is bound by the latency of its loads
         // and atomic), a whole wave beyond
 #define PREP(NHV, LV)                                                                                      \

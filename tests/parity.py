@@ -42,52 +42,100 @@ def _probe_tie(orc_ix, q, npi):
     return npi < orc_ix.nlist and abs(gl[npi] - gl[npi - 1]) <= 1e-4 * max(gl[npi - 1], 1e-30)
 
 
+def _check_one(orc_ix, X, q, g, gd, ki, npi, prm, rel, risk_rel, tie_rel):
+    """One row: (category, detail); categories as in check_rows."""
+    b = _row_basics(X, q, g, gd, rel)
+    if isinstance(b, str):
+        return "failure", b
+    gv, _ = b
+    _, exd0, risk0 = orc_ix.topk_risk(q, ki, npi, prm, margin=0.0)
+    fin = exd0[np.isfinite(exd0)]
+    margin = risk_rel * (float(fin.max()) if fin.size else 1.0)
+    ex, exd, risk = orc_ix.topk_risk(q, ki, npi, prm, margin=margin)
+    exv = ex[ex >= 0]
+    if set(exv.tolist()) == set(gv.tolist()):
+        return "exact_match", None
+    if _probe_tie(orc_ix, q, npi):
+        return "probe_tie", None
+    ex2, exd2 = orc_ix.search(q, ki + 1, npi, mode=0)
+    got = set(gv.tolist())
+    missing = [m for m in exv.tolist() if m not in got]
+    pos = {int(m): j for j, m in enumerate(ex.tolist())}
+    near_tie = len(exv) == ki and ex2[ki] >= 0 and abs(exd2[ki] - exd2[ki - 1]) <= tie_rel * exd2[ki - 1]
+    hard = margin_only = False
+    for m in missing:
+        j = pos[int(m)]
+        if risk0[j]:
+            hard = True        # an oracle bound of this member is at or above its exact distance
+        elif risk[j]:
+            margin_only = True  # a bound within the FP32 margin below its exact distance
+        elif near_tie and j >= ki - 1:
+            pass
+        else:
+            return "failure", f"missing {missing} (risk {risk.tolist()})"
+    if hard:
+        # the oracle's own Algorithm 2 with verification logs the same kind of bound failure for this query
+        _, _, cnt = orc_ix.search(q, ki, npi, mode=1, prm=_verify(prm), counters=True)
+        if cnt["viol1"] + cnt["viol_ext"] + cnt["viol2"] == 0:
+            return "failure", f"missing {missing}: flagged at risk but the oracle logs no bound violation"
+        return "risk_hard", None
+    return ("risk_margin", None) if margin_only else ("tie_excused", None)
+
+
+def _verify(prm):
+    import ctypes
+
+    v = type(prm)()
+    ctypes.memmove(ctypes.addressof(v), ctypes.addressof(prm), ctypes.sizeof(prm))
+    v.verify = 1
+    return v
+
+
 def check_rows(orc_ix, X, Q, ids, dists, k, nprobe, prm, rel=1e-5, risk_rel=1e-4, tie_rel=1e-5,
-               ks=None, nprobes=None):
-    stats = dict(queries=0, exact_match=0, risk_excused=0, tie_excused=0, probe_tie=0, failures=[])
-    for i in range(Q.shape[0]):
+               ks=None, nprobes=None, threads=8):
+    """Check every row (see the module docstring); rows run on `threads` host threads (the oracle's
+    calls release the interpreter lock).  Returns counts per category:
+      exact_match   the id set equals the oracle's EXACT-IVF top-k
+      risk_hard     a missing member has an oracle bound (Eq 5 + Eq 6 stage 1, B-bit or Eq 7) at or above
+                    its exact distance: a failure of the paper's bound, which the oracle's Algorithm 2 in
+                    verification mode also logs for the query (checked)
+      risk_margin   a missing member's bound is within risk_rel (relative) below its exact distance: FP32
+                    vs FP64 rounding of the bound can put it on either side
+      tie_excused   the only differences are at a near-tie of the k-th distance
+      probe_tie     the nprobe-th and next lists are nearly equidistant (FP32 vs FP64 may take either)
+    and `failures` [(row, message)]."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = Q.shape[0]
+
+    def one(i):
         ki = k if ks is None else int(ks[i])
         npi = nprobe if nprobes is None else int(nprobes[i])
-        g = np.asarray(ids[i])[:ki]
-        gd = np.asarray(dists[i])[:ki]
-        stats["queries"] += 1
-        b = _row_basics(X, Q[i], g, gd, rel)
-        if isinstance(b, str):
-            stats["failures"].append((i, b))
-            continue
-        gv, _ = b
-        nv = len(gv)
-        probe_tie = _probe_tie(orc_ix, Q[i], npi)
-        _, exd0, _ = orc_ix.topk_risk(Q[i], ki, npi, prm, margin=0.0)
-        fin = exd0[np.isfinite(exd0)]
-        margin = risk_rel * (float(fin.max()) if fin.size else 1.0)
-        ex, exd, risk = orc_ix.topk_risk(Q[i], ki, npi, prm, margin=margin)
-        exv = ex[ex >= 0]
-        if set(exv.tolist()) == set(gv.tolist()):
-            stats["exact_match"] += 1
-            continue
-        if probe_tie:
-            stats["probe_tie"] += 1
-            continue
-        ex2, exd2 = orc_ix.search(Q[i], ki + 1, npi, mode=0)
-        missing = [m for m in exv.tolist() if m not in set(gv.tolist())]
-        pos = {int(m): j for j, m in enumerate(ex.tolist())}
-        near_tie = len(exv) == ki and ex2[ki] >= 0 and abs(exd2[ki] - exd2[ki - 1]) <= tie_rel * exd2[ki - 1]
-        ok = True
-        used_risk = False
-        for m in missing:
-            j = pos[int(m)]
-            if risk[j]:
-                used_risk = True
-            elif near_tie and j >= ki - 1:
-                pass
-            else:
-                ok = False
-        if not ok:
-            stats["failures"].append((i, f"missing {missing} (risk {risk.tolist()})"))
-            continue
-        stats["risk_excused" if used_risk else "tie_excused"] += 1
+        return _check_one(orc_ix, X, Q[i], np.asarray(ids[i])[:ki], np.asarray(dists[i])[:ki], ki, npi, prm,
+                          rel, risk_rel, tie_rel)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        res = list(ex.map(one, range(n)))
+    stats = dict(queries=n, exact_match=0, risk_hard=0, risk_margin=0, tie_excused=0, probe_tie=0, failures=[])
+    for i, (cat, detail) in enumerate(res):
+        if cat == "failure":
+            stats["failures"].append((i, detail))
+        else:
+            stats[cat] += 1
     return stats
+
+
+def soft_excuses(st) -> int:
+    """Rows excused for rounding reasons rather than a failed bound (margin, k-th tie, probe tie)."""
+    return st["risk_margin"] + st["tie_excused"] + st["probe_tie"]
+
+
+def assert_rows(st, what=""):
+    """No failures, and rounding excuses in at most max(2, 2 %) of the rows; bound failures (risk_hard) are
+    the paper's own and are reported, not capped."""
+    print(f"[parity] {what}: {dict((a, b) for a, b in st.items() if a != 'failures')}", flush=True)
+    assert not st["failures"], st["failures"][:5]
+    assert soft_excuses(st) <= max(2, 0.02 * st["queries"]), st
 
 
 def check_mrsq_rows(orc_ix, X, Q, ids, dists, k, nprobe, R, rel=1e-5, est_rel=1e-5, tie_rel=1e-5, ks=None,
