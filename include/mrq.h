@@ -169,6 +169,56 @@ mrq_status mrq_search_noalloc(const mrq_index *index, const float *Q, int64_t nq
                               int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
 
 /*
+ * mrq_search_trace — mrq_search with the per-stage values of chosen queries recorded by the search
+ * kernels themselves (a tracing instantiation of the same device code, same arithmetic), for checking
+ * each stage element by element against a reference:
+ *   per (query, list) pair (Algorithm 2, normalise / rotate / quantise the query for the list): the pair's
+ *   scalars, its FP32 rotated unit vector q' (d floats) and its B_q-bit levels u (d bytes);
+ *   per candidate and stage: stage 1 (Eq 4 estimate with the Eq 5 and Eq 6 bounds, from the integer inner
+ *   product ip = sum_i b_i u_i and pc = popcount(b)), the B-bit refinement (ip = sum_i ux_i u_i), stage 2
+ *   (Eq 7) and the exact distance, each with the threshold tau it was tested against.
+ * Q is nq x D (host), ids / dists nq x k (host); traced[] holds ntraced distinct query indices of the batch.
+ * pairs / qprime (max_pairs x d) / levels (max_pairs x d) and cands (max_cands) are host arrays; *npairs and
+ * *ncands receive the number of records produced (records beyond max_* are counted, not written).  The
+ * search runs with query group 16 (results never depend on it); opts->mode must be MRQ_BATCHED and
+ * opts->method MRQ_METHOD_MRQ; synchronous.  Debugging and testing only: slower than mrq_search.
+ */
+enum { MRQ_TRACE_STAGE1 = 1, MRQ_TRACE_EXT = 2, MRQ_TRACE_STAGE2 = 3, MRQ_TRACE_EXACT = 4 };
+
+typedef struct {
+    int32_t phase;    /* 0 = the seed pass (nearest list), p >= 1 = batched phase p */
+    int32_t q;        /* query index in the batch */
+    int32_t list;     /* IVF list */
+    int32_t su;       /* sum_i u_i */
+    float nq;         /* ||q_d - c|| */
+    float vl, delta;  /* lowest level and level step of the quantised q' */
+    float kr;         /* ||q_d - c||^2 + ||q_r||^2 - eps_r */
+    float ebc;        /* 2 ||q_d - c|| eps0 / sqrt(d - 1) */
+    float er;         /* eps_r = 2 m sigma (Eq 6) */
+    float qn2;        /* ||q - mu||^2 */
+    float pad;
+} mrq_trace_pair;
+
+typedef struct {
+    int32_t kind;     /* MRQ_TRACE_* */
+    int32_t phase;    /* as in mrq_trace_pair */
+    int32_t q, list;
+    int64_t id;       /* vector id */
+    int32_t ip;       /* STAGE1: sum_i b_i u_i; EXT: sum_i ux_i u_i (ux: the B-bit level index); else 0 */
+    int32_t pc;       /* STAGE1: popcount of the sign code; else 0 */
+    float v0;         /* STAGE1 / EXT: estimate minus eps_r, dis' - eps_r;  STAGE2: dis_o';  EXACT: ||x - q||^2 */
+    float v1;         /* STAGE1 / EXT: eps_b (Eq 5 in distance units);  STAGE2: eps_r */
+    float v2;         /* STAGE1 / EXT: the lower bound tested, dis' - eps_b - eps_r;  STAGE2: dis_o' - eps_r */
+    float v3;         /* the threshold tau of the test (+inf while the result queue is not full); NaN in the seed
+                         pass's stage 1, whose candidates are tested later against the tau of their batch */
+} mrq_trace_cand;
+
+mrq_status mrq_search_trace(const mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe,
+                            const mrq_search_opts *opts, const int32_t *traced, int32_t ntraced, int64_t *ids,
+                            float *dists, mrq_trace_pair *pairs, float *qprime, uint8_t *levels, int64_t max_pairs,
+                            int64_t *npairs, mrq_trace_cand *cands, int64_t max_cands, int64_t *ncands);
+
+/*
  * mrq_tune — autotuner of the scan schedule: runs mrq_search on Q (nq queries, host or device) with each
  * query-group size of the scan work items (16, 32, 64 queries per 64-vector block) and each phase growth
  * (2, 4, 8), times each on `stream` with HIP events, and makes the fastest pair the index's default (used

@@ -23,9 +23,19 @@ EXPORTED = [
     "mrq_build_opts_default", "mrq_search_opts_default", "mrq_build", "mrq_search", "mrq_search_mixed",
     "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
     "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
-    "mrq_server_destroy", "mrq_choose_dr", "mrq_tune", "mrq_search_noalloc",
+    "mrq_server_destroy", "mrq_choose_dr", "mrq_tune", "mrq_search_noalloc", "mrq_search_trace",
 ]
 NOALLOC_BYTES = 128 << 20  # MRQ_NOALLOC_BYTES
+
+# mrq_search_trace records (include/mrq.h)
+TRACE_STAGE1, TRACE_EXT, TRACE_STAGE2, TRACE_EXACT = 1, 2, 3, 4
+TRACE_PAIR_DTYPE = np.dtype([("phase", "<i4"), ("q", "<i4"), ("list", "<i4"), ("su", "<i4"), ("nq", "<f4"),
+                             ("vl", "<f4"), ("delta", "<f4"), ("kr", "<f4"), ("ebc", "<f4"), ("er", "<f4"),
+                             ("qn2", "<f4"), ("pad", "<f4")])
+TRACE_CAND_DTYPE = np.dtype([("kind", "<i4"), ("phase", "<i4"), ("q", "<i4"), ("list", "<i4"), ("id", "<i8"),
+                             ("ip", "<i4"), ("pc", "<i4"), ("v0", "<f4"), ("v1", "<f4"), ("v2", "<f4"),
+                             ("v3", "<f4")])
+assert TRACE_PAIR_DTYPE.itemsize == 48 and TRACE_CAND_DTYPE.itemsize == 48
 
 
 class MRQError(RuntimeError):
@@ -62,6 +72,8 @@ def lib() -> C.CDLL:
         L.mrq_search.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_mixed.argtypes = [P, P, I64, P, P, P, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_noalloc.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
+        L.mrq_search_trace.argtypes = [P, P, I64, I32, I32, C.POINTER(SearchOpts), P, I32, P, P, P, P, P, I64, P,
+                                       P, I64, P]
         L.mrq_index_info.argtypes = [P, P, P, P, P, P, P]
         L.mrq_export.argtypes = [P, C.c_char_p]
         L.mrq_save.argtypes = [P, C.c_char_p]
@@ -202,6 +214,29 @@ class Index:
         _check(lib().mrq_search_noalloc(self._h, _ptr(Q), int(Q.shape[0]), k, nprobe, _ptr(ids), _ptr(dists),
                                         C.byref(o), _stream(stream)))
         return ids, dists
+
+    def search_trace(self, Q, k: int, nprobe: int, traced, max_pairs: int = 4096, max_cands: int = 1 << 20,
+                     opts: Optional[SearchOpts] = None, **kw):
+        """mrq_search_trace on host arrays: (ids, dists, pairs, qprime, levels, cands) with the per-stage
+        records of the queries `traced` (indices into Q); raises if a buffer was too small."""
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        nq = Q.shape[0]
+        tr = np.ascontiguousarray(traced, dtype=np.int32)
+        ids = np.empty((nq, k), dtype=np.int64)
+        dists = np.empty((nq, k), dtype=np.float32)
+        pairs = np.empty(max_pairs, dtype=TRACE_PAIR_DTYPE)
+        qp = np.empty((max_pairs, self.d), dtype=np.float32)
+        lev = np.empty((max_pairs, self.d), dtype=np.uint8)
+        cands = np.empty(max_cands, dtype=TRACE_CAND_DTYPE)
+        npairs, ncands = C.c_int64(0), C.c_int64(0)
+        o = opts if opts is not None else search_opts(**kw)
+        _check(lib().mrq_search_trace(self._h, _ptr(Q), nq, k, nprobe, C.byref(o), _ptr(tr), len(tr), _ptr(ids),
+                                      _ptr(dists), pairs.ctypes.data, _ptr(qp), _ptr(lev), max_pairs,
+                                      C.byref(npairs), cands.ctypes.data, max_cands, C.byref(ncands)))
+        if npairs.value > max_pairs or ncands.value > max_cands:
+            raise MRQError(MRQ_ENOMEM, f"trace buffers too small ({npairs.value} pairs, {ncands.value} records)")
+        n, m = npairs.value, ncands.value
+        return ids, dists, pairs[:n], qp[:n], lev[:n], cands[:m]
 
     def search_mixed(self, Q, k, nprobe, opts: Optional[SearchOpts] = None, stream=None, **kw):
         """Per-query k[i] / nprobe[i]; returns (ids, dists, out_off) as flat host arrays."""

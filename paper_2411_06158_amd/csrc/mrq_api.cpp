@@ -504,7 +504,7 @@ void resolve_opts(const mrq_search_opts* in, mrq_search_opts* o) {
 mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uniform_kq, int32_t k_u, int32_t np_u,
                       const int32_t* k_arr, const int32_t* np_arr, const int64_t* out_off_arr, int64_t* ids,
                       float* dists, const mrq_search_opts* opts_in, hipStream_t s, void* fixed_ws = nullptr,
-                      size_t fixed_bytes = 0) {
+                      size_t fixed_bytes = 0, const TraceSink* trace = nullptr) {
     mrq_index* ix = const_cast<mrq_index*>(cix);
     const bool fixed = fixed_ws != nullptr;  // the allocation-free search: caller buffers plus a fixed workspace
     if (!ix) throw Fail(MRQ_EINVAL, "index is NULL");
@@ -677,6 +677,9 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.rerank = rerank;
     a.phase_shift = o.phase_growth == 2 ? 1 : (o.phase_growth == 4 ? 2 : (o.phase_growth == 8 ? 3 : ix->phase_shift_default));
     a.counters = cnt_d;
+    a.trace = trace;
+    if (trace && (per_query || o.method != MRQ_METHOD_MRQ))
+        throw Fail(MRQ_EINVAL, "a traced search runs the batched MRQ method");
     if (fixed) {
         a.timed = false;      // timing events would be created on demand
         a.fork_seed = false;  // no auxiliary stream or events to create
@@ -955,6 +958,59 @@ mrq_status mrq_search_noalloc(const mrq_index* index, const float* Q, int64_t nq
         hip_check(noalloc_scratch(&buf, &bytes), "fixed search buffer");
         return run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts,
                           (hipStream_t)stream, buf, bytes);
+    });
+}
+
+mrq_status mrq_search_trace(const mrq_index* index, const float* Q, int64_t nq, int32_t k, int32_t nprobe,
+                            const mrq_search_opts* opts, const int32_t* traced, int32_t ntraced, int64_t* ids,
+                            float* dists, mrq_trace_pair* pairs, float* qprime, uint8_t* levels, int64_t max_pairs,
+                            int64_t* npairs, mrq_trace_cand* cands, int64_t max_cands, int64_t* ncands) {
+    return guarded([&]() {
+        if (!index || !Q || !ids || !dists || !npairs || !ncands) throw Fail(MRQ_EINVAL, "NULL argument");
+        if (nq < 1 || ntraced < 0 || (ntraced > 0 && !traced) || max_pairs < 0 || max_cands < 0 ||
+            (max_pairs > 0 && (!pairs || !qprime || !levels)) || (max_cands > 0 && !cands))
+            throw Fail(MRQ_EINVAL, "bad trace buffers");
+        if (is_device_ptr(Q) || is_device_ptr(ids) || is_device_ptr(dists))
+            throw Fail(MRQ_EINVAL, "a traced search takes host Q, ids and dists");
+        std::vector<uint8_t> flag(nq, 0);
+        for (int32_t i = 0; i < ntraced; i++) {
+            if (traced[i] < 0 || traced[i] >= nq) throw Fail(MRQ_EINVAL, "traced query index out of range");
+            flag[traced[i]] = 1;
+        }
+        const int d = index->d;
+        DevTemp dflag(nq), dpairs(sizeof(mrq_trace_pair) * std::max<int64_t>(max_pairs, 1)),
+            dqp(sizeof(float) * d * std::max<int64_t>(max_pairs, 1)), du((size_t)d * std::max<int64_t>(max_pairs, 1)),
+            dc(sizeof(mrq_trace_cand) * std::max<int64_t>(max_cands, 1)), dn(2 * sizeof(unsigned long long)),
+            dsink(sizeof(TraceSink));
+        hipStream_t s = nullptr;
+        hip_check(hipMemcpy(dflag.p, flag.data(), nq, hipMemcpyHostToDevice), "trace flags");
+        hip_check(hipMemset(dn.p, 0, dn.bytes), "trace counts");
+        TraceSink sink;
+        sink.qflag = dflag.as<uint8_t>();
+        sink.pairs = dpairs.as<mrq_trace_pair>();
+        sink.qp = dqp.as<float>();
+        sink.u = du.as<uint8_t>();
+        sink.cands = dc.as<mrq_trace_cand>();
+        sink.n = dn.as<unsigned long long>();
+        sink.max_pairs = max_pairs;
+        sink.max_cands = max_cands;
+        hip_check(hipMemcpy(dsink.p, &sink, sizeof(sink), hipMemcpyHostToDevice), "trace sink");
+        const mrq_status st = run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts, s,
+                                         nullptr, 0, dsink.as<TraceSink>());
+        if (st != MRQ_OK) return st;
+        hip_check(hipDeviceSynchronize(), "trace sync");
+        unsigned long long n[2];
+        hip_check(hipMemcpy(n, dn.p, sizeof(n), hipMemcpyDeviceToHost), "trace counts");
+        *npairs = (int64_t)n[0];
+        *ncands = (int64_t)n[1];
+        const int64_t wp = std::min<int64_t>((int64_t)n[0], max_pairs), wc = std::min<int64_t>((int64_t)n[1], max_cands);
+        if (wp > 0) {
+            hip_check(hipMemcpy(pairs, dpairs.p, sizeof(mrq_trace_pair) * wp, hipMemcpyDeviceToHost), "trace pairs");
+            hip_check(hipMemcpy(qprime, dqp.p, sizeof(float) * d * wp, hipMemcpyDeviceToHost), "trace q'");
+            hip_check(hipMemcpy(levels, du.p, (size_t)d * wp, hipMemcpyDeviceToHost), "trace levels");
+        }
+        if (wc > 0) hip_check(hipMemcpy(cands, dc.p, sizeof(mrq_trace_cand) * wc, hipMemcpyDeviceToHost), "trace cands");
+        return MRQ_OK;
     });
 }
 

@@ -130,6 +130,18 @@ struct Index {
     ~Index();
 };
 
+// Where the tracing instantiation of the search kernels records per-stage values (mrq_search_trace);
+// device memory, null in ordinary searches.
+struct TraceSink {
+    const uint8_t* qflag;          // nq: 1 = the query is traced
+    mrq_trace_pair* pairs;         // max_pairs
+    float* qp;                     // max_pairs x d: q' of the pair
+    uint8_t* u;                    // max_pairs x d: levels of the pair
+    mrq_trace_cand* cands;         // max_cands
+    unsigned long long* n;         // [0] pair records, [1] candidate records (counted beyond the maxima)
+    int64_t max_pairs, max_cands;
+};
+
 // ---- kernels (defined in mrq_search.hip and mrq_build.hip) --------------------------------------------------------
 struct SearchArgs {
     const Index* ix;
@@ -154,6 +166,7 @@ struct SearchArgs {
     int64_t* counters;     // device int64[8] or null
     bool timed = true;     // record per-kernel events when the index timer is on
     bool fork_seed = true; // run the seed pass on the index's auxiliary stream beside the pair preparation
+    const TraceSink* trace = nullptr;  // device; non-null: run the tracing instantiations (query group 16)
 };
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,

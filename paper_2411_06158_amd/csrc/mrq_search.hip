@@ -1102,6 +1102,49 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
     atomicAdd(&cnt[phase_of(r, sh) * nlist + pair_list[pi]], 1);
 }
 
+// ---- tracing (mrq_search_trace): records written by the tracing instantiations only ----
+__device__ __forceinline__ bool trace_on(const TraceSink* tr, int q) { return tr->qflag[q] != 0; }
+
+__device__ __noinline__ void trace_cand(const TraceSink* tr, int kind, int phase, int q, int list, int64_t id, int ip,
+                                        int pc, float v0, float v1, float v2, float v3) {
+    const unsigned long long t = atomicAdd(tr->n + 1, 1ull);
+    if (t >= (unsigned long long)tr->max_cands) return;
+    mrq_trace_cand e;
+    e.kind = kind;
+    e.phase = phase;
+    e.q = q;
+    e.list = list;
+    e.id = id;
+    e.ip = ip;
+    e.pc = pc;
+    e.v0 = v0;
+    e.v1 = v1;
+    e.v2 = v2;
+    e.v3 = v3;
+    tr->cands[t] = e;
+}
+// A record slot for a traced pair (-1 when the buffer is full).
+__device__ __forceinline__ long long trace_pair_slot(const TraceSink* tr) {
+    const unsigned long long t = atomicAdd(tr->n, 1ull);
+    return t < (unsigned long long)tr->max_pairs ? (long long)t : -1ll;
+}
+__device__ __forceinline__ void trace_pair(const TraceSink* tr, long long t, int phase, const PairRec& R) {
+    mrq_trace_pair e;
+    e.phase = phase;
+    e.q = R.q;
+    e.list = R.list;
+    e.su = (int)R.su;
+    e.nq = 0.5f * R.two_nq;
+    e.vl = R.vl;
+    e.delta = R.delta;
+    e.kr = R.Kr;
+    e.ebc = R.ebc;
+    e.er = R.er;
+    e.qn2 = R.qn2;
+    e.pad = 0.f;
+    tr->pairs[t] = e;
+}
+
 // Query code of one (query, list) pair by a group of L lanes (Algorithm 2: normalise, rotate and quantise
 // q_d for list j):
 //   w = P_r^T q_d - P_r^T c_j,  n_q = ||w||,  q' = w / n_q,
@@ -1113,12 +1156,13 @@ __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_
 // gives the same values); lane g of the group holds virtual lanes g, g + L, ....  ||w||^2 is summed per
 // virtual lane, then by the xor butterfly of wave_sum (steps 32, 16, ..., 1), its steps o >= L inside the
 // lane, so every L gives the same bits.
-template <int NH, int L>
+// TR (tracing): qp_out / u_out, when not null, receive q' and u of the d dimensions.
+template <int NH, int L, bool TR = false>
 __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* __restrict__ rq,
                                           const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
                                           const float* __restrict__ Tq, const float* __restrict__ er,
                                           const float* __restrict__ qn2, int KP, PairRec* rec, uint32_t* pl,
-                                          int8_t* qbyte) {
+                                          int8_t* qbyte, float* qp_out = nullptr, uint8_t* u_out = nullptr) {
     static_assert(L == 16 || L == 32 || L == 64, "lanes per pair");
     constexpr int V = 64 / L;
     const int g = lane & (L - 1);
@@ -1194,6 +1238,21 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
     }
 #pragma unroll
     for (int o = L / 2; o >= 1; o >>= 1) su += __shfl_xor(su, o);
+    if constexpr (TR) {
+        if (qp_out) {
+#pragma unroll
+            for (int t = 0; t < V; t++) {
+#pragma unroll
+                for (int h = 0; h < NH; h++) {
+                    const int i = g + L * t + 64 * h;
+                    if (i < d) {
+                        qp_out[i] = wv[t][h];
+                        u_out[i] = (uint8_t)uv[t][h];
+                    }
+                }
+            }
+        }
+    }
     if (qbyte) {  // levels as signed bytes for the i8 matrix-core scan (u - 128 when bq = 8), zero beyond d
         const int ob = bq == 8 ? 128 : 0;
 #pragma unroll
@@ -1240,14 +1299,14 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
 // One group of L lanes per (query, list) pair (256 / L pairs per block): its slot in the (phase, list)
 // bucket and its query code (the level bytes the scan multiplies; the seed pass builds the bit planes of
 // its own pairs).
-template <int NH, int L>
+template <int NH, int L, bool TR>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
     const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh, const float* __restrict__ rq,
     const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
     const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
     const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
-    PairRec* __restrict__ recs, int8_t* __restrict__ qu8, int32_t* __restrict__ pair_pos) {
+    PairRec* __restrict__ recs, int8_t* __restrict__ qu8, int32_t* __restrict__ pair_pos, const TraceSink* tr) {
     const int64_t pi = blockIdx.x * (int64_t)(256 / L) + threadIdx.x / L;
     if (pi >= npairs) return;  // whole groups: the group's shuffles stay among active lanes
     const int lane = threadIdx.x & 63;
@@ -1260,8 +1319,18 @@ __global__ __launch_bounds__(256) void k_pair_prep(
     if (lane == first) pos = boff[p * nlist + j] + atomicAdd(&fill[p * nlist + j], 1);
     pos = __shfl(pos, first);
     if (lane == first) pair_pos[pi] = pos;
-    pair_code<NH, L>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
-                     qu8 + (int64_t)pos * KP);
+    if constexpr (TR) {
+        long long ts = -1;
+        if (lane == first && trace_on(tr, q)) ts = trace_pair_slot(tr);
+        ts = __shfl(ts, first);
+        pair_code<NH, L, true>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
+                               qu8 + (int64_t)pos * KP, ts >= 0 ? tr->qp + ts * d : nullptr,
+                               ts >= 0 ? tr->u + ts * d : nullptr);
+        if (lane == first && ts >= 0) trace_pair(tr, ts, p, recs[pos]);  // the record this lane just wrote
+    } else {
+        pair_code<NH, L>(lane, q, j, rq, RC, d, d4, WP, bq, eps0, Tq, er, qn2, KP, recs + pos, nullptr,
+                         qu8 + (int64_t)pos * KP);
+    }
 }
 
 __global__ void k_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_nb, int nlist,
@@ -1303,19 +1372,22 @@ __global__ __launch_bounds__(256) void k_item_desc(const int32_t* __restrict__ i
 // inner product of the candidate's sign code b with the query levels u:
 //   ip = sum_i b_i u_i,   I = Delta (2 ip - S_u) + v_l (2 popcount(b) - d) = sqrt(d) <xbar_b, qbar_b>,
 //   dis' = (A_x + K) - 2 n_q F_x I,   LB = dis' - ebc E_x - eps_r  (evaluated as (A_x + Kr) - ...).
-__device__ __forceinline__ float stage1_from_ip(int ip, int pc, float A, float F, float E, const PairRec& R,
-                                                int d) {
+// stage1_inner = dis' - eps_r; the bound subtracts eps_b = ebc E_x from it with one fused step.
+__device__ __forceinline__ float stage1_inner(int ip, int pc, float A, float F, const PairRec& R, int d) {
     const float J1 = (float)(2 * ip - (int)R.su);
     const float J2 = (float)(2 * pc - d);
     const float I = fmaf(R.delta, J1, R.vl * J2);
-    return fmaf(-R.ebc, E, fmaf(-(R.two_nq * F), I, A + R.Kr));
+    return fmaf(-(R.two_nq * F), I, A + R.Kr);
+}
+__device__ __forceinline__ float stage1_from_ip(int ip, int pc, float A, float F, float E, const PairRec& R,
+                                                int d) {
+    return fmaf(-R.ebc, E, stage1_inner(ip, pc, A, F, R, d));
 }
 
 // The same with ip from the bit planes U_b of the query levels: ip = sum_b 2^b popcount(b & U_b)
 // (the seed pass, one candidate per lane).
 template <int WP, int BQT>
-__device__ __forceinline__ float stage1_lb(const uint32_t (&c)[WP], int pc, float A, float F, float E,
-                                           const PairRec& R, const uint32_t* __restrict__ U, int bq, int d) {
+__device__ __forceinline__ int plane_ip(const uint32_t (&c)[WP], const uint32_t* __restrict__ U, int bq) {
     const int nb = BQT > 0 ? BQT : bq;
     int ip = 0;
 #pragma unroll
@@ -1326,24 +1398,26 @@ __device__ __forceinline__ float stage1_lb(const uint32_t (&c)[WP], int pc, floa
         for (int w = 0; w < WP; w++) acc += __builtin_popcount(c[w] & U[b * WP + w]);
         ip += acc << b;
     }
-    return stage1_from_ip(ip, pc, A, F, E, R, d);
+    return ip;
 }
 
 // B-bit refinement of a stage-1 survivor (extended code whose top plane is the sign plane), from
 // ipB = sum_i ux_i u_i with ux the candidate's level indices:
 //   I_B = Delta (2 ipB - (2^B - 1) S_u) + v_l SX_x = 2 <y, qbar'>,
 //   dis_B = (A_x + K) - 2 n_q FB_x I_B,   LB_B = dis_B - ebc EB_x - eps_r.
-__device__ __forceinline__ float ext_from_ip(long long ip, int B, float A, float FB, float EB, float SX,
-                                             const PairRec& R) {
+__device__ __forceinline__ float ext_inner(long long ip, int B, float A, float FB, float SX, const PairRec& R) {
     const float J1 = (float)(2 * ip - (long long)((1 << B) - 1) * (long long)R.su);
     const float I = fmaf(R.delta, J1, R.vl * SX);
-    return fmaf(-R.ebc, EB, fmaf(-(R.two_nq * FB), I, A + R.Kr));
+    return fmaf(-(R.two_nq * FB), I, A + R.Kr);
+}
+__device__ __forceinline__ float ext_from_ip(long long ip, int B, float A, float FB, float EB, float SX,
+                                             const PairRec& R) {
+    return fmaf(-R.ebc, EB, ext_inner(ip, B, A, FB, SX, R));
 }
 
-// The same with ipB = sum_{a, b} 2^(a + b) popcount(X_a & U_b) (the seed pass).
-__device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const uint32_t* __restrict__ extp,
-                                        int B, int WP, float A, float FB, float EB, float SX, const PairRec& R,
-                                        const uint32_t* __restrict__ U, int bq) {
+// ipB = sum_{a, b} 2^(a + b) popcount(X_a & U_b) from the planes (the seed pass).
+__device__ __forceinline__ long long ext_plane_ip(const uint32_t* __restrict__ sign, const uint32_t* __restrict__ extp,
+                                                  int B, int WP, const uint32_t* __restrict__ U, int bq) {
     long long ip = 0;
     for (int a = 0; a < B; a++) {
         const uint32_t* X = a == B - 1 ? sign : extp + a * WP;
@@ -1353,7 +1427,7 @@ __device__ __forceinline__ float ext_lb(const uint32_t* __restrict__ sign, const
             ip += (long long)acc << (a + b);
         }
     }
-    return ext_from_ip(ip, B, A, FB, EB, SX, R);
+    return ip;
 }
 
 struct ScanCtx {
@@ -1390,6 +1464,7 @@ struct ScanCtx {
     const float* rq;
     const float* RC;
     const float* Tq;
+    const TraceSink* tr;  // tracing instantiations only
     float eps0;
     int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, cq;
 };
@@ -1544,7 +1619,7 @@ __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slo
 // KIT = 0: any d.  QL (d4 = 64 KIT, KIT <= 2): operands reach LDS by direct global-to-LDS loads ahead of
 // their use (the next item's stage-1 operands during the current item, the current item's q_d rows at its
 // start) and the x_d slices of a row tile are loaded while the previous tile is multiplied.
-template <int GT, int KIT, bool QL>
+template <int GT, int KIT, bool QL, bool TR>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
@@ -1737,6 +1812,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             const PairRec& R = rec[g < ng ? g : 0];
                             const bool ps = g < ng &&
                                             stage1_from_ip(acc[v] + ob * pc, pc, fa[rt], ff[rt], fe[rt], R, c.d) < R.tau;
+                            if constexpr (TR) {
+                                if (g < ng && trace_on(c.tr, R.q)) {
+                                    const int ip = acc[v] + ob * pc;
+                                    const float in1 = stage1_inner(ip, pc, fa[rt], ff[rt], R, c.d);
+                                    trace_cand(c.tr, MRQ_TRACE_STAGE1, p, R.q, R.list, c.ids[row0 + 16 * rt + li], ip, pc,
+                                               in1, R.ebc * fe[rt], fmaf(-R.ebc, fe[rt], in1), R.tau);
+                                }
+                            }
                             const unsigned long long mv = __ballot(ps);
                             if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
                             cnt += __popcll(mv);
@@ -1767,6 +1850,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                         const int g = ct * 16 + 4 * kg + v;
                         const PairRec& R = rec[g < ng ? g : 0];
                         const bool ps = g < ng && stage1_from_ip(acc[v] + ob * pc, pc, A, F, E, R, c.d) < R.tau;
+                        if constexpr (TR) {
+                            if (g < ng && trace_on(c.tr, R.q)) {
+                                const int ip = acc[v] + ob * pc;
+                                const float in1 = stage1_inner(ip, pc, A, F, R, c.d);
+                                trace_cand(c.tr, MRQ_TRACE_STAGE1, p, R.q, R.list, c.ids[row], ip, pc, in1, R.ebc * E,
+                                           fmaf(-R.ebc, E, in1), R.tau);
+                            }
+                        }
                         const unsigned long long mv = __ballot(ps);
                         if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
                         cnt += __popcll(mv);
@@ -1811,6 +1902,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             const long long ipB = (long long)acc2[v] + ob * sumux + oa * (long long)R.su -
                                                   (long long)oa * ob * c.d;
                             ps = ext_from_ip(ipB, c.B, A, FB, EB, SX, R) < R.tau;
+                            if constexpr (TR) {
+                                if (trace_on(c.tr, R.q)) {
+                                    const float inB = ext_inner(ipB, c.B, A, FB, SX, R);
+                                    trace_cand(c.tr, MRQ_TRACE_EXT, p, R.q, R.list, c.ids[row], (int)ipB, 0, inB,
+                                               R.ebc * EB, fmaf(-R.ebc, EB, inB), R.tau);
+                                }
+                            }
                         }
                         const unsigned long long nm = __ballot(ps);
                         if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
@@ -1868,6 +1966,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             if (ps) {
                                 const PairRec& R = rec[ct * 16 + 4 * kg + v];
                                 ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                                if constexpr (TR) {
+                                    if (trace_on(c.tr, R.q)) {
+                                        const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                        trace_cand(c.tr, MRQ_TRACE_STAGE2, p, R.q, R.list, c.ids[row0 + 16 * rt + li], 0, 0,
+                                                   dso, R.er, dso - R.er, R.tau);
+                                    }
+                                }
                             }
                             const unsigned long long nm = __ballot(ps);
                             if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
@@ -1896,6 +2001,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             if (ps) {
                                 const PairRec& R = rec[ct * 16 + 4 * kg + v];
                                 ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                                if constexpr (TR) {
+                                    if (trace_on(c.tr, R.q)) {
+                                        const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                        trace_cand(c.tr, MRQ_TRACE_STAGE2, p, R.q, R.list, c.ids[row], 0, 0, dso, R.er,
+                                                   dso - R.er, R.tau);
+                                    }
+                                }
                             }
                             const unsigned long long nm = __ballot(ps);
                             if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = nm;
@@ -1965,7 +2077,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 // (QL, D4 <= kExactLdsFloats), then k_max keys.  The bin's count is cleared for the next phase.
 constexpr int kExactLdsFloats = 8192;
 
-template <bool QL>
+template <bool QL, bool TR>
 __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     extern __shared__ float4 dyn_x[];
     __shared__ int n_s;
@@ -1994,6 +2106,10 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
         if (valid && (lane & 15) == 0) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
             topk_insert(queue, k, key);
+            if constexpr (TR) {
+                if (trace_on(c.tr, q))
+                    trace_cand(c.tr, MRQ_TRACE_EXACT, c.phase, q, -1, c.ids[row], 0, 0, dist, 0.f, 0.f, 0.f);
+            }
         }
     }
     __syncthreads();
@@ -2027,15 +2143,21 @@ struct QueryState {
 // One batch of at most 64 candidates (one per lane; `pass` = passed stage 1 against st.tau): B-bit
 // refinement, Eq 7 re-check, exact distances four at a time, then a merge of the new keys into the
 // sorted queue and the new tau.
-template <int WP>
+template <int WP, bool TR>
 __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
                            QueryState& st, unsigned long long* nk, const float4* qs, bool qlds, int lane,
                            long long* n1, long long* next, long long* n2) {
     *n1 += __popcll(__ballot(pass));
     const bool open = st.tau == INFINITY;  // every test passes until the queue holds k results
     if (pass && !open && c.B > 1 && c.use_ext) {
-        const float lb = ext_lb(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, c.fA[row], c.fFB[row],
-                                c.fEB[row], c.fSX[row], R, U, c.bq);
+        const long long ipB = ext_plane_ip(c.code + row * WP, c.ext + row * (c.B - 1) * WP, c.B, WP, U, c.bq);
+        const float inB = ext_inner(ipB, c.B, c.fA[row], c.fFB[row], c.fSX[row], R);
+        const float lb = fmaf(-R.ebc, c.fEB[row], inB);
+        if constexpr (TR) {
+            if (trace_on(c.tr, q))
+                trace_cand(c.tr, MRQ_TRACE_EXT, 0, q, R.list, c.ids[row], (int)ipB, 0, inB, R.ebc * c.fEB[row], lb,
+                           st.tau);
+        }
         pass = lb < st.tau;
     }
     *next += __popcll(__ballot(pass));
@@ -2043,6 +2165,12 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
         const float dot = qlds ? dot_lane_lds(c.xd + row * c.d4, qs + (c.D4 >> 2), c.d4)
                                : dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
         pass = fmaf(-2.f, dot, c.ax[row] + R.qn2) - er < st.tau;
+        if constexpr (TR) {
+            if (trace_on(c.tr, q)) {
+                const float dso = fmaf(-2.f, dot, c.ax[row] + R.qn2);
+                trace_cand(c.tr, MRQ_TRACE_STAGE2, 0, q, R.list, c.ids[row], 0, 0, dso, er, dso - er, st.tau);
+            }
+        }
     }
     const unsigned long long m2 = __ballot(pass);
     *n2 += __popcll(m2);
@@ -2057,6 +2185,10 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
         const float dist = qlds ? exact_dist_group_lds(c.X + rs * c.D4, qs, c.D4, lane & 15)
                                 : exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+        if constexpr (TR) {
+            if (src >= 0 && (lane & 15) == 0 && trace_on(c.tr, q))
+                trace_cand(c.tr, MRQ_TRACE_EXACT, 0, q, R.list, c.ids[rs], 0, 0, dist, 0.f, 0.f, st.tau);
+        }
         for (int g = 0; g < 4; g++) {
             const int sg = __shfl(src, g * 16);
             const unsigned long long kgv = __shfl(key, g * 16);
@@ -2087,16 +2219,24 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     if (st.have == st.k) st.tau = __uint_as_float((uint32_t)(st.now()[st.k - 1] >> 32));
 }
 
-template <int WP, int BQT>
+template <int WP, int BQT, bool TR>
 __device__ __forceinline__ float seed_lb(const ScanCtx& c, int64_t row, const PairRec& R, const uint32_t* U) {
     uint32_t cw[WP];
     int pc = 0;
 #pragma unroll
     for (int w = 0; w < WP; w++) { cw[w] = c.code[row * WP + w]; pc += __builtin_popcount(cw[w]); }
-    return stage1_lb<WP, BQT>(cw, pc, c.fA[row], c.fF[row], c.fE[row], R, U, c.bq, c.d);
+    const int ip = plane_ip<WP, BQT>(cw, U, c.bq);
+    const float E = c.fE[row];
+    const float in1 = stage1_inner(ip, pc, c.fA[row], c.fF[row], R, c.d);
+    const float lb = fmaf(-R.ebc, E, in1);
+    if constexpr (TR) {
+        if (trace_on(c.tr, R.q))
+            trace_cand(c.tr, MRQ_TRACE_STAGE1, 0, R.q, R.list, c.ids[row], ip, pc, in1, R.ebc * E, lb, NAN);
+    }
+    return lb;
 }
 
-template <int WP, int BQT>
+template <int WP, int BQT, bool TR>
 __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
     __shared__ int32_t pend_row[128];
@@ -2125,9 +2265,18 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ PairRec sh_R;
     __shared__ uint32_t sh_U[8 * WP];
     const int j = c.pair_list[c.pair_off[q]];
-    pair_code<(WP <= 2 ? 1 : WP / 2), 64>(lane, q, j, c.rq, c.RC, c.d, c.d4, WP, c.bq, c.eps0, c.Tq, c.er, c.qn2, 0, &sh_R,
-                                     sh_U, nullptr);
+    long long ts = -1;  // trace record of the pair (tracing instantiation)
+    if constexpr (TR) {
+        if (lane == 0 && trace_on(c.tr, q)) ts = trace_pair_slot(c.tr);
+        ts = __shfl(ts, 0);
+    }
+    pair_code<(WP <= 2 ? 1 : WP / 2), 64, TR>(lane, q, j, c.rq, c.RC, c.d, c.d4, WP, c.bq, c.eps0, c.Tq, c.er, c.qn2, 0,
+                                              &sh_R, sh_U, nullptr, TR && ts >= 0 ? c.tr->qp + ts * c.d : nullptr,
+                                              TR && ts >= 0 ? c.tr->u + ts * c.d : nullptr);
     __syncthreads();
+    if constexpr (TR) {
+        if (lane == 0 && ts >= 0) trace_pair(c.tr, ts, 0, sh_R);
+    }
     const PairRec R = sh_R;
     const uint32_t* U = sh_U;
     const int n = c.list_len[j];
@@ -2136,7 +2285,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     long long n1 = 0, next = 0, n2 = 0;
     // round 1: keys (ord(lb), row) of the first nsel rows, and the s-th smallest of them
     for (int i = lane; i < nsel; i += 64) {
-        const float lb = seed_lb<WP, BQT>(c, base + i, R, U);
+        const float lb = seed_lb<WP, BQT, TR>(c, base + i, R, U);
         keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)i;
     }
     __syncthreads();
@@ -2166,7 +2315,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         const bool in = lane < cnt;
         const int i = in ? pend_row[lane] : 0;
         const float lb = in ? pend_lb[lane] : INFINITY;
-        seed_batch<WP>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, qs, qlds, lane, &n1, &next, &n2);
+        seed_batch<WP, TR>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, qs, qlds, lane, &n1, &next, &n2);
         const int rest = np - cnt;  // move the remaining entries to the front
         int r_row = 0;
         float r_lb = 0.f;
@@ -2205,7 +2354,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
                 lb = ord_to_float((uint32_t)(key >> 32));
                 take = key > T && lb < st.tau;
             } else {
-                lb = seed_lb<WP, BQT>(c, base + i, R, U);
+                lb = seed_lb<WP, BQT, TR>(c, base + i, R, U);
                 take = lb < st.tau;
             }
         }
@@ -2671,9 +2820,9 @@ struct Timed {
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs, int bq,
                               int np_max, int method, int rerank);
 
-template <int WP, int BQT>
+template <int WP, int BQT, bool TR>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
-    hipLaunchKernelGGL((k_seed<WP, BQT>), dim3((unsigned)nq), dim3(64),
+    hipLaunchKernelGGL((k_seed<WP, BQT, TR>), dim3((unsigned)nq), dim3(64),
                        sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
                            (c.D4 <= kSeedLdsFloats ? sizeof(float) * (c.D4 + c.d4) : 0),
                        s, c);
@@ -2682,7 +2831,7 @@ static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
 // Blocks of a persistent kernel that are resident at once on the current device (cached per device).
 template <class K>
 static int resident_blocks(K kernel, int threads, int slot, size_t lds) {
-    static int cache[16][32];
+    static int cache[16][48];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
     int& v = cache[dev][slot];
@@ -2703,73 +2852,81 @@ static bool scan_ql(const ScanCtx& c) {
 }
 static size_t scan_lds(const ScanCtx& c, int GT) { return (size_t)4 * GT * c.d4 * sizeof(float); }
 
-template <int GT, int KIT>
+// TR: the tracing instantiations (c.tr set; query group 16 only).
+template <int GT, int KIT, bool TR>
 static void launch_scan_k(const ScanCtx& c, hipStream_t s, int blocks) {
     if constexpr (KIT == 1 || KIT == 2) {
         if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536) {
-            hipLaunchKernelGGL((k_scan<GT, KIT, true>), dim3(blocks), dim3(256), scan_lds(c, GT), s, c);
+            hipLaunchKernelGGL((k_scan<GT, KIT, true, TR>), dim3(blocks), dim3(256), scan_lds(c, GT), s, c);
             return;
         }
     }
-    hipLaunchKernelGGL((k_scan<GT, KIT, false>), dim3(blocks), dim3(256), 0, s, c);
+    hipLaunchKernelGGL((k_scan<GT, KIT, false, TR>), dim3(blocks), dim3(256), 0, s, c);
 }
 
-template <int GT>
+template <int GT, bool TR>
 static void launch_scan_g(const ScanCtx& c, hipStream_t s, int blocks) {
     switch (c.KI) {
-        case 1: launch_scan_k<GT, 1>(c, s, blocks); break;
-        case 2: launch_scan_k<GT, 2>(c, s, blocks); break;
-        case 3: case 4: launch_scan_k<GT, 4>(c, s, blocks); break;
-        default: launch_scan_k<GT, 0>(c, s, blocks); break;
+        case 1: launch_scan_k<GT, 1, TR>(c, s, blocks); break;
+        case 2: launch_scan_k<GT, 2, TR>(c, s, blocks); break;
+        case 3: case 4: launch_scan_k<GT, 4, TR>(c, s, blocks); break;
+        default: launch_scan_k<GT, 0, TR>(c, s, blocks); break;
     }
 }
 
 static void launch_scan(const ScanCtx& c, hipStream_t s, int blocks) {
-    if (c.G <= 16) launch_scan_g<16>(c, s, blocks);
-    else if (c.G <= 32) launch_scan_g<32>(c, s, blocks);
-    else launch_scan_g<64>(c, s, blocks);
+    if (c.tr) launch_scan_g<16, true>(c, s, blocks);
+    else if (c.G <= 16) launch_scan_g<16, false>(c, s, blocks);
+    else if (c.G <= 32) launch_scan_g<32, false>(c, s, blocks);
+    else launch_scan_g<64, false>(c, s, blocks);
 }
 
 // Blocks of the persistent scan grid: what is resident at once on the device, at most kMaxScanBlocks.
-template <int GT, int KIT>
+template <int GT, int KIT, bool TR>
 static int scan_grid_k(const ScanCtx& c, int slot) {
     if constexpr (KIT == 1 || KIT == 2) {
         if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536)
-            return std::min(resident_blocks(k_scan<GT, KIT, true>, 256, slot, scan_lds(c, GT)), kMaxScanBlocks);
+            return std::min(resident_blocks(k_scan<GT, KIT, true, TR>, 256, slot, scan_lds(c, GT)), kMaxScanBlocks);
     }
-    return std::min(resident_blocks(k_scan<GT, KIT, false>, 256, slot + 1, 0), kMaxScanBlocks);
+    return std::min(resident_blocks(k_scan<GT, KIT, false, TR>, 256, slot + 1, 0), kMaxScanBlocks);
 }
-template <int GT>
+template <int GT, bool TR>
 static int scan_grid_g(const ScanCtx& c, int slot) {
     switch (c.KI) {
-        case 1: return scan_grid_k<GT, 1>(c, slot + 0);
-        case 2: return scan_grid_k<GT, 2>(c, slot + 2);
-        case 3: case 4: return scan_grid_k<GT, 4>(c, slot + 4);
-        default: return scan_grid_k<GT, 0>(c, slot + 6);
+        case 1: return scan_grid_k<GT, 1, TR>(c, slot + 0);
+        case 2: return scan_grid_k<GT, 2, TR>(c, slot + 2);
+        case 3: case 4: return scan_grid_k<GT, 4, TR>(c, slot + 4);
+        default: return scan_grid_k<GT, 0, TR>(c, slot + 6);
     }
 }
 static int scan_grid(const ScanCtx& c) {
-    if (c.G <= 16) return scan_grid_g<16>(c, 0);
-    if (c.G <= 32) return scan_grid_g<32>(c, 8);
-    return scan_grid_g<64>(c, 16);
+    if (c.tr) return scan_grid_g<16, true>(c, 32);
+    if (c.G <= 16) return scan_grid_g<16, false>(c, 0);
+    if (c.G <= 32) return scan_grid_g<32, false>(c, 8);
+    return scan_grid_g<64, false>(c, 16);
 }
 
-template <int WP>
+template <int WP, bool TR>
 static void launch_seed_w(const ScanCtx& c, int64_t nq, hipStream_t s) {
-    if (c.bq == 4) launch_seed_t<WP, 4>(c, nq, s);
-    else launch_seed_t<WP, 0>(c, nq, s);
+    if (c.bq == 4) launch_seed_t<WP, 4, TR>(c, nq, s);
+    else launch_seed_t<WP, 0, TR>(c, nq, s);
 }
 
-static void launch_seed(const ScanCtx& c, int64_t nq, hipStream_t s) {
+template <bool TR>
+static void launch_seed_tr(const ScanCtx& c, int64_t nq, hipStream_t s) {
     switch (c.WP) {
-        case 1: launch_seed_w<1>(c, nq, s); break;
-        case 2: launch_seed_w<2>(c, nq, s); break;
-        case 4: launch_seed_w<4>(c, nq, s); break;
-        case 8: launch_seed_w<8>(c, nq, s); break;
-        case 16: launch_seed_w<16>(c, nq, s); break;
-        case 32: launch_seed_w<32>(c, nq, s); break;
-        default: launch_seed_w<48>(c, nq, s); break;
+        case 1: launch_seed_w<1, TR>(c, nq, s); break;
+        case 2: launch_seed_w<2, TR>(c, nq, s); break;
+        case 4: launch_seed_w<4, TR>(c, nq, s); break;
+        case 8: launch_seed_w<8, TR>(c, nq, s); break;
+        case 16: launch_seed_w<16, TR>(c, nq, s); break;
+        case 32: launch_seed_w<32, TR>(c, nq, s); break;
+        default: launch_seed_w<48, TR>(c, nq, s); break;
     }
+}
+static void launch_seed(const ScanCtx& c, int64_t nq, hipStream_t s) {
+    if (c.tr) launch_seed_tr<true>(c, nq, s);
+    else launch_seed_tr<false>(c, nq, s);
 }
 
 int padded_words(int d) {
@@ -2987,7 +3144,8 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     int nph = 1;
     while (nph < kPhases && phase_lo(nph, a.phase_shift) < a.np_max) nph++;
     const int64_t P = (int64_t)nph * nlist;
-    const int G = a.group <= 16 ? 16 : (a.group <= 32 ? 32 : 64);  // queries per scan work item
+    // queries per scan work item (the tracing instantiations exist for 16 only)
+    const int G = a.trace || a.group <= 16 ? 16 : (a.group <= 32 ? 32 : 64);
 
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
         Timed t(tm, s, "project");
@@ -3012,7 +3170,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.xd = ix.xd; c.ax = ix.ax; c.X = ix.X; c.ids = ix.ids; c.qd = w.qd; c.qpad = w.qpad; c.qn2 = w.qn2; c.er = w.er;
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
     c.slots = w.slots; c.surv = w.surv; c.qcnt = w.qcnt; c.counters = a.counters;
-    c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0;
+    c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0; c.tr = a.trace;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = level_bytes(d);
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
@@ -3053,11 +3211,16 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         const int KP = level_bytes(d);
         // 16 lanes per pair up to d = 256 (4 pairs per wave: the kernel is bound by the latency of its loads
         // and atomic), a whole wave beyond
-#define PREP(NHV, LV)                                                                                      \
-    hipLaunchKernelGGL((k_pair_prep<NHV, LV>), dim3((unsigned)((a.total_pairs + 256 / LV - 1) / (256 / LV))), \
+#define PREP_T(NHV, LV, TRV)                                                                                \
+    hipLaunchKernelGGL((k_pair_prep<NHV, LV, TRV>), dim3((unsigned)((a.total_pairs + 256 / LV - 1) / (256 / LV))), \
                        dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift,  \
                        w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP, w.recs,  \
-                       w.qu8, w.pair_pos)
+                       w.qu8, w.pair_pos, a.trace)
+#define PREP(NHV, LV)                     \
+    do {                                  \
+        if (a.trace) PREP_T(NHV, LV, true);  \
+        else PREP_T(NHV, LV, false);      \
+    } while (0)
         if (nh <= 1) PREP(1, 16);
         else if (nh <= 2) PREP(2, 16);
         else if (nh <= 4) PREP(4, 16);
@@ -3065,6 +3228,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         else if (nh <= 16) PREP(16, 64);
         else PREP(24, 64);
 #undef PREP
+#undef PREP_T
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
                            nlist, G, (int)P, w.items);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.items, w.ioff, P);
@@ -3089,10 +3253,14 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         {
             Timed t(tm, s, "exact");
             const size_t qk = (size_t)a.k_max * sizeof(unsigned long long);
-            if (D4 <= kExactLdsFloats)
-                hipLaunchKernelGGL(k_exact<true>, dim3((unsigned)nq), dim3(256), (size_t)D4 * sizeof(float) + qk, s, c);
-            else
-                hipLaunchKernelGGL(k_exact<false>, dim3((unsigned)nq), dim3(256), qk, s, c);
+            const size_t ql = (size_t)D4 * sizeof(float) + qk;
+            if (D4 <= kExactLdsFloats) {
+                if (a.trace) hipLaunchKernelGGL((k_exact<true, true>), dim3((unsigned)nq), dim3(256), ql, s, c);
+                else hipLaunchKernelGGL((k_exact<true, false>), dim3((unsigned)nq), dim3(256), ql, s, c);
+            } else {
+                if (a.trace) hipLaunchKernelGGL((k_exact<false, true>), dim3((unsigned)nq), dim3(256), qk, s, c);
+                else hipLaunchKernelGGL((k_exact<false, false>), dim3((unsigned)nq), dim3(256), qk, s, c);
+            }
             HIP_TRY(hipGetLastError());
         }
     }
