@@ -2,10 +2,11 @@
 """Benchmark of the batched MRQ search on one MI355X.
 
 Metric: queries per second of the batched search at the smallest nprobe whose recall@10 against
-exact brute-force ground truth is >= 0.95, on the GIST-shaped synthetic workload (N = 1,000,000,
-D = 960, 10,000 queries, nlist = 4,096, d_r = 128, 1-bit codes, k = 10).  A step is one batched
-search of all queries (projection, probe, query codes, seed pass, phased scans, top-k) with the
-index and the queries resident in HBM.  Prints one JSON line.
+exact brute-force ground truth is >= 0.95.  Headline: the DEEP-shaped synthetic workload, the largest
+that fits one GPU (N = 10,000,000, D = 128, 10,000 queries, nlist = 16,384, d_r = 64, 1-bit codes,
+k = 10); the GIST-shaped one (N = 1,000,000, D = 960, nlist = 4,096, d_r = 128) follows as a nested block.
+A step is one batched search of all queries (projection, probe, query codes, seed pass, phased scans,
+top-k) with the index and the queries resident in HBM.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_I8_PEAK = 5.0e15      # dense int8 matrix-core ops/s
+MFMA_F32_PEAK = 157.3e12   # FP32 matrix-core FLOP/s
+VALU_F32_PEAK = 157.3e12   # FP32 vector FLOP/s
 SEARCH_SOURCES = ["paper_2411_06158_amd/csrc/mrq_search.hip", "paper_2411_06158_amd/csrc/mrq_internal.h"]
 
 
@@ -76,22 +80,385 @@ def recall(ids, gt, k):
     return hit / (gt.shape[0] * k)
 
 
+# Index and search configuration per workload (the stand-ins of the paper's data sets): nlist, d_r, bits.
+WORKLOADS = {
+    "small": dict(nlist=64, d=32, bits=1),         # the plain-method case: 20k x 128
+    "gist1m": dict(nlist=4096, d=128, bits=1),     # GIST-shaped: 1M x 960
+    "deep10m": dict(nlist=16384, d=64, bits=1),    # DEEP-shaped: 10M x 128 (the largest single-GPU case)
+    "openai2m": dict(nlist=4096, d=256, bits=4),   # embedding-shaped: 2M x 1536
+}
+
+
+def cpu_description():
+    """Host CPU model and clock (lscpu), for the oracle baseline."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "CPU max MHz", "CPU MHz", "CPU(s)"):
+                info[k] = v
+    except Exception:
+        pass
+    return info
+
+
+def copy_bandwidth(torch, mrq, dev, gib=4, reps=10):
+    """Achievable HBM bandwidth: the library's streaming copy over `gib` GiB (2 x bytes moved per copy)."""
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        mrq.stream_copy(dst, src, s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        mrq.stream_copy(dst, src, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(dst[:1024], src[:1024]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9, ok
+
+
+def measure(args, name, np, torch, mrq, synth, dev, headline, copy_gbs):
+    """Build the index of workload `name`, find the smallest nprobe reaching the target recall, time K plain
+    batched searches (the throughput) and K instrumented ones (per-kernel times, stage and work counters:
+    the roofline).  The headline workload also times the per-query path, the CPU oracle and the per-result
+    error report."""
+    cfg = dict(WORKLOADS.get(name, WORKLOADS["gist1m"]))
+    if headline:
+        for key in ("nlist", "d", "bits"):
+            if getattr(args, key):
+                cfg[key] = getattr(args, key)
+    t0 = time.time()
+    X, Q, spec = synth.workload(name, N=args.N if headline else None, nq=args.nq if headline else None)
+    N, D = X.shape
+    nq = Q.shape[0]
+    log(f"{name}: data {N}x{D}, {nq} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    ix = mrq.Index.build(Xd, d_r=cfg["d"], bits=cfg["bits"], nlist=cfg["nlist"])
+    build_s = time.time() - t1
+    log(f"{name}: build {build_s:.1f}s, index {ix.device_bytes / 2**30:.2f} GiB")
+
+    k = args.k
+    ids_buf = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
+
+    def run(nprobe, counters=None, mode=mrq.MRQ_BATCHED, Qs=None, ib=None, db=None):
+        o = mrq.search_opts(mode=mode, counters=counters, group=args.group, phase_growth=args.phase_growth)
+        Qs = Qd if Qs is None else Qs
+        return ix.search(Qs, k, nprobe, ids=ids_buf if ib is None else ib, dists=d_buf if db is None else db,
+                         opts=o)
+
+    chosen, rec_at = (args.nprobe if headline else 0), None
+    sweep = []
+    gt = None
+    if not args.profile_only:
+        t2 = time.time()
+        gt = ground_truth(torch, Xd, Qd, k)
+        log(f"{name}: ground truth {time.time() - t2:.1f}s")
+        # the smallest nprobe reaching the target: a coarse grid, the autotuner at its first value reaching
+        # the target, then (with the tuned schedule) every value between the last one below the target and
+        # that one
+        cands = [chosen] if chosen else [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+
+        def try_np(npb):
+            run(npb)
+            torch.cuda.synchronize()
+            r = recall(ids_buf.cpu().numpy(), gt, k)
+            sweep.append((npb, r))
+            log(f"{name}: nprobe {npb}: recall@{k} {r:.4f}")
+            return r
+
+        prev = 0
+        fixed = bool(chosen)
+        for npb in cands:
+            if npb > cfg["nlist"]:
+                break
+            chosen, rec_at = npb, try_np(npb)
+            if rec_at >= args.target_recall:
+                break
+            prev = npb
+    else:
+        fixed = bool(chosen)
+    if not chosen:
+        chosen = 64
+
+    if args.calib_copy and headline:  # a copy kernel of known size: 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # the autotuner picks the scan schedule (query-group size, phase growth) on this batch; the group size
+    # never changes a result, the phase growth only where an error bound fails
+    if args.group and args.phase_growth:
+        group, growth = args.group, args.phase_growth
+        log(f"{name}: query group {group}, phase growth {growth}")
+    else:
+        group, growth = ix.tune(Qd, k, chosen)
+        log(f"{name}: autotuned query group {group}, phase growth {growth}")
+    if not args.profile_only and not fixed and rec_at is not None and rec_at >= args.target_recall:
+        for fine in list(range(prev + 1, chosen)) + [chosen]:
+            rf = try_np(fine)
+            if rf >= args.target_recall or fine == chosen:
+                chosen, rec_at = fine, rf
+                break
+
+    # timed region: W warm-up steps, then K plain searches (the throughput); then K more searches, not
+    # timed, with per-kernel HIP events and device counters (the kernel breakdown and the roofline)
+    for _ in range(args.warmup):
+        run(chosen)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        run(chosen)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    cnt = torch.zeros(16, dtype=torch.int64, device=dev)
+    ix.timing_enable(True, reset=True)
+    ti = time.perf_counter()
+    for _ in range(args.steps):
+        run(chosen, counters=cnt)
+    torch.cuda.synchronize()
+    ms_instr = 1e3 * (time.perf_counter() - ti) / args.steps
+    ix.timing_enable(False, reset=False)
+    kt = ix.timing()
+    cnt = cnt.cpu().numpy() / args.steps
+    qps = nq * args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+    log(f"{name}: batched {qps:,.0f} QPS, {ms_step:.2f} ms/step at nprobe {chosen} "
+        f"({ms_instr:.2f} ms/step with per-step events and device counters)")
+    log(f"{name}: kernel ms/step: " + ", ".join(f"{n}={v[0] / args.steps:.3f}" for n, v in kt.items()))
+
+    # ---- roofline of the scan (and the exact stage) -------------------------------------------------------
+    # per (query, candidate) pair: the bytes a candidate's tests read as if each pair streamed its list
+    # (sign code + A, F, E per candidate; record + query levels per pair; the B-bit code and factors per
+    # stage-1 survivor; x_d row + a_x per stage-2 entrant; 8 B per exact-stage candidate written)
+    d, B = cfg["d"], cfg["bits"]
+    d4 = (d + 3) // 4 * 4
+    WP = next(w for w in (1, 2, 4, 8, 16, 32, 48) if 32 * w >= d)
+    KI = (d + 63) // 64
+    KP = 64 * (4 if KI == 3 else KI)
+    scanned, p1, pext, p2 = (float(x) for x in cnt[:4])
+    items, tiles2 = float(cnt[8]), float(cnt[9])
+    pairs_scan = nq * (chosen - 1)
+    pair_bytes = (scanned * (d / 8 + 12) + pairs_scan * (48 + KP)
+                  + (p1 * ((B - 1) * d / 8 + 12) if B > 1 else 0) + pext * (4 * d4 + 4) + p2 * 8)
+    # unique fetch: what the work items must read at least: each item's 64-row code block, factors and
+    # descriptor once, the x_d rows (and a_x) of each row tile that entered stage 2 once, each pair's record
+    # and levels once, the B-bit planes and factors of each item's block once (B > 1), the exact-stage
+    # entries written
+    unique_bytes = (items * (64 * (4 * WP + 12) + 16) + tiles2 * 16 * (4 * d4 + 4) + pairs_scan * (48 + KP)
+                    + (items * 64 * ((B - 1) * 4 * WP + 12) if B > 1 else 0) + p2 * 4)
+    G = group if group else 16
+    i8_ops = items * 2 * 64 * G * KP                  # stage-1 int8 products (64 rows x G queries x KP)
+    f32_ops = tiles2 * 2 * 16 * G * d4                # stage-2 FP32 products
+    valu_ops = items * 64 * G * 12                    # the Eq 4-6 epilogue per (row, query) entry
+    kern = {"scan": dict(bytes=pair_bytes, unique=unique_bytes, ops=scanned * 2 * d + pext * 2 * d),
+            "exact": dict(bytes=p2 * (8 + 4 * D), unique=p2 * (8 + 4 * D), ops=p2 * 3 * D)}
+    rows = {}
+    for kn, kb in kern.items():
+        ms_tot, launches = kt.get(kn, (0.0, 0))
+        if launches == 0 or ms_tot <= 0:
+            continue
+        per_ms = ms_tot / launches
+        lps = launches / args.steps
+        rows[kn] = dict(ms_per_step=ms_tot / args.steps, launch_ms=per_ms, launches=lps,
+                        gbs=kb["bytes"] / lps / (per_ms * 1e-3) / 1e9,
+                        ugbs=kb["unique"] / lps / (per_ms * 1e-3) / 1e9,
+                        tops=kb["ops"] / lps / (per_ms * 1e-3) / 1e12,
+                        bytes_per_launch=kb["bytes"] / lps, unique_per_launch=kb["unique"] / lps)
+    roof = None
+    if "scan" in rows:
+        r = rows["scan"]
+        t = r["launch_ms"] * 1e-3
+        lps = r["launches"]
+        t_hbm = r["unique_per_launch"] / (HBM_PEAK_GBS * 1e9)
+        t_cmp = (i8_ops / lps) / MFMA_I8_PEAK + (f32_ops / lps) / MFMA_F32_PEAK + (valu_ops / lps) / VALU_F32_PEAK
+        tag = f"{name}_d{d}_b{B}_np{chosen}_k{k}"
+        traffic = counter_traffic(tag, "k_scan")
+        roof = {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(r["gbs"] / HBM_PEAK_GBS, 4), "traffic": None if traffic is None else round(traffic),
+                "kernel": "k_scan",
+                "achieved_basis": "bytes per (query, candidate) pair: each candidate's code and factors once per "
+                                  "pair, as if every (query, list) pair streamed its list",
+                "algorithmic_bytes_per_launch": round(r["bytes_per_launch"]), "launch_ms": round(r["launch_ms"], 4),
+                "unique_fetch": {"bytes_per_launch": round(r["unique_per_launch"]), "GB/s": round(r["ugbs"], 1),
+                                 "frac": round(r["ugbs"] / HBM_PEAK_GBS, 4),
+                                 "frac_of_copy": None if not copy_gbs else round(r["ugbs"] / copy_gbs, 4)},
+                "roofline_frac": round(max(t_hbm, t_cmp) / t, 4),
+                "roofline_bound": "hbm (unique bytes)" if t_hbm >= t_cmp else "compute (i8 + f32 MFMA, VALU)",
+                "counter_GB/s": None if traffic is None else round(traffic / t / 1e9, 1),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                "work_per_launch": {"items": round(items / lps), "stage2_row_tiles": round(tiles2 / lps),
+                                    "pairs": round(pairs_scan / lps), "candidates": round(scanned / lps)},
+                "per_kernel": {n: {"ms_per_step": round(v["ms_per_step"], 4), "GB/s": round(v["gbs"], 1),
+                                   "unique_GB/s": round(v["ugbs"], 1), "TOP/s": round(v["tops"], 3)}
+                               for n, v in rows.items()}}
+
+    # ---- per-result distance error against FP64 (every returned row) ----------------------------------------
+    run(chosen)
+    torch.cuda.synchronize()
+    ids_h = ids_buf.cpu().numpy()
+    ok = ids_h >= 0
+    rel = []
+    for s0 in range(0, nq, 1024):
+        ii = ids_buf[s0:s0 + 1024].clamp(min=0)
+        d64 = ((Xd[ii].double() - Qd[s0:s0 + 1024, None, :].double()) ** 2).sum(-1)
+        e = (d_buf[s0:s0 + 1024].double() - d64).abs() / d64.clamp(min=1e-30)
+        rel.append(e[ids_buf[s0:s0 + 1024] >= 0].cpu())
+    rel = torch.cat(rel).numpy()
+    dist_err = {"results": int(ok.sum()), "max_rel": float(rel.max()), "p99_rel": float(np.percentile(rel, 99)),
+                "mean_rel": float(rel.mean())}
+
+    out = {
+        "value": round(qps, 1), "ms_per_step": round(ms_step, 4),
+        "config": {"workload": f"{name}: N={N} D={D} nq={nq} nlist={cfg['nlist']} d_r={d} bits={B} k={k}",
+                   "N": N, "D": D, "nq": nq, "nlist": cfg["nlist"], "d_r": d, "bits": B, "k": k,
+                   "nprobe": chosen, "recall_at_10": None if rec_at is None else round(rec_at, 4),
+                   "query_group": group, "phase_growth": growth, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "build_s": round(build_s, 2),
+        "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in kt.items()},
+        "ms_per_step_instrumented": round(ms_instr, 4),
+        "pass_rates": {"stage1": round(p1 / max(scanned, 1), 5), "ext": round(pext / max(scanned, 1), 5),
+                       "stage2_exact": round(p2 / max(scanned, 1), 6),
+                       "seed_scanned_per_query": round(float(cnt[4]) / nq, 1),
+                       "seed_exact_per_query": round(float(cnt[7]) / nq, 1),
+                       "exact_per_query": round(p2 / nq, 1),
+                       "scanned_per_query": round(scanned / nq, 1)},
+        "nprobe_sweep": sweep,
+        "distance_error_vs_fp64": dist_err,
+    }
+    if headline and not args.profile_only:
+        # the plain per-query GPU path at the same nprobe
+        npq = min(args.per_query, nq)
+        Qs = Qd[:npq].contiguous()
+        ib = torch.empty((npq, k), dtype=torch.int64, device=dev)
+        db = torch.empty((npq, k), dtype=torch.float32, device=dev)
+        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
+        torch.cuda.synchronize()
+        pq_qps = npq / (time.perf_counter() - tp)
+        same = bool(torch.equal(ib, ids_buf[:npq]))
+        log(f"{name}: per-query path {pq_qps:,.0f} QPS (ids identical to batched: {same})")
+        out.update({"per_query_qps": round(pq_qps, 1), "speedup_vs_per_query": round(qps / pq_qps, 1),
+                    "per_query_matches_batched": same})
+    if headline and not args.profile_only and not args.no_cpu_baseline:
+        out.update(cpu_baseline_leg(args, ix, X, Q, k, chosen, np, mrq))
+    del Xd, Qd, ids_buf, d_buf
+    ix.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_leg(args, ix, X, Q, k, nprobe, np, mrq):
+    """The CPU oracle (test infrastructure) on the exported index: its single-threaded Algorithm 2 timed on
+    one pinned host core over a bounded sample of the workload's queries, and, for the first queries, the
+    per-result error of the device's Eq 7 projected distance (FP32 projection) and eps_r (BF16 tail
+    coordinates) against the oracle's FP64 values."""
+    import oracle
+    res = {}
+    tmp = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    with tempfile.TemporaryDirectory(dir=tmp) as td:
+        path = os.path.join(td, "bench.mrqx")
+        ix.export(path)
+        orc = oracle.Index.load_export(path).attach(X)
+    prm = oracle.params()
+    cpu_info = cpu_description()
+    core = sorted(os.sched_getaffinity(0))[-1]
+    old_aff = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})  # this thread only, as `taskset -c core`
+    try:
+        n, tc = 0, time.perf_counter()
+        tot = {}
+        while n < Q.shape[0] and time.perf_counter() - tc < args.cpu_seconds:
+            _, _, c = orc.search(Q[n], k, nprobe, mode=oracle.ALG2, prm=prm, counters=True)
+            for key_, v in c.items():
+                tot[key_] = tot.get(key_, 0) + v
+            n += 1
+        el = time.perf_counter() - tc
+    finally:
+        os.sched_setaffinity(0, old_aff)
+    res["cpu_baseline"] = {
+        "value": round(n / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+        "sample": f"first {n} queries, single-threaded FP64 Algorithm 2 on the exported index, nprobe {nprobe}, "
+                  f"k {k}",
+        "cpu_model": cpu_info.get("Model name"), "cpu_mhz": cpu_info.get("CPU max MHz") or cpu_info.get("CPU MHz"),
+        "host_cpus": cpu_info.get("CPU(s)"), "pinning": f"sched_setaffinity of the oracle thread to core {core}",
+        "oracle_pass_rates": {"stage1": round(tot["pass1"] / max(tot["scanned"], 1), 5),
+                              "stage2_exact": round(tot["pass2"] / max(tot["scanned"], 1), 6),
+                              "scanned_per_query": round(tot["scanned"] / max(n, 1), 1)}}
+    log(f"cpu oracle: {res['cpu_baseline']['value']} QPS over {n} queries on core {core} "
+        f"({cpu_info.get('Model name')})")
+    # per-result projection error: the Eq 7 projected distance of every returned result that went through
+    # stage 2, device (FP32 q_d from the projection product) vs the oracle (FP64), relative to its exact
+    # distance; and eps_r per query (BF16 tail product) vs FP64
+    nt = min(args.proj_queries, Q.shape[0])
+    sub = np.ascontiguousarray(Q[:nt])
+    ids, dists, pairs, _, _, cands = ix.search_trace(sub, k, nprobe, list(range(nt)), max_pairs=nt * (nprobe + 1),
+                                                     max_cands=4 << 20)
+    diso = {(int(c["q"]), int(c["id"])): (float(c["v0"]), int(c["list"])) for c in cands
+            if c["kind"] == mrq.TRACE_STAGE2}
+    errs, er_err = [], []
+    cache = {}
+    for q in range(nt):
+        for i in ids[q][ids[q] >= 0].tolist():
+            hit = diso.get((q, i))
+            if hit is None:
+                continue
+            v, lst = hit
+            if (q, lst) not in cache:
+                cache[(q, lst)] = orc.pair_trace(sub[q], lst, prm)
+            qs, _, _, lid, cand = cache[(q, lst)]
+            r = int(np.nonzero(lid == i)[0][0])
+            errs.append(abs(v - cand["diso"][r]) / max(cand["dis"][r], 1e-30))
+        rec = pairs[pairs["q"] == q]
+        if len(rec):
+            qs0 = orc.pair_trace(sub[q], int(rec[0]["list"]), prm)[0]
+            er_err.append(abs(float(rec[0]["er"]) - qs0["er"]) / max(qs0["er"], 1e-30))
+    errs = np.array(errs) if errs else np.zeros(1)
+    res["projection_error_vs_fp64_oracle"] = {
+        "queries": nt, "results_with_stage2": int(len(errs)),
+        "dis_o_rel_to_exact_max": float(errs.max()), "dis_o_rel_to_exact_p99": float(np.percentile(errs, 99)),
+        "eps_r_rel_max": float(max(er_err) if er_err else 0.0),
+        "note": "q_d from the FP32 matrix-core projection; the tail coordinates (sigma, eps_r of Eq 6) from the "
+                "BF16 product with FP32 accumulation"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="gist1m")
+    ap.add_argument("--workload", default="deep10m", help="headline workload (deep10m, gist1m, openai2m, small)")
+    ap.add_argument("--nested", default="gist1m", help="workloads measured after the headline ('' for none)")
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--nlist", type=int, default=4096)
-    ap.add_argument("--d", type=int, default=128)
-    ap.add_argument("--bits", type=int, default=1)
+    ap.add_argument("--nlist", type=int, default=0, help="headline override of the workload's nlist")
+    ap.add_argument("--d", type=int, default=0, help="headline override of the workload's d_r")
+    ap.add_argument("--bits", type=int, default=0, help="headline override of the workload's code bits")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--nprobe", type=int, default=0, help="fixed nprobe (0 = smallest reaching the recall)")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--per-query", type=int, default=200, help="queries timed on the per-query path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline time budget")
+    ap.add_argument("--proj-queries", type=int, default=32, help="queries of the per-result projection report")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="skip GT/sweep/baselines (profiler runs)")
     ap.add_argument("--group", type=int, default=0,
@@ -132,229 +499,38 @@ def main():
         serve_main(args, np, torch, mrq, synth, dev)
         return
     if args.sweep_d:
+        if not args.nlist:
+            args.nlist = WORKLOADS.get(args.workload, WORKLOADS["gist1m"])["nlist"]
+        args.bits = args.bits or 1
         sweep_d_main(args, np, torch, mrq, synth, dev)
         return
     if args.mrsq:
+        if not args.nlist:
+            args.nlist = WORKLOADS.get(args.workload, WORKLOADS["gist1m"])["nlist"]
+        args.bits = args.bits or 1
         mrsq_main(args, np, torch, mrq, synth, dev)
         return
-    t0 = time.time()
-    X, Q, spec = synth.workload(args.workload, N=args.N, nq=args.nq)
-    N, D = X.shape
-    nq = Q.shape[0]
-    log(f"data {N}x{D}, {nq} queries in {time.time() - t0:.1f}s")
-    Xd = torch.from_numpy(X).to(dev)
-    Qd = torch.from_numpy(Q).to(dev)
-    torch.cuda.synchronize()
-    t1 = time.time()
-    ix = mrq.Index.build(Xd, d_r=args.d, bits=args.bits, nlist=args.nlist)
-    build_s = time.time() - t1
-    log(f"build {build_s:.1f}s, index {ix.device_bytes / 2**30:.2f} GiB")
-
-    k = args.k
-    ids_buf = torch.empty((nq, k), dtype=torch.int64, device=dev)
-    d_buf = torch.empty((nq, k), dtype=torch.float32, device=dev)
-
-    def run(nprobe, counters=None, mode=mrq.MRQ_BATCHED, Qs=None, ib=None, db=None):
-        o = mrq.search_opts(mode=mode, counters=counters, group=args.group, phase_growth=args.phase_growth)
-        Qs = Qd if Qs is None else Qs
-        return ix.search(Qs, k, nprobe, ids=ids_buf if ib is None else ib, dists=d_buf if db is None else db,
-                         opts=o)
-
-    chosen, rec_at = args.nprobe, None
-    sweep = []
+    copy_gbs, copy_ok = copy_bandwidth(torch, mrq, dev)
+    log(f"streaming copy: {copy_gbs:,.0f} GB/s (2 x 4 GiB per copy; correct: {copy_ok})")
+    head = measure(args, args.workload, np, torch, mrq, synth, dev, True, copy_gbs)
+    nested = {}
     if not args.profile_only:
-        t2 = time.time()
-        gt = ground_truth(torch, Xd, Qd, k)
-        log(f"ground truth {time.time() - t2:.1f}s")
-        # the smallest nprobe reaching the target: a coarse grid, the autotuner at its first value reaching
-        # the target, then (with the tuned schedule) every value between the last one below the target and
-        # that one
-        cands = [args.nprobe] if args.nprobe else [8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
-
-        def try_np(npb):
-            run(npb)
-            torch.cuda.synchronize()
-            r = recall(ids_buf.cpu().numpy(), gt, k)
-            sweep.append((npb, r))
-            log(f"nprobe {npb}: recall@{k} {r:.4f}")
-            return r
-
-        prev = 0
-        for npb in cands:
-            if npb > args.nlist:
-                break
-            chosen, rec_at = npb, try_np(npb)
-            if rec_at >= args.target_recall:
-                break
-            prev = npb
-    if not chosen:
-        chosen = 64
-
-    if args.calib_copy:  # a copy kernel of known size: 1 GiB read + 1 GiB written
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    # the autotuner picks the scan schedule (query-group size, phase growth) on this batch; the group size
-    # never changes a result, the phase growth only where an error bound fails
-    if args.group and args.phase_growth:
-        group, growth = args.group, args.phase_growth
-        log(f"query group {group}, phase growth {growth}")
-    else:
-        group, growth = ix.tune(Qd, k, chosen)
-        log(f"autotuned query group {group}, phase growth {growth}")
-    if not args.profile_only:
-        if chosen is not None and rec_at is not None and rec_at >= args.target_recall:
-            for fine in list(range(prev + 1, chosen)) + [chosen] if not args.nprobe else [chosen]:
-                rf = try_np(fine)
-                if rf >= args.target_recall or fine == chosen:
-                    chosen, rec_at = fine, rf
-                    break
-
-    # timed region: W warm-up steps, then K plain searches (the throughput); then K more searches, not
-    # timed, with per-kernel HIP events and device counters (the kernel breakdown and the roofline)
-    for _ in range(args.warmup):
-        run(chosen)
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    for _ in range(args.steps):
-        run(chosen)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - ts
-    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
-    ix.timing_enable(True, reset=True)
-    ti = time.perf_counter()
-    for _ in range(args.steps):
-        run(chosen, counters=cnt)
-    torch.cuda.synchronize()
-    ms_instr = 1e3 * (time.perf_counter() - ti) / args.steps
-    ix.timing_enable(False, reset=False)
-    kt = ix.timing()
-    cnt = cnt.cpu().numpy() / args.steps
-    qps = nq * args.steps / elapsed
-    ms_step = 1e3 * elapsed / args.steps
-    log(f"batched: {qps:,.0f} QPS, {ms_step:.2f} ms/step at nprobe {chosen} "
-        f"({ms_instr:.2f} ms/step with per-step events and device counters)")
-    log("kernel ms/step: " + ", ".join(f"{n}={v[0] / args.steps:.3f}" for n, v in kt.items()))
-
-    # roofline: algorithmic bytes (and multiply-add ops) per launch of each batched-phase kernel, from the
-    # device stage counters; the kernel with the largest device time is reported as dominant
-    d, B, bq = args.d, args.bits, 4
-    d4 = (d + 3) // 4 * 4
-    scanned, p1, pext, p2 = (float(x) for x in cnt[:4])
-    pairs_scan = nq * (chosen - 1)
-    KP = 64 * ((d + 63) // 64)
-    kern = {
-        # stage 1 (codes + factors per candidate, record + query bytes per pair), B-bit refinement per
-        # stage-1 survivor, Eq 7 per refined survivor (x_d row + a_x), 8 B per exact-stage candidate written
-        "scan": dict(bytes=scanned * (d / 8 + 12) + pairs_scan * (48 + KP)
-                     + (p1 * ((B - 1) * d / 8 + 12) if B > 1 else 0) + pext * (4 * d4 + 4) + p2 * 8,
-                     ops=scanned * 2 * d + pext * 2 * d),
-        "exact": dict(bytes=p2 * (8 + 4 * D), ops=p2 * 3 * D),
-    }
-    rows = {}
-    for name, kb in kern.items():
-        ms_tot, launches = kt.get(name, (0.0, 0))
-        if launches == 0 or ms_tot <= 0:
-            continue
-        per_ms = ms_tot / launches
-        per_launch_bytes = kb["bytes"] / (launches / args.steps)
-        per_launch_ops = kb["ops"] / (launches / args.steps)
-        rows[name] = dict(ms_per_step=ms_tot / args.steps, launch_ms=per_ms,
-                          gbs=per_launch_bytes / (per_ms * 1e-3) / 1e9,
-                          tops=per_launch_ops / (per_ms * 1e-3) / 1e12,
-                          bytes_per_launch=per_launch_bytes)
-    dom = max(rows, key=lambda n: rows[n]["ms_per_step"]) if rows else None
-    if dom:
-        r = rows[dom]
-        # both kernels stream per-candidate data: the HBM roof bounds them (the scan's matrix-core work,
-        # int8 stage 1 and FP32 stage 2, is far below the int8 / FP32 MFMA peaks; see per_kernel TOP/s)
-        roof = {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(r["gbs"] / HBM_PEAK_GBS, 4)}
-        tag = f"{args.workload}_d{args.d}_b{args.bits}_np{chosen}_k{k}"
-        kname = {"scan": "k_scan", "exact": "k_exact"}[dom]
-        traffic = counter_traffic(tag, kname)
-        roof.update({"kernel": kname, "traffic": None if traffic is None else round(traffic),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "algorithmic_bytes_per_launch": round(r["bytes_per_launch"]),
-                     "launch_ms": round(r["launch_ms"], 4),
-                     "per_kernel": {n: {"ms_per_step": round(v["ms_per_step"], 4), "GB/s": round(v["gbs"], 1),
-                                        "TOP/s": round(v["tops"], 3)} for n, v in rows.items()}})
-    else:
-        roof = None
-
-    out_extra = {}
-    if not args.profile_only:
-        # the plain per-query GPU path at the same nprobe
-        npq = min(args.per_query, nq)
-        Qs = Qd[:npq].contiguous()
-        ib = torch.empty((npq, k), dtype=torch.int64, device=dev)
-        db = torch.empty((npq, k), dtype=torch.float32, device=dev)
-        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
-        torch.cuda.synchronize()
-        tp = time.perf_counter()
-        run(chosen, mode=mrq.MRQ_PER_QUERY, Qs=Qs, ib=ib, db=db)
-        torch.cuda.synchronize()
-        pq_qps = npq / (time.perf_counter() - tp)
-        same = bool(torch.equal(ib, ids_buf[:npq]))
-        log(f"per-query path: {pq_qps:,.0f} QPS (ids identical to batched: {same})")
-        out_extra.update({"per_query_qps": round(pq_qps, 1), "speedup_vs_per_query": round(qps / pq_qps, 1),
-                          "per_query_matches_batched": same})
-
-    cpu = None
-    if not args.profile_only and not args.no_cpu_baseline:
-        import oracle
-        with tempfile.TemporaryDirectory() as td:
-            path = os.path.join(td, "bench.mrqx")
-            ix.export(path)
-            orc = oracle.Index.load_export(path).attach(X)
-            prm = oracle.params()
-            n, tc = 0, time.perf_counter()
-            tot = {}
-            while n < nq and time.perf_counter() - tc < args.cpu_seconds:
-                _, _, c = orc.search(Q[n], k, chosen, mode=oracle.ALG2, prm=prm, counters=True)
-                for key_, v in c.items():
-                    tot[key_] = tot.get(key_, 0) + v
-                n += 1
-            el = time.perf_counter() - tc
-            cpu = {"value": round(n / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-                   "sample": f"first {n} queries, single-threaded FP64 Algorithm 2 on the exported index, "
-                             f"nprobe {chosen}, k {k}",
-                   "oracle_pass_rates": {"stage1": round(tot["pass1"] / max(tot["scanned"], 1), 5),
-                                         "stage2_exact": round(tot["pass2"] / max(tot["scanned"], 1), 6),
-                                         "scanned_per_query": round(tot["scanned"] / max(n, 1), 1)}}
-            log(f"cpu oracle: {cpu['value']} QPS over {n} queries")
-
+        for nm in [w for w in args.nested.split(",") if w and w != args.workload]:
+            nested[nm] = measure(args, nm, np, torch, mrq, synth, dev, False, copy_gbs)
     res = {
         "metric": "QPS at recall@10=0.95 (1 GPU, batched vs per-query); scan HBM GB/s vs peak",
-        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": head.pop("value"), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} d_r={args.d} "
-                               f"bits={args.bits} k={k}",
-                   "N": N, "D": D, "nq": nq, "nlist": args.nlist, "d_r": args.d, "bits": args.bits, "k": k,
-                   "nprobe": chosen, "recall_at_10": None if rec_at is None else round(rec_at, 4),
-                   "query_group": group, "phase_growth": growth,
-                   "parallelism": "single-gpu"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "build_s": round(build_s, 2),
-        "kernel_ms_per_step": {n: round(v[0] / args.steps, 4) for n, v in kt.items()},
-        "ms_per_step_instrumented": round(ms_instr, 4),
-        "pass_rates": {"stage1": round(p1 / max(scanned, 1), 5), "ext": round(pext / max(scanned, 1), 5),
-                       "stage2_exact": round(p2 / max(scanned, 1), 6),
-                       "seed_scanned_per_query": round(float(cnt[4]) / nq, 1),
-                       "seed_exact_per_query": round(float(cnt[7]) / nq, 1),
-                       "exact_per_query": round(p2 / nq, 1),
-                       "scanned_per_query": round(scanned / nq, 1)},
-        "nprobe_sweep": sweep,
+        "config": head.pop("config"),
+        "roofline": head.pop("roofline"),
+        "cpu_baseline": head.pop("cpu_baseline", None),
+        "achievable_copy_GBps": round(copy_gbs, 1),
     }
-    res.update(out_extra)
+    res.update(head)
+    for nm, r in nested.items():
+        res[nm] = r
     print(json.dumps(res), flush=True)
-    ix.close()
 
 
 def sweep_d_main(args, np, torch, mrq, synth, dev):

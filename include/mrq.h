@@ -82,7 +82,7 @@ typedef struct {
     float m;                /* Eq 6 / Chebyshev multiplier; eps_r = 2 m sigma; default 3 */
     int32_t stage2;         /* 1 = use the Eq 7 projected-distance stage (MRQ+), 0 = plain MRQ; default 1 */
     int32_t use_ext;        /* 1 = refine stage-1 survivors with the B-bit code when B > 1; default 1 */
-    int64_t *counters;      /* optional device or host int64[8], accumulated (not cleared):
+    int64_t *counters;      /* optional device or host int64[ncounters], accumulated (not cleared):
                                [0..3] batched scan: candidates scanned, stage-1 survivors, B-bit
                                survivors, exact distances; [4..7] the same for the seed pass over
                                each query's nearest list */
@@ -99,7 +99,10 @@ typedef struct {
                                list), each against the threshold tau reached before it; g in {2, 4, 8}, 0 =
                                the index default (4, or what mrq_tune chose).  A result may differ between
                                values only where an error bound fails */
-    int32_t reserved[1];
+    int32_t ncounters;      /* entries of `counters`: 8 (0 = 8) or 16.  With 16, [8] and [9] also count the
+                               batched scan's work: work items (a 64-vector list block against up to `group`
+                               pairs) and 16-row tiles whose x_d rows entered stage 2; [10..15] are left
+                               untouched */
 } mrq_search_opts;
 
 /* Defaults for the option structs (pass NULL to any call to use them). */
@@ -167,6 +170,14 @@ mrq_status mrq_search(const mrq_index *index, const float *Q, int64_t nq, int32_
 #define MRQ_NOALLOC_BYTES ((size_t)128 << 20)
 mrq_status mrq_search_noalloc(const mrq_index *index, const float *Q, int64_t nq, int32_t k, int32_t nprobe,
                               int64_t *ids, float *dists, const mrq_search_opts *opts, mrq_stream stream);
+
+/*
+ * mrq_stream_copy — measurement aid: copies `bytes` from src to dst (device pointers, 16-byte aligned, bytes a
+ * multiple of 16) with a plain streaming kernel (each byte read once and written once, 16-byte accesses),
+ * asynchronously on `stream`.  Timed over a buffer far larger than the caches, 2 x bytes / time is the HBM
+ * bandwidth a streaming kernel achieves on the device, the reference the scan's bandwidth is compared with.
+ */
+mrq_status mrq_stream_copy(void *dst, const void *src, size_t bytes, mrq_stream stream);
 
 /*
  * mrq_search_trace — mrq_search with the per-stage values of chosen queries recorded by the search

@@ -24,6 +24,7 @@ EXPORTED = [
     "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
     "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
     "mrq_server_destroy", "mrq_choose_dr", "mrq_tune", "mrq_search_noalloc", "mrq_search_trace",
+    "mrq_stream_copy",
 ]
 NOALLOC_BYTES = 128 << 20  # MRQ_NOALLOC_BYTES
 
@@ -52,7 +53,7 @@ class SearchOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("bq", C.c_int32), ("eps0", C.c_float), ("m", C.c_float),
                 ("stage2", C.c_int32), ("use_ext", C.c_int32), ("counters", C.c_void_p),
                 ("group", C.c_int32), ("exact_cap", C.c_int32), ("method", C.c_int32), ("rerank", C.c_int32),
-                ("phase_growth", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("phase_growth", C.c_int32), ("ncounters", C.c_int32)]
 
 
 _lib = None
@@ -72,6 +73,7 @@ def lib() -> C.CDLL:
         L.mrq_search.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_mixed.argtypes = [P, P, I64, P, P, P, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_noalloc.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
+        L.mrq_stream_copy.argtypes = [P, P, C.c_size_t, P]
         L.mrq_search_trace.argtypes = [P, P, I64, I32, I32, C.POINTER(SearchOpts), P, I32, P, P, P, P, P, I64, P,
                                        P, I64, P]
         L.mrq_index_info.argtypes = [P, P, P, P, P, P, P]
@@ -135,6 +137,7 @@ def _stream(stream) -> Optional[int]:
 
 def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=True, counters=None,
                 group=0, exact_cap=0, method=MRQ_METHOD_MRQ, rerank=0, phase_growth=0) -> SearchOpts:
+    """Search options; `counters` (int64 array / tensor) of 8 entries, or of 16 for the extended counters."""
     o = SearchOpts()
     lib().mrq_search_opts_default(C.byref(o))
     o.mode, o.bq, o.eps0, o.m = int(mode), int(bq), float(eps0), float(m)
@@ -142,7 +145,14 @@ def search_opts(mode=MRQ_BATCHED, bq=4, eps0=1.9, m=3.0, stage2=True, use_ext=Tr
     o.exact_cap = int(exact_cap)
     o.method, o.rerank, o.phase_growth = int(method), int(rerank), int(phase_growth)
     o.counters = _ptr(counters) if counters is not None else None
+    o.ncounters = 16 if counters is not None and len(counters) >= 16 else 8
     return o
+
+
+def stream_copy(dst, src, stream=None):
+    """mrq_stream_copy of src into dst (device tensors of the same byte size)."""
+    nb = src.numel() * src.element_size()
+    _check(lib().mrq_stream_copy(_ptr(dst), _ptr(src), nb, _stream(stream)))
 
 
 def choose_dr(lam) -> int:

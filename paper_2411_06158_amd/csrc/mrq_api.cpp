@@ -519,6 +519,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (o.method != MRQ_METHOD_MRQ && o.method != MRQ_METHOD_MRSQ) throw Fail(MRQ_EINVAL, "unknown method");
     if (o.phase_growth != 0 && o.phase_growth != 2 && o.phase_growth != 4 && o.phase_growth != 8)
         throw Fail(MRQ_EINVAL, "phase_growth must be 0, 2, 4 or 8");
+    if (o.ncounters != 0 && o.ncounters != 8 && o.ncounters != 16) throw Fail(MRQ_EINVAL, "ncounters must be 0, 8 or 16");
+    const int ncnt = o.ncounters == 16 ? 16 : 8;
     const int rerank = o.rerank == 0 ? 500 : o.rerank;
     if (o.method == MRQ_METHOD_MRSQ) {
         if (ix->dq == 0) throw Fail(MRQ_ESTATE, "the index has no MR-SQ codes (build it with sq8 = 1)");
@@ -598,7 +600,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
         *qs = q_dev ? nullptr : c.take<float>(nq * ix->D);
         *ids_s = ids_dev ? nullptr : c.take<int64_t>(out_total);
         *d_s = d_dev ? nullptr : c.take<float>(out_total);
-        *cnt_s = cnt_host ? c.take<int64_t>(8) : nullptr;
+        *cnt_s = cnt_host ? c.take<int64_t>(ncnt) : nullptr;
         *sw = base ? base + c.used : nullptr;
         *used = c.used + search_workspace_bytes(*ix, nq_run, slots_run, pairs_run, o.bq, np_max, o.method, rerank);
     };
@@ -649,7 +651,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     int64_t* ids_d = ids_dev ? ids : ids_s;
     float* dd = d_dev ? dists : d_s;
     int64_t* cnt_d = o.counters ? (cnt_host ? cnt_s : o.counters) : nullptr;
-    if (cnt_host) hip_check(launch_fill_i32(reinterpret_cast<int32_t*>(cnt_s), 0, 16, s), "fill");
+    if (cnt_host) hip_check(launch_fill_i32(reinterpret_cast<int32_t*>(cnt_s), 0, 2 * ncnt, s), "fill");
     if (!uniform_kq) {
         std::vector<int64_t> so_h(nq + 1, 0), po_h(nq + 1, 0);
         for (int64_t i = 0; i < nq; i++) {
@@ -677,6 +679,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.rerank = rerank;
     a.phase_shift = o.phase_growth == 2 ? 1 : (o.phase_growth == 4 ? 2 : (o.phase_growth == 8 ? 3 : ix->phase_shift_default));
     a.counters = cnt_d;
+    a.ncounters = ncnt;
     a.trace = trace;
     if (trace && (per_query || o.method != MRQ_METHOD_MRQ))
         throw Fail(MRQ_EINVAL, "a traced search runs the batched MRQ method");
@@ -734,11 +737,12 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (!ids_dev || !d_dev || cnt_host) {
         if (!ids_dev) hip_check(hipMemcpyAsync(ids, ids_s, out_total * 8, hipMemcpyDeviceToHost, s), "copy ids");
         if (!d_dev) hip_check(hipMemcpyAsync(dists, d_s, out_total * 4, hipMemcpyDeviceToHost, s), "copy dists");
-        int64_t ch[8] = {0};
-        if (cnt_host) hip_check(hipMemcpyAsync(ch, cnt_s, sizeof(ch), hipMemcpyDeviceToHost, s), "copy counters");
+        int64_t ch[16] = {0};
+        if (cnt_host)
+            hip_check(hipMemcpyAsync(ch, cnt_s, sizeof(int64_t) * ncnt, hipMemcpyDeviceToHost, s), "copy counters");
         hip_check(hipStreamSynchronize(s), "search sync");
         if (cnt_host)
-            for (int i = 0; i < 8; i++) o.counters[i] += ch[i];
+            for (int i = 0; i < ncnt; i++) o.counters[i] += ch[i];
     }
     return MRQ_OK;
 }
@@ -958,6 +962,17 @@ mrq_status mrq_search_noalloc(const mrq_index* index, const float* Q, int64_t nq
         hip_check(noalloc_scratch(&buf, &bytes), "fixed search buffer");
         return run_search(index, Q, nq, true, k, nprobe, nullptr, nullptr, nullptr, ids, dists, opts,
                           (hipStream_t)stream, buf, bytes);
+    });
+}
+
+mrq_status mrq_stream_copy(void* dst, const void* src, size_t bytes, mrq_stream stream) {
+    return guarded([&]() {
+        if (!dst || !src) throw Fail(MRQ_EINVAL, "dst and src must not be NULL");
+        if (bytes % 16 || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15))
+            throw Fail(MRQ_EINVAL, "bytes and both pointers must be multiples of 16");
+        if (!is_device_ptr(dst) || !is_device_ptr(src)) throw Fail(MRQ_EINVAL, "device pointers only");
+        hip_check(launch_stream_copy(dst, src, bytes, (hipStream_t)stream), "stream copy");
+        return MRQ_OK;
     });
 }
 

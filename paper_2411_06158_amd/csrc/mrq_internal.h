@@ -163,7 +163,8 @@ struct SearchArgs {
     int32_t rerank = 500;   // MR-SQ: candidates re-ranked by exact distance per query
     int64_t* ids;          // device output
     float* dists;          // device output
-    int64_t* counters;     // device int64[8] or null
+    int64_t* counters;     // device int64[ncounters] or null
+    int32_t ncounters = 8; // 8 or 16
     bool timed = true;     // record per-kernel events when the index timer is on
     bool fork_seed = true; // run the seed pass on the index's auxiliary stream beside the pair preparation
     const TraceSink* trace = nullptr;  // device; non-null: run the tracing instantiations (query group 16)
@@ -177,6 +178,8 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
 // kNoAllocBytes, its address looked up once per device).
 constexpr size_t kNoAllocBytes = MRQ_NOALLOC_BYTES;
 hipError_t noalloc_scratch(void** p, size_t* bytes);
+// Streaming copy of bytes / 16 words (16-byte aligned device pointers).
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // build-side launchers
 // MR-SQ codes of an index whose x_d and ids are in place (tx64_rows: FP64 ||x_r||^2 per row; scratch:

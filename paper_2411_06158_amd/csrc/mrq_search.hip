@@ -1465,6 +1465,7 @@ struct ScanCtx {
     const float* RC;
     const float* Tq;
     const TraceSink* tr;  // tracing instantiations only
+    int cnt_ext;          // counters has 16 entries: the scan also counts its work units into [8..11]
     float eps0;
     int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, cq;
 };
@@ -1619,8 +1620,10 @@ __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slo
 // KIT = 0: any d.  QL (d4 = 64 KIT, KIT <= 2): operands reach LDS by direct global-to-LDS loads ahead of
 // their use (the next item's stage-1 operands during the current item, the current item's q_d rows at its
 // start) and the x_d slices of a row tile are loaded while the previous tile is multiplied.
+// At least two waves per SIMD (at most 256 VGPRs + AGPRs per lane) for groups of 16 and 32: the LDS-staged
+// form sits at that edge; groups of 64 take one (they would spill).
 template <int GT, int KIT, bool QL, bool TR>
-__global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
+__global__ __launch_bounds__(256, GT >= 64 ? 1 : 2) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
     constexpr int XS = QL && KIT > 0 ? 4 * KIT : 1;  // x_d slices of a row tile held in registers
@@ -1654,6 +1657,10 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     const int wid = uniform(blockIdx.x * 4 + wv);
     int nreg = 0;  // candidates this wave passed to the exact stage (bins or in place)
     long long nscan = 0, n1 = 0, next = 0;
+    // extended counters: row tiles whose x_d entered stage 2, accumulated in the wave's LDS slot (nothing
+    // held in registers across items); the wave's item count follows from the loop bounds
+    __shared__ int sh_tiles[4];
+    if (lane == 0) sh_tiles[wv] = 0;
     // Items are dealt to the waves round-robin (neighbouring waves take neighbouring blocks of a list).
     // Descriptors are read two items ahead; the pair records of the next item travel in registers (three
     // float4 per lane) until they are stored.
@@ -1867,6 +1874,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         }
         nscan += 64ll * ng;
         n1 += cnt;
+
         wave_lds_fence();
         // ---- B-bit refinement of the stage-1 survivors ----
         if (cnt > 0 && do_ext) {
@@ -1934,6 +1942,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                     for (int ct = 0; ct < nct; ct++)
 #pragma unroll
                         for (int v = 0; v < 4; v++) rtany |= (msk[(ct * 4 + rt) * 4 + v] != 0ull ? 1u : 0u) << rt;
+                if (c.cnt_ext && lane == 0) sh_tiles[wv] += __popc(rtany);
                 float4 xb[2][XS];
                 float axb[2] = {0.f, 0.f};
 #pragma unroll
@@ -1983,12 +1992,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             } else {
                 for (int rt = 0; rt < 4; rt++) {
                     const int64_t row = row0 + 16 * rt + li;
+                    bool tile_used = false;
                     for (int ct = 0; ct < nct; ct++) {
                         unsigned long long mv[4];
                         bool any = false;
 #pragma unroll
                         for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
                         if (!any) continue;
+                        tile_used = true;
                         const int qs = ct * 16 + li;
                         const bool qv = qs < ng;
                         const int qrow = rec[qv ? qs : 0].q;
@@ -2014,6 +2025,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             cnt += __popcll(nm);
                         }
                     }
+                    if (c.cnt_ext && lane == 0 && tile_used) sh_tiles[wv] += 1;
                 }
             }
             wave_lds_fence();
@@ -2067,6 +2079,11 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         atomicAdd((unsigned long long*)&c.counters[1], (unsigned long long)n1);
         atomicAdd((unsigned long long*)&c.counters[2], (unsigned long long)next);
         atomicAdd((unsigned long long*)&c.counters[3], (unsigned long long)nreg);
+        if (c.cnt_ext) {
+            const int items = wid < total ? (total - wid - 1) / nwaves + 1 : 0;
+            atomicAdd((unsigned long long*)&c.counters[8], (unsigned long long)items);
+            atomicAdd((unsigned long long*)&c.counters[9], (unsigned long long)sh_tiles[wv]);
+        }
     }
 }
 
@@ -3105,6 +3122,38 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
     return hipSuccess;
 }
 
+// ---- streaming copy: the achievable HBM bandwidth the scan is measured against -----------------------
+// Each thread moves four 16-byte words per step (all four loads issued before the stores), grid-stride,
+// with non-temporal hints: every byte is read once and written once.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                     int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 1024;
+    for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t j = i + 256 * u;
+            if (j < n) v[u] = __builtin_nontemporal_load(src + j);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t j = i + 256 * u;
+            if (j < n) __builtin_nontemporal_store(v[u], dst + j);
+        }
+    }
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 1023) / 1024, 8192);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const u32x4*>(src),
+                       reinterpret_cast<u32x4*>(dst), n);
+    return hipGetLastError();
+}
+
 // ---- fixed device buffer of the allocation-free search ---------------------------------------------
 // One array per device, held for the life of the process.  Host code must not pass `scratch` itself to a
 // kernel (in host code the name stands for a host-side shadow, not a device address): its device address
@@ -3171,6 +3220,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.kq = a.kq; c.npq = a.npq; c.slot_off = a.slot_off; c.pair_off = a.pair_off; c.pair_pos = w.pair_pos;
     c.slots = w.slots; c.surv = w.surv; c.qcnt = w.qcnt; c.counters = a.counters;
     c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0; c.tr = a.trace;
+    c.cnt_ext = a.counters && a.ncounters >= 16;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = level_bytes(d);
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;

@@ -242,6 +242,35 @@ def test_counters_monotone(small):
         assert scanned > 0 and scanned >= p1 >= pext >= p2 > 0
 
 
+def test_extended_counters_count_scan_work(small):
+    """16 counters: [0..7] as with 8; [8] scan work items, [9] row tiles whose x_d entered stage 2 (at most four
+    per item, at least one per item with a stage-2 entrant)."""
+    c8 = torch.zeros(8, dtype=torch.int64, device="cuda")
+    c16 = torch.zeros(16, dtype=torch.int64, device="cuda")
+    small["ix"].search(small["Qd"], 10, 16, counters=c8, group=16)
+    small["ix"].search(small["Qd"], 10, 16, counters=c16, group=16)
+    torch.cuda.synchronize()
+    c8, c16 = c8.cpu().numpy(), c16.cpu().numpy()
+    assert np.array_equal(c8, c16[:8])
+    items, tiles = c16[8], c16[9]
+    assert items > 0 and 0 < tiles <= 4 * items
+    assert np.all(c16[10:] == 0)
+    # every item is a 64-row block against at most 16 pairs: items * 64 * 16 >= candidates scanned
+    assert items * 64 * 16 >= c16[0]
+
+
+def test_stream_copy_moves_every_byte():
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    mrq.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    with pytest.raises(mrq.MRQError) as e:
+        mrq.lib()
+        mrq._check(mrq.lib().mrq_stream_copy(dst.data_ptr() + 4, src.data_ptr(), 64, None))
+    assert e.value.status == mrq.MRQ_EINVAL
+
+
 # ---- edge cases -----------------------------------------------------------------------------------
 
 def test_padding_when_k_exceeds_candidates():
