@@ -342,7 +342,7 @@ def measure(args, name, np, torch, mrq, synth, dev, headline, copy_gbs):
         "nprobe_sweep": sweep,
         "distance_error_vs_fp64": dist_err,
     }
-    if headline and not args.profile_only:
+    if headline and not args.profile_only and args.per_query > 0:
         # the plain per-query GPU path at the same nprobe
         npq = min(args.per_query, nq)
         Qs = Qd[:npq].contiguous()
@@ -447,7 +447,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="deep10m", help="headline workload (deep10m, gist1m, openai2m, small)")
-    ap.add_argument("--nested", default="gist1m", help="workloads measured after the headline ('' for none)")
+    ap.add_argument("--nested", default="gist1m", help="workloads measured after the headline ('none' for none)")
     ap.add_argument("--N", type=int, default=None)
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--nlist", type=int, default=0, help="headline override of the workload's nlist")
@@ -515,7 +515,7 @@ def main():
     head = measure(args, args.workload, np, torch, mrq, synth, dev, True, copy_gbs)
     nested = {}
     if not args.profile_only:
-        for nm in [w for w in args.nested.split(",") if w and w != args.workload]:
+        for nm in [w for w in args.nested.split(",") if w in WORKLOADS and w != args.workload]:
             nested[nm] = measure(args, nm, np, torch, mrq, synth, dev, False, copy_gbs)
     res = {
         "metric": "QPS at recall@10=0.95 (1 GPU, batched vs per-query); scan HBM GB/s vs peak",

@@ -1620,10 +1620,11 @@ __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slo
 // KIT = 0: any d.  QL (d4 = 64 KIT, KIT <= 2): operands reach LDS by direct global-to-LDS loads ahead of
 // their use (the next item's stage-1 operands during the current item, the current item's q_d rows at its
 // start) and the x_d slices of a row tile are loaded while the previous tile is multiplied.
-// At least two waves per SIMD (at most 256 VGPRs + AGPRs per lane) for groups of 16 and 32: the LDS-staged
-// form sits at that edge; groups of 64 take one (they would spill).
+// The LDS-staged form at 16 queries per item sits at the edge of two waves per SIMD (VGPRs + AGPRs <= 256).
+// Declaring that occupancy (a minimum of two waves) made the compiler keep the accumulators out of AGPRs and
+// the scan 25 % slower (measured), so the budget is left to the compiler's own heuristic.
 template <int GT, int KIT, bool QL, bool TR>
-__global__ __launch_bounds__(256, GT >= 64 ? 1 : 2) void k_scan(ScanCtx c) {
+__global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
     constexpr int XS = QL && KIT > 0 ? 4 * KIT : 1;  // x_d slices of a row tile held in registers
