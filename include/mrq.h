@@ -250,6 +250,27 @@ mrq_status mrq_search_mixed(const mrq_index *index, const float *Q, int64_t nq, 
                             const mrq_search_opts *opts, mrq_stream stream);
 
 /*
+ * mrq_search_mixed_dev — mrq_search_mixed for a batch whose per-query k[i] and nprobe[i] (Algorithm 2's
+ * inputs, per query) are device arrays, with host upper bounds k_max >= every k[i] and nprobe_max >= every
+ * nprobe[i].  The per-query offsets are formed and the entries checked on the device, so the call neither
+ * synchronises with the host nor copies anything to it, and it may be recorded into a HIP graph (stream
+ * capture) once a search of the same nq, bounds and options has run, like mrq_search.
+ *   k, nprobe   nq int32 each (device); a query with k outside [1, k_max], nprobe outside [1, nprobe_max] or
+ *               a negative out_off is rejected: nothing is searched or written for it, and the number of
+ *               rejected queries is written to *rejected (device int32, may be NULL)
+ *   out_off     nq int64 (device) offsets of the result rows, or NULL: rows packed in query order, query i
+ *               at sum_{j < i} k[j] over the accepted queries
+ *   k_max       in [1, 1024]; nprobe_max in [1, min(nlist, 1024)]; the workspace is sized for nq x k_max
+ *               result slots and nq x nprobe_max pairs
+ *   Q, ids, dists and opts->counters are device pointers; opts->mode must be MRQ_BATCHED and opts->method
+ *   MRQ_METHOD_MRQ (MRQ_EINVAL otherwise).  Results equal mrq_search_mixed's.
+ */
+mrq_status mrq_search_mixed_dev(const mrq_index *index, const float *Q, int64_t nq, const int32_t *k,
+                                const int32_t *nprobe, const int64_t *out_off, int32_t k_max, int32_t nprobe_max,
+                                int64_t *ids, float *dists, int32_t *rejected, const mrq_search_opts *opts,
+                                mrq_stream stream);
+
+/*
  * mrq_choose_dr — the rule of Eq 8 (Section 5.3): the smallest power of two d = 2^i with d >= 128 whose
  * leading eigenvalues hold at least 80 % of the total variance, sum_{j<d} lambda_j >= 0.8 sum_j lambda_j
  * (lambda: the D eigenvalues in descending order, host FP64).  A choice reaching D returns D; above
@@ -292,19 +313,21 @@ mrq_status mrq_timing_enable(mrq_index *index, int on, int reset);
 
 /*
  * Serving (continuous batching) of mrq_search for requests that arrive one at a time.  A server owns a
- * host thread and two batch slots (each with its own stream, pinned staging buffers and device
- * workspace).  Submitted requests wait in arrival order; whenever a slot is free the thread admits
- * the waiting requests (up to max_slots per batch) whose batch still fits the device-memory budget
- * left by the other slot, copies them to the device, runs one mixed-k / nprobe batched search and
- * copies the results back on the slot's stream, so a new batch is packed and launched while the
- * previous one is still on the device.  A request's result is the same as mrq_search's for that query
- * alone (search results do not depend on the batch).
- *   mrq_server_create:  mem_budget = device bytes both slots may use together (0 = no limit);
+ * host thread and two batch slots (each with its own stream, its own auxiliary stream and events for the
+ * search's seed pass, pinned staging buffers and a device buffer).  Submitted requests wait in arrival
+ * order; whenever a slot is free the thread admits the waiting requests (up to max_slots per batch) whose
+ * batch still fits the slot's device buffer, copies them to the device, runs one mixed-k / nprobe batched
+ * search and copies the results back on the slot's stream, so a new batch is packed and launched while
+ * the previous one is still on the device.  A request's result is the same as mrq_search's for that query
+ * alone (search results do not depend on the batch).  The server shares only the index's read-only
+ * arrays, so the index may also be searched directly while the server runs (not tuned or freed).
+ *   mrq_server_create:  mem_budget = device bytes of the server (0 = no limit): each slot's buffer is half
+ *                       of it, allocated here, so nothing is allocated or freed while batches run;
  *                       max_slots in [1, 65536] queries per batch; opts as for mrq_search (mode and
  *                       counters are ignored); the index must outlive the server
  *   mrq_server_submit:  q_host = D floats (copied before return); MRQ_EINVAL for a bad k or nprobe,
- *                       MRQ_ENOMEM when one such request alone would exceed the budget; otherwise the
- *                       request is queued until it can be admitted
+ *                       MRQ_ENOMEM when one such request alone would exceed a slot's half of the budget;
+ *                       otherwise the request is queued until it can be admitted
  *   mrq_server_poll:    moves up to max_done finished requests out: req_ids[i], ks[i] (may be NULL),
  *                       ids / dists rows of stride `row` (>= the request's k), latency_ms[i] = arrival
  *                       to completion (may be NULL; -1 if the batch failed, its row is -1 / +inf);
@@ -321,6 +344,11 @@ int mrq_server_poll(mrq_server *server, uint64_t *req_ids, int32_t *ks, int64_t 
                     int32_t row, int32_t max_done, double *latency_ms);
 mrq_status mrq_server_drain(mrq_server *server, int64_t timeout_ms);
 void mrq_server_destroy(mrq_server *server);
+/* Server statistics (any pointer may be NULL): device bytes held now and at most, batches launched, and the
+ * largest number of batches on the device at once (2 when a batch was launched while the other slot's was
+ * still running). */
+mrq_status mrq_server_stats(const mrq_server *server, int64_t *device_bytes, int64_t *peak_device_bytes,
+                            int64_t *batches, int32_t *max_in_flight);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ EXPORTED = [
     "mrq_index_info", "mrq_export", "mrq_save", "mrq_load", "mrq_free", "mrq_last_error", "mrq_timing",
     "mrq_timing_enable", "mrq_server_create", "mrq_server_submit", "mrq_server_poll", "mrq_server_drain",
     "mrq_server_destroy", "mrq_choose_dr", "mrq_tune", "mrq_search_noalloc", "mrq_search_trace",
-    "mrq_stream_copy",
+    "mrq_stream_copy", "mrq_search_mixed_dev", "mrq_server_stats",
 ]
 NOALLOC_BYTES = 128 << 20  # MRQ_NOALLOC_BYTES
 
@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
         L.mrq_search_mixed.argtypes = [P, P, I64, P, P, P, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_noalloc.argtypes = [P, P, I64, I32, I32, P, P, C.POINTER(SearchOpts), P]
         L.mrq_stream_copy.argtypes = [P, P, C.c_size_t, P]
+        L.mrq_search_mixed_dev.argtypes = [P, P, I64, P, P, P, I32, I32, P, P, P, C.POINTER(SearchOpts), P]
         L.mrq_search_trace.argtypes = [P, P, I64, I32, I32, C.POINTER(SearchOpts), P, I32, P, P, P, P, P, I64, P,
                                        P, I64, P]
         L.mrq_index_info.argtypes = [P, P, P, P, P, P, P]
@@ -94,6 +95,7 @@ def lib() -> C.CDLL:
             L.mrq_server_drain.argtypes = [P, I64]
             L.mrq_server_destroy.argtypes = [P]
             L.mrq_server_destroy.restype = None
+            L.mrq_server_stats.argtypes = [P, P, P, P, P]
         L.mrq_choose_dr.argtypes = [P, I32]
         L.mrq_choose_dr.restype = I32
         L.mrq_tune.argtypes = [P, P, I64, I32, I32, P, P, P]
@@ -261,6 +263,17 @@ class Index:
         _check(lib().mrq_search_mixed(self._h, _ptr(Q), len(k), _ptr(k), _ptr(nprobe), _ptr(off), _ptr(ids),
                                       _ptr(dists), C.byref(o), _stream(stream)))
         return ids, dists, off
+
+    def search_mixed_dev(self, Q, k, nprobe, k_max: int, nprobe_max: int, ids, dists, out_off=None,
+                         rejected=None, opts: Optional[SearchOpts] = None, stream=None, **kw):
+        """mrq_search_mixed_dev: per-query k / nprobe as device int32 tensors (bounded by k_max / nprobe_max),
+        results into device tensors ids / dists at out_off (device int64, or None: packed in query order);
+        no host synchronisation (capturable)."""
+        o = opts if opts is not None else search_opts(**kw)
+        _check(lib().mrq_search_mixed_dev(self._h, _ptr(Q), int(Q.shape[0]), _ptr(k), _ptr(nprobe), _ptr(out_off),
+                                          int(k_max), int(nprobe_max), _ptr(ids), _ptr(dists), _ptr(rejected),
+                                          C.byref(o), _stream(stream)))
+        return ids, dists
 
     def tune(self, Q, k: int, nprobe: int, stream=None):
         """Time the scan schedules (query group, phase growth) on queries Q and keep the fastest as this

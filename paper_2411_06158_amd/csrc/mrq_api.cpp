@@ -504,7 +504,11 @@ void resolve_opts(const mrq_search_opts* in, mrq_search_opts* o) {
 mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uniform_kq, int32_t k_u, int32_t np_u,
                       const int32_t* k_arr, const int32_t* np_arr, const int64_t* out_off_arr, int64_t* ids,
                       float* dists, const mrq_search_opts* opts_in, hipStream_t s, void* fixed_ws = nullptr,
-                      size_t fixed_bytes = 0, const TraceSink* trace = nullptr) {
+                      size_t fixed_bytes = 0, const TraceSink* trace = nullptr, int32_t dev_kb = 0, int32_t dev_npb = 0,
+                      int32_t* rejected = nullptr) {
+    // dev_kb > 0: a mixed batch whose k / nprobe / out_off are device arrays, bounded by dev_kb / dev_npb (checked
+    // and prefix-summed on the device: no host synchronisation, so the call may be captured)
+    const bool dev_mixed = !uniform_kq && dev_kb > 0;
     mrq_index* ix = const_cast<mrq_index*>(cix);
     const bool fixed = fixed_ws != nullptr;  // the allocation-free search: caller buffers plus a fixed workspace
     if (!ix) throw Fail(MRQ_EINVAL, "index is NULL");
@@ -534,7 +538,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     hip_check(hipStreamIsCapturing(s, &cap), "capture status");
     const bool capturing = cap != hipStreamCaptureStatusNone;
     if (capturing) {
-        if (!uniform_kq) throw Fail(MRQ_ESTATE, "a search with per-query k / nprobe cannot be captured");
+        if (!uniform_kq && !dev_mixed)
+            throw Fail(MRQ_ESTATE, "a search with per-query k / nprobe on the host cannot be captured");
         if (!is_device_ptr(Q) || !is_device_ptr(ids) || !is_device_ptr(dists) ||
             (o.counters && !is_device_ptr(o.counters)))
             throw Fail(MRQ_ESTATE, "a captured search needs device Q, ids, dists and counters");
@@ -546,7 +551,21 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     std::vector<int64_t> offh;
     int32_t k_max = k_u, np_max = np_u;
     int64_t total_slots = 0, total_pairs = 0, out_total = 0;
-    if (uniform_kq) {
+    if (dev_mixed) {
+        if (!k_arr || !np_arr) throw Fail(MRQ_EINVAL, "k and nprobe must not be NULL");
+        if (!is_device_ptr(k_arr) || !is_device_ptr(np_arr) || (out_off_arr && !is_device_ptr(out_off_arr)) ||
+            (rejected && !is_device_ptr(rejected)))
+            throw Fail(MRQ_EINVAL, "k, nprobe, out_off and rejected must be device arrays");
+        if (dev_kb < 1 || dev_kb > kMaxK) throw Fail(MRQ_EINVAL, "k_max must be in [1, 1024]");
+        if (dev_npb < 1 || dev_npb > np_cap) throw Fail(MRQ_EINVAL, "nprobe_max must be in [1, min(nlist, 1024)]");
+        if (o.mode != MRQ_BATCHED || o.method != MRQ_METHOD_MRQ)
+            throw Fail(MRQ_EINVAL, "a device-side mixed batch runs the batched MRQ method");
+        k_max = dev_kb;
+        np_max = dev_npb;
+        total_slots = nq * dev_kb;  // upper bounds: the kernels read the actual totals from the device offsets
+        total_pairs = nq * dev_npb;
+        out_total = 0;
+    } else if (uniform_kq) {
         if (k_u < 1 || k_u > kMaxK) throw Fail(MRQ_EINVAL, "k must be in [1, 1024]");
         if (np_u < 1 || np_u > np_cap) throw Fail(MRQ_EINVAL, "nprobe must be in [1, min(nlist, 1024)]");
         if (o.method == MRQ_METHOD_MRSQ && k_u > rerank) throw Fail(MRQ_EINVAL, "rerank must be in [k, 16384]");
@@ -585,6 +604,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     const int64_t pairs_run = per_query ? np_max : total_pairs;
     const bool q_dev = is_device_ptr(Q), ids_dev = is_device_ptr(ids), d_dev = is_device_ptr(dists);
     const bool cnt_host = o.counters && !is_device_ptr(o.counters);
+    if (dev_mixed && (!q_dev || !ids_dev || !d_dev || cnt_host))
+        throw Fail(MRQ_EINVAL, "a device-side mixed batch takes device Q, ids, dists and counters");
     if (fixed && (!uniform_kq || !q_dev || !ids_dev || !d_dev || cnt_host))
         throw Fail(MRQ_EINVAL, "the allocation-free search takes device Q, ids, dists and counters and a uniform k / nprobe");
 
@@ -652,7 +673,10 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     float* dd = d_dev ? dists : d_s;
     int64_t* cnt_d = o.counters ? (cnt_host ? cnt_s : o.counters) : nullptr;
     if (cnt_host) hip_check(launch_fill_i32(reinterpret_cast<int32_t*>(cnt_s), 0, 2 * ncnt, s), "fill");
-    if (!uniform_kq) {
+    if (dev_mixed) {
+        hip_check(launch_mixed_meta(nq, k_arr, np_arr, out_off_arr, dev_kb, dev_npb, kq, npq, so, po, oo, rejected, s),
+                  "meta");
+    } else if (!uniform_kq) {
         std::vector<int64_t> so_h(nq + 1, 0), po_h(nq + 1, 0);
         for (int64_t i = 0; i < nq; i++) {
             so_h[i + 1] = so_h[i] + kh[i];
@@ -1083,6 +1107,17 @@ mrq_status mrq_search_mixed(const mrq_index* index, const float* Q, int64_t nq, 
                             const mrq_search_opts* opts, mrq_stream stream) {
     return guarded([&]() {
         return run_search(index, Q, nq, false, 0, 0, k, nprobe, out_off, ids, dists, opts, (hipStream_t)stream);
+    });
+}
+
+mrq_status mrq_search_mixed_dev(const mrq_index* index, const float* Q, int64_t nq, const int32_t* k,
+                                const int32_t* nprobe, const int64_t* out_off, int32_t k_max, int32_t nprobe_max,
+                                int64_t* ids, float* dists, int32_t* rejected, const mrq_search_opts* opts,
+                                mrq_stream stream) {
+    return guarded([&]() {
+        if (k_max < 1) throw Fail(MRQ_EINVAL, "k_max must be in [1, 1024]");
+        return run_search(index, Q, nq, false, 0, 0, k, nprobe, out_off, ids, dists, opts, (hipStream_t)stream,
+                          nullptr, 0, nullptr, k_max, nprobe_max, rejected);
     });
 }
 

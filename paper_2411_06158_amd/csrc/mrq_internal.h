@@ -168,6 +168,9 @@ struct SearchArgs {
     bool timed = true;     // record per-kernel events when the index timer is on
     bool fork_seed = true; // run the seed pass on the index's auxiliary stream beside the pair preparation
     const TraceSink* trace = nullptr;  // device; non-null: run the tracing instantiations (query group 16)
+    // stream and events of the seed pass's fork (null: the index's own, created by its first search)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, int64_t total_pairs,
@@ -215,6 +218,9 @@ hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, cons
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_uniform_meta(int64_t nq, int k, int np, int32_t* kq, int32_t* npq, int64_t* slot_off,
                                int64_t* pair_off, int64_t* out_off, hipStream_t s);
+hipError_t launch_mixed_meta(int64_t nq, const int32_t* k, const int32_t* np, const int64_t* out_off_in, int kb,
+                             int npb, int32_t* kq, int32_t* npq, int64_t* slot_off, int64_t* pair_off,
+                             int64_t* out_off, int32_t* rejected, hipStream_t s);
 hipError_t launch_gather_rows(const float* src, int64_t lds, const int32_t* idx, int64_t n, int dim,
                               float* dst, int64_t ldd, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);

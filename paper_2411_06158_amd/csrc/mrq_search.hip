@@ -290,6 +290,72 @@ __global__ void k_uniform_meta(int64_t nq, int k, int np, int32_t* __restrict__ 
         out_off[q] = q * k;
     }
 }
+// Per-query metadata of a batch whose k[i] / nprobe[i] (and optionally out_off[i]) are device arrays, with
+// upper bounds kb, npb given by the caller: a query whose k is outside [1, kb], nprobe outside [1, npb] or
+// out_off negative is rejected (k = nprobe = 0: no pairs, no output) and counted into *rejected; slot_off
+// and pair_off are the exclusive prefix sums of the accepted k and nprobe (n + 1 entries), out_off the
+// caller's offsets or, when none are given, slot_off.  One block of 1024 threads; thread t takes a
+// contiguous chunk of queries.
+__global__ __launch_bounds__(1024) void k_mixed_meta(int64_t nq, const int32_t* __restrict__ k_in,
+                                                    const int32_t* __restrict__ np_in,
+                                                    const int64_t* __restrict__ oo_in, int kb, int npb,
+                                                    int32_t* __restrict__ kq, int32_t* __restrict__ npq,
+                                                    int64_t* __restrict__ slot_off, int64_t* __restrict__ pair_off,
+                                                    int64_t* __restrict__ out_off, int32_t* __restrict__ rejected) {
+    __shared__ long long ws[16], wp[16];
+    __shared__ int wr[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t per = (nq + 1023) / 1024;
+    const int64_t b = (int64_t)t * per, e = b + per < nq ? b + per : nq;
+    long long sk = 0, sp = 0;
+    int bad = 0;
+    for (int64_t i = b; i < e; i++) {
+        const int k = k_in[i], np = np_in[i];
+        const bool ok = k >= 1 && k <= kb && np >= 1 && np <= npb && (!oo_in || oo_in[i] >= 0);
+        kq[i] = ok ? k : 0;
+        npq[i] = ok ? np : 0;
+        sk += ok ? k : 0;
+        sp += ok ? np : 0;
+        bad += ok ? 0 : 1;
+    }
+    // exclusive scan of the per-thread sums over the block
+    long long ik = sk, ip = sp;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long yk = __shfl_up(ik, o), yp = __shfl_up(ip, o);
+        if (lane >= o) { ik += yk; ip += yp; }
+    }
+    int rb = bad;
+    for (int o = 32; o >= 1; o >>= 1) rb += __shfl_xor(rb, o);
+    if (lane == 63) { ws[w] = ik; wp[w] = ip; }
+    if (lane == 0) wr[w] = rb;
+    __syncthreads();
+    long long bk = 0, bp = 0;
+    for (int i = 0; i < w; i++) { bk += ws[i]; bp += wp[i]; }
+    bk += ik - sk;
+    bp += ip - sp;
+    for (int64_t i = b; i < e; i++) {
+        slot_off[i] = bk;
+        pair_off[i] = bp;
+        out_off[i] = oo_in ? oo_in[i] : bk;
+        bk += kq[i];
+        bp += npq[i];
+    }
+    if (t == 1023) {
+        slot_off[nq] = bk;
+        pair_off[nq] = bp;
+        int tot = 0;
+        for (int i = 0; i < 16; i++) tot += wr[i];
+        if (rejected) *rejected = tot;
+    }
+}
+hipError_t launch_mixed_meta(int64_t nq, const int32_t* k, const int32_t* np, const int64_t* out_off_in, int kb,
+                             int npb, int32_t* kq, int32_t* npq, int64_t* slot_off, int64_t* pair_off,
+                             int64_t* out_off, int32_t* rejected, hipStream_t s) {
+    hipLaunchKernelGGL(k_mixed_meta, dim3(1), dim3(1024), 0, s, nq, k, np, out_off_in, kb, npb, kq, npq, slot_off,
+                       pair_off, out_off, rejected);
+    return hipGetLastError();
+}
+
 hipError_t launch_uniform_meta(int64_t nq, int k, int np, int32_t* kq, int32_t* npq, int64_t* slot_off,
                                int64_t* pair_off, int64_t* out_off, hipStream_t s) {
     hipLaunchKernelGGL(k_uniform_meta, dim3((unsigned)((nq + 256) / 256)), dim3(256), 0, s, nq, k, np, kq, npq,
@@ -790,6 +856,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const float* g = G + (int64_t)q * nlist;
     const int np = npq[q];
+    if (np == 0) return;  // block-uniform
     uint32_t v[V];
 #pragma unroll
     for (int u = 0; u < V; u++) {
@@ -897,6 +964,7 @@ __global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, i
     if (q >= nq) return;
     const float* g = G + q * nlist;
     const int np = npq[q];
+    if (np == 0) return;  // wave-uniform
     uint32_t v[V];
 #pragma unroll
     for (int u = 0; u < V; u++) {
@@ -991,6 +1059,7 @@ __global__ __launch_bounds__(256) void k_select_s(const float* __restrict__ G, i
     if (q >= nq) return;
     const uint32_t* g = reinterpret_cast<const uint32_t*>(G + q * nlist);  // non-negative: patterns order like values
     const int np = npq[q];
+    if (np == 0) return;  // wave-uniform
     const int64_t o = pair_off[q];
     const unsigned long long lt = (1ull << lane) - 1ull;
     uint32_t mn = 0xFFFFFFFFu;
@@ -1092,11 +1161,13 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
 // ------------------------------------------------------------------------------------------------
 // Pair bucketing by (phase, list) and per-pair query codes.
 
+// The pair total is read from the device offsets (pair_total = pair_off + nq): a batch whose per-query
+// k / nprobe live on the device is launched for an upper bound of the pairs.
 __global__ void k_pair_count(const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
-                             const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh,
-                             int32_t* __restrict__ cnt) {
+                             const int64_t* __restrict__ pair_off, const int64_t* __restrict__ pair_total, int nlist,
+                             int sh, int32_t* __restrict__ cnt) {
     int64_t pi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (pi >= npairs) return;
+    if (pi >= *pair_total) return;
     const int q = pair_q[pi];
     const int r = (int)(pi - pair_off[q]);
     atomicAdd(&cnt[phase_of(r, sh) * nlist + pair_list[pi]], 1);
@@ -1302,13 +1373,14 @@ __device__ __forceinline__ void pair_code(int lane, int q, int j, const float* _
 template <int NH, int L, bool TR>
 __global__ __launch_bounds__(256) void k_pair_prep(
     const int32_t* __restrict__ pair_list, const int32_t* __restrict__ pair_q,
-    const int64_t* __restrict__ pair_off, int64_t npairs, int nlist, int sh, const float* __restrict__ rq,
+    const int64_t* __restrict__ pair_off, const int64_t* __restrict__ pair_total, int nlist, int sh,
+    const float* __restrict__ rq,
     const float* __restrict__ RC, int d, int d4, int WP, int bq, float eps0,
     const float* __restrict__ Tq, const float* __restrict__ er, const float* __restrict__ qn2,
     const int32_t* __restrict__ boff, int32_t* __restrict__ fill, int KP,
     PairRec* __restrict__ recs, int8_t* __restrict__ qu8, int32_t* __restrict__ pair_pos, const TraceSink* tr) {
     const int64_t pi = blockIdx.x * (int64_t)(256 / L) + threadIdx.x / L;
-    if (pi >= npairs) return;  // whole groups: the group's shuffles stay among active lanes
+    if (pi >= *pair_total) return;  // whole groups: the group's shuffles stay among active lanes
     const int lane = threadIdx.x & 63;
     const int q = pair_q[pi];
     const int j = pair_list[pi];
@@ -2262,6 +2334,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     extern __shared__ unsigned long long dyn[];  // queue: 2 x k_max keys, kSeedMax candidate keys, query rows
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
+    if (c.npq[q] == 0 || c.kq[q] == 0) return;  // a query without pairs (rejected by the mixed-batch check)
     QueryState st;
     st.tk[0] = dyn;
     st.tk[1] = dyn + c.k_max;
@@ -2393,10 +2466,10 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
 // every pair record of the phase.
 __global__ void k_tau_snap(const unsigned long long* __restrict__ slots, const int64_t* __restrict__ slot_off,
                            const int32_t* __restrict__ kq, const int32_t* __restrict__ boff, int nlist, int phase,
-                           int64_t npairs, PairRec* __restrict__ recs) {
+                           const int64_t* __restrict__ pair_total, PairRec* __restrict__ recs) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t pos = boff[phase * nlist] + i;
-    if (i >= npairs || pos >= boff[(phase + 1) * nlist]) return;
+    if (i >= *pair_total || pos >= boff[(phase + 1) * nlist]) return;
     const int q = recs[pos].q;
     const unsigned long long v = slots[slot_off[q] + kq[q] - 1];
     recs[pos].tau = v == kEmptyKey ? INFINITY : __uint_as_float((uint32_t)(v >> 32));
@@ -3235,28 +3308,36 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     // Without a fork (the allocation-free search) the seed pass runs first on the search stream.
     HIP_TRY(fill_u64(w.slots, kEmptyKey, a.total_slots, s));
     HIP_TRY(launch_fill_i32(w.qcnt, 0, nq, s));
+    // The fork's stream and events are the caller's (a server slot's) or the index's own.
+    hipStream_t aux = a.aux;
+    hipEvent_t ev_fork = a.ev_fork, ev_join = a.ev_join;
     if (a.fork_seed) {
-        if (!ix.aux) {
-            HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
-            HIP_TRY(hipEventCreateWithFlags(&ix.ev_join, hipEventDisableTiming));
+        if (!aux) {
+            if (!ix.aux) {
+                HIP_TRY(hipStreamCreateWithFlags(&ix.aux, hipStreamNonBlocking));
+                HIP_TRY(hipEventCreateWithFlags(&ix.ev_fork, hipEventDisableTiming));
+                HIP_TRY(hipEventCreateWithFlags(&ix.ev_join, hipEventDisableTiming));
+            }
+            aux = ix.aux;
+            ev_fork = ix.ev_fork;
+            ev_join = ix.ev_join;
         }
-        HIP_TRY(hipEventRecord(ix.ev_fork, s));
-        HIP_TRY(hipStreamWaitEvent(ix.aux, ix.ev_fork, 0));
+        HIP_TRY(hipEventRecord(ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(aux, ev_fork, 0));
     }
-    const hipStream_t seed_s = a.fork_seed ? ix.aux : s;
+    const hipStream_t seed_s = a.fork_seed ? aux : s;
     {
         Timed t(tm, seed_s, "seed");
         launch_seed(c, nq, seed_s);
         HIP_TRY(hipGetLastError());
     }
-    if (a.fork_seed) HIP_TRY(hipEventRecord(ix.ev_join, ix.aux));
+    if (a.fork_seed) HIP_TRY(hipEventRecord(ev_join, aux));
     {   // per-pair query codes, grouped by (phase, list)
         Timed t(tm, s, "pair_prep");
         HIP_TRY(launch_fill_i32(w.cnt, 0, P, s));
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
-                           w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift, w.cnt);
+                           w.pair_list, w.pair_q, a.pair_off, a.pair_off + nq, nlist, a.phase_shift, w.cnt);
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
         const int nh = (d + 63) / 64;
         const int KP = level_bytes(d);
@@ -3264,7 +3345,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         // and atomic), a whole wave beyond
 #define PREP_T(NHV, LV, TRV)                                                                                \
     hipLaunchKernelGGL((k_pair_prep<NHV, LV, TRV>), dim3((unsigned)((a.total_pairs + 256 / LV - 1) / (256 / LV))), \
-                       dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.total_pairs, nlist, a.phase_shift,  \
+                       dim3(256), 0, s, w.pair_list, w.pair_q, a.pair_off, a.pair_off + nq, nlist, a.phase_shift, \
                        w.rq, ix.RC, d, d4, ix.WP, a.bq, a.eps0, w.Tq, w.er, w.qn2, w.boff, w.fill, KP, w.recs,  \
                        w.qu8, w.pair_pos, a.trace)
 #define PREP(NHV, LV)                     \
@@ -3287,14 +3368,14 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
                            ix.list_off, nlist, G, P, w.desc);
         HIP_TRY(hipGetLastError());
     }
-    if (a.fork_seed) HIP_TRY(hipStreamWaitEvent(s, ix.ev_join, 0));
+    if (a.fork_seed) HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
     for (int p = 1; p < kPhases; p++) {
         if (a.np_max <= phase_lo(p, a.phase_shift)) break;
         c.phase = p;
         {
             Timed t(tm, s, "tau");
             hipLaunchKernelGGL(k_tau_snap, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
-                               w.slots, a.slot_off, a.kq, w.boff, nlist, p, a.total_pairs, w.recs);
+                               w.slots, a.slot_off, a.kq, w.boff, nlist, p, a.pair_off + nq, w.recs);
         }
         {
             Timed t(tm, s, "scan");

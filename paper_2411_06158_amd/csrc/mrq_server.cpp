@@ -1,14 +1,17 @@
 // Continuous-batching request loop on top of the batched search (serving entry points of mrq.h).
 //
-// A host worker thread owns two batch slots, each with its own HIP stream, pinned staging buffers and
-// device workspace.  Requests wait in a FIFO until a slot is free; the worker then admits requests in
-// arrival order while the slot has room (max_slots queries) and the device memory of the batch
-// (workspace + staging, sized for the admitted mix of k and nprobe) fits the budget left by the
-// other slot.  The batch is copied to the device, searched with per-query k / nprobe, and copied
-// back on the slot's stream; the worker polls the slot's event and hands finished rows to
-// mrq_server_poll.  With two slots one batch is packed and launched while the other is still running.
-// Search results do not depend on the batch a query is in, so a request returns the same ids and
-// distances alone and in any mix.
+// A host worker thread owns two batch slots, each with its own HIP stream, its own auxiliary stream and
+// events for the search's seed-pass fork, pinned staging buffers and a device buffer.  Requests wait in a
+// FIFO until a slot is free; the worker then admits requests in arrival order while the slot has room
+// (max_slots queries) and the device memory of the batch (workspace + staging, sized for the admitted mix
+// of k and nprobe) fits the slot's buffer.  With a memory budget each slot's buffer is half of it,
+// allocated when the server is created, so the server's device memory never exceeds the budget and
+// nothing is allocated or freed while batches run (a free would synchronise the device and stall the
+// other slot).  The batch is copied to the device, searched with per-query k / nprobe, and copied back on
+// the slot's stream; the worker polls the slot's event and hands finished rows to mrq_server_poll.  With
+// two slots one batch is packed and launched while the other is still running.  Search results do not
+// depend on the batch a query is in, so a request returns the same ids and distances alone and in any mix.
+// The server shares only the index's read-only arrays: the index may be searched directly meanwhile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,6 +65,8 @@ struct Pinned {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done_ev = nullptr;
+    hipStream_t aux = nullptr;                     // the seed pass of this slot's searches
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool busy = false;
     std::vector<Request> reqs;
     std::vector<int64_t> out_off;
@@ -91,6 +96,11 @@ struct mrq_server {
     std::string error;
     Slot slots[2];
     std::thread worker;
+    std::vector<void*> retired;          // outgrown slot buffers (no budget), freed with the server
+    std::atomic<int64_t> dev_bytes{0};   // device bytes the server holds
+    std::atomic<int64_t> dev_peak{0};
+    std::atomic<int64_t> batches{0};
+    std::atomic<int32_t> max_in_flight{0};
 };
 
 namespace {
@@ -119,11 +129,17 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
     }
     const size_t need = batch_bytes(ix, nq, tslots, tpairs, np_max, sv->opts);
     if (sl.dev_bytes < need) {
-        if (sl.dev) (void)hipFree(sl.dev);
-        sl.dev = nullptr;
-        sl.dev_bytes = 0;
-        if (hipMalloc(&sl.dev, need + need / 4) != hipSuccess) return false;
+        // only without a budget (a budgeted slot's buffer is allocated at creation and admission keeps the
+        // batch within it); the old buffer is kept until the server ends, as freeing it would synchronise
+        if (sv->budget) return false;
+        void* nb = nullptr;
+        if (hipMalloc(&nb, need + need / 4) != hipSuccess) return false;
+        if (sl.dev) sv->retired.push_back(sl.dev);
+        sl.dev = nb;
         sl.dev_bytes = need + need / 4;
+        const int64_t tot = sv->dev_bytes += (int64_t)sl.dev_bytes;
+        int64_t pk = sv->dev_peak.load();
+        while (tot > pk && !sv->dev_peak.compare_exchange_weak(pk, tot)) {}
     }
     sl.reserved = need;
     // carve the device buffer
@@ -143,7 +159,7 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
     const size_t meta_bytes = nq * 4 * 2 + (nq + 1) * 8 * 2 + nq * 8;
     if (!sl.h_meta.reserve(meta_bytes) || !sl.h_q.reserve(nq * (size_t)ix.D) || !sl.h_ids.reserve(tslots) ||
         !sl.h_d.reserve(tslots))
-        return false;
+        return false;  // sized for max_slots at creation: only grows when that failed
     int32_t* h_kq = reinterpret_cast<int32_t*>(sl.h_meta.p);
     int32_t* h_np = h_kq + nq;
     int64_t* h_so = reinterpret_cast<int64_t*>(h_np + nq);
@@ -196,11 +212,18 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
     a.dists = d_d;
     a.counters = nullptr;
     a.timed = false;
+    a.aux = sl.aux;
+    a.ev_fork = sl.ev_fork;
+    a.ev_join = sl.ev_join;
     if (mrq::launch_search(a, ws, ws_bytes, s) != hipSuccess) return false;
     if (hipMemcpyAsync(sl.h_ids.p, d_ids, tslots * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
     if (hipMemcpyAsync(sl.h_d.p, d_d, tslots * 4, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
     if (hipEventRecord(sl.done_ev, s) != hipSuccess) return false;
     sl.busy = true;
+    sv->batches++;
+    const int32_t now = (int32_t)sv->slots[0].busy + (int32_t)sv->slots[1].busy;
+    int32_t m = sv->max_in_flight.load();
+    while (now > m && !sv->max_in_flight.compare_exchange_weak(m, now)) {}
     return true;
 }
 
@@ -242,7 +265,7 @@ void worker_loop(mrq_server* sv) {
         for (int si = 0; si < 2; si++) {
             Slot& sl = sv->slots[si];
             if (sl.busy) continue;
-            const size_t other = sv->slots[si ^ 1].busy ? sv->slots[si ^ 1].reserved : 0;
+            const size_t cap = sv->budget ? sl.dev_bytes : 0;  // a budgeted slot's fixed buffer
             {
                 std::lock_guard<std::mutex> lk(sv->mu);
                 int64_t tslots = 0, tpairs = 0;
@@ -252,7 +275,7 @@ void worker_loop(mrq_server* sv) {
                     const int np2 = std::max(np_max, r.nprobe);
                     const size_t need = batch_bytes(*sv->core, (int64_t)sl.reqs.size() + 1, tslots + r.k,
                                                     tpairs + r.nprobe, np2, sv->opts);
-                    if (sv->budget && need + other > sv->budget) break;  // admit later, when memory frees up
+                    if (cap && need > cap) break;  // admit later, in the next batch of a slot
                     tslots += r.k;
                     tpairs += r.nprobe;
                     np_max = np2;
@@ -323,13 +346,35 @@ mrq_status mrq_server_create(const mrq_index* index, size_t mem_budget, int32_t 
     if (sv->opts.phase_growth != 0 && sv->opts.phase_growth != 2 && sv->opts.phase_growth != 4 &&
         sv->opts.phase_growth != 8) { delete sv; return MRQ_EINVAL; }
     (void)hipSetDevice(sv->core->device);
+    const mrq::Index& ix = *sv->core;
     for (Slot& sl : sv->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&sl.aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.ev_join, hipEventDisableTiming) != hipSuccess) {
             mrq_server_destroy(sv);
             return MRQ_EDEVICE;
         }
+        // pinned staging for a full batch of the largest requests
+        const size_t ms = (size_t)max_slots;
+        if (!sl.h_meta.reserve(ms * 4 * 2 + (ms + 1) * 8 * 2 + ms * 8) || !sl.h_q.reserve(ms * (size_t)ix.D) ||
+            !sl.h_ids.reserve(ms * mrq::kMaxK) || !sl.h_d.reserve(ms * mrq::kMaxK)) {
+            mrq_server_destroy(sv);
+            return MRQ_ENOMEM;
+        }
+        if (sv->budget) {  // each slot holds half of the budget for the server's lifetime
+            sl.dev_bytes = (sv->budget / 2) & ~(size_t)255;
+            if (hipMalloc(&sl.dev, std::max<size_t>(sl.dev_bytes, 256)) != hipSuccess) {
+                sl.dev = nullptr;
+                sl.dev_bytes = 0;
+                mrq_server_destroy(sv);
+                return MRQ_ENOMEM;
+            }
+            sv->dev_bytes += (int64_t)sl.dev_bytes;
+        }
     }
+    sv->dev_peak = sv->dev_bytes.load();
     sv->worker = std::thread(worker_loop, sv);
     *out = sv;
     return MRQ_OK;
@@ -340,7 +385,7 @@ mrq_status mrq_server_submit(mrq_server* sv, uint64_t req_id, const float* q_hos
     const mrq::Index& ix = *sv->core;
     if (k < 1 || k > mrq::kMaxK || nprobe < 1 || nprobe > std::min(ix.nlist, mrq::kMaxProbe)) return MRQ_EINVAL;
     if (sv->opts.method == MRQ_METHOD_MRSQ && k > sv->opts.rerank) return MRQ_EINVAL;
-    if (sv->budget && batch_bytes(ix, 1, k, nprobe, nprobe, sv->opts) > sv->budget) return MRQ_ENOMEM;
+    if (sv->budget && batch_bytes(ix, 1, k, nprobe, nprobe, sv->opts) > sv->slots[0].dev_bytes) return MRQ_ENOMEM;
     Request r;
     r.id = req_id;
     r.k = k;
@@ -393,11 +438,28 @@ void mrq_server_destroy(mrq_server* sv) {
     if (sv->worker.joinable()) sv->worker.join();
     for (Slot& sl : sv->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.aux) (void)hipStreamSynchronize(sl.aux);
+    }
+    for (Slot& sl : sv->slots) {
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
+        if (sl.ev_fork) (void)hipEventDestroy(sl.ev_fork);
+        if (sl.ev_join) (void)hipEventDestroy(sl.ev_join);
+        if (sl.aux) (void)hipStreamDestroy(sl.aux);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    for (void* p : sv->retired) (void)hipFree(p);
     delete sv;
+}
+
+mrq_status mrq_server_stats(const mrq_server* sv, int64_t* device_bytes, int64_t* peak_device_bytes,
+                            int64_t* batches, int32_t* max_in_flight) {
+    if (!sv) return MRQ_EINVAL;
+    if (device_bytes) *device_bytes = sv->dev_bytes.load();
+    if (peak_device_bytes) *peak_device_bytes = sv->dev_peak.load();
+    if (batches) *batches = sv->batches.load();
+    if (max_in_flight) *max_in_flight = sv->max_in_flight.load();
+    return MRQ_OK;
 }
 
 }  // extern "C"

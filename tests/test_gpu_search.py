@@ -175,6 +175,74 @@ def test_mixed_k_nprobe(small):
     assert_rows(st, "mixed k / nprobe")
 
 
+def test_mixed_batch_on_the_device(small):
+    """Per-query k / nprobe as device arrays (mrq_search_mixed_dev): the same rows as the host-metadata mixed
+    search; entries outside the bounds are rejected and counted, the other rows are unchanged."""
+    rng = np.random.default_rng(11)
+    n = small["Q"].shape[0]
+    ks = rng.integers(1, 40, n).astype(np.int32)
+    nps = rng.integers(1, 20, n).astype(np.int32)
+    ids, dists, off = small["ix"].search_mixed(small["Qd"], ks, nps)
+    tot = int(ks.sum())
+    kd, npd = torch.from_numpy(ks).cuda(), torch.from_numpy(nps).cuda()
+    ib = torch.full((tot,), -7, dtype=torch.int64, device="cuda")
+    db = torch.full((tot,), -7.0, dtype=torch.float32, device="cuda")
+    rej = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    small["ix"].search_mixed_dev(small["Qd"], kd, npd, 40, 20, ib, db, rejected=rej)
+    torch.cuda.synchronize()
+    assert int(rej.item()) == 0
+    assert np.array_equal(ib.cpu().numpy(), ids)
+    assert np.array_equal(db.cpu().numpy().view(np.uint32), dists.view(np.uint32))
+    # two bad entries: k = 0 and nprobe above the bound; rows at the caller's offsets
+    ks2, nps2 = ks.copy(), nps.copy()
+    ks2[3], nps2[5] = 0, 21
+    offd = torch.from_numpy(off).cuda()
+    ib.fill_(-7)
+    db.fill_(-7.0)
+    small["ix"].search_mixed_dev(small["Qd"], torch.from_numpy(ks2).cuda(), torch.from_numpy(nps2).cuda(), 40, 20,
+                                 ib, db, out_off=offd, rejected=rej)
+    torch.cuda.synchronize()
+    assert int(rej.item()) == 2
+    ih, dh = ib.cpu().numpy(), db.cpu().numpy()
+    for i in range(n):
+        sl = slice(int(off[i]), int(off[i] + ks[i]))
+        if i in (3, 5):
+            assert np.all(ih[sl] == -7)
+        else:
+            assert np.array_equal(ih[sl], ids[sl]) and np.array_equal(dh[sl].view(np.uint32), dists[sl].view(np.uint32))
+
+
+def test_mixed_batch_replays_from_a_captured_graph(small):
+    """A device-side mixed batch recorded into a HIP graph gives the eager rows on every replay, with eager
+    searches between the replays."""
+    rng = np.random.default_rng(12)
+    Qd = small["Qd"]
+    n = Qd.shape[0]
+    ks = torch.from_numpy(rng.integers(1, 30, n).astype(np.int32)).cuda()
+    nps = torch.from_numpy(rng.integers(1, 16, n).astype(np.int32)).cuda()
+    tot = int(ks.sum().item())
+    ib = torch.empty((tot,), dtype=torch.int64, device="cuda")
+    db = torch.empty((tot,), dtype=torch.float32, device="cuda")
+    opts = mrq.search_opts(group=16, phase_growth=4)
+    s = torch.cuda.Stream()
+    small["ix"].search_mixed_dev(Qd, ks, nps, 30, 16, ib, db, opts=opts, stream=s)  # sizes the workspace
+    torch.cuda.synchronize()
+    ref_i, ref_d = ib.clone(), db.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        small["ix"].search_mixed_dev(Qd, ks, nps, 30, 16, ib, db, opts=opts, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        ib.fill_(-7)
+        db.fill_(-1.0)
+        small["ix"].search(Qd[:6 + rep].contiguous(), 5, 4, opts=opts)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ib, ref_i), rep
+        assert torch.equal(db.view(torch.int32), ref_d.view(torch.int32)), rep
+
+
 @pytest.mark.parametrize("nlist", [256, 1500, 5000])
 def test_probe_selection_kernels_agree(nlist):
     """Batches whose largest nprobe is at most 64 rank the lists one wave per query, larger ones one block

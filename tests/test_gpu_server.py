@@ -70,6 +70,36 @@ def test_server_results_equal_search_alone(env):
     print(f"[gpu] server latency p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms", flush=True)
 
 
+def _stats(srv):
+    L = mrq.lib()
+    cur, peak, nb = C.c_int64(), C.c_int64(), C.c_int64()
+    inflight = C.c_int32()
+    assert L.mrq_server_stats(srv, C.byref(cur), C.byref(peak), C.byref(nb), C.byref(inflight)) == mrq.MRQ_OK
+    return cur.value, peak.value, nb.value, inflight.value
+
+
+def test_budget_bounds_device_memory_and_slots_overlap(env):
+    """With a budget the server holds exactly it (half per slot, allocated at creation) and never more; a
+    burst of requests keeps both slots' batches on the device at once."""
+    L = mrq.lib()
+    srv = C.c_void_p()
+    budget = 64 << 20
+    assert L.mrq_server_create(env["ix"]._h, budget, 32, None, C.byref(srv)) == mrq.MRQ_OK
+    try:
+        n = env["Q"].shape[0]
+        for i in range(n):
+            q = np.ascontiguousarray(env["Q"][i])
+            assert L.mrq_server_submit(srv, i, q.ctypes.data, 100, 16) == mrq.MRQ_OK
+        assert L.mrq_server_drain(srv, 60_000) == mrq.MRQ_OK
+        cur, peak, nb, inflight = _stats(srv)
+        print(f"[gpu] server stats: bytes {cur} peak {peak} batches {nb} max in flight {inflight}", flush=True)
+        assert peak <= budget and cur <= budget
+        assert nb >= (n + 31) // 32
+        assert inflight == 2
+    finally:
+        L.mrq_server_destroy(srv)
+
+
 def test_memory_admission_defers_requests(env):
     n = 40
     ks = np.full(n, 10, np.int32)
@@ -82,7 +112,7 @@ def test_memory_admission_defers_requests(env):
     assert L.mrq_server_submit(probe, 0, q.ctypes.data, 10, 8) == mrq.MRQ_ENOMEM   # can never fit 1 byte
     assert L.mrq_server_submit(probe, 0, q.ctypes.data, 0, 8) == mrq.MRQ_EINVAL
     L.mrq_server_destroy(probe)
-    rid, kk, ids, dd, lat = _serve(env["ix"], env["Q"][:n], ks, nps, budget=3 << 20, max_slots=64)
+    rid, kk, ids, dd, lat = _serve(env["ix"], env["Q"][:n], ks, nps, budget=6 << 20, max_slots=64)
     for j in range(n):
         i = int(rid[j])
         a, _ = env["ix"].search(env["Q"][i:i + 1].copy(), 10, 8)
