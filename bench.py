@@ -467,6 +467,8 @@ def main():
                     help="probe-rank phase growth (2, 4 or 8); with --group skips the autotuner")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--c4", action="store_true",
+                    help="one hipGraph-captured launch of a 20k-query mixed k / nprobe batch (embedding-shaped index)")
     ap.add_argument("--serve", action="store_true",
                     help="serving benchmark instead: Poisson arrivals on the embedding-shaped index")
     ap.add_argument("--rates", default="5000,10000,20000,50000", help="--serve: arrival rates (queries/s)")
@@ -497,6 +499,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.serve:
         serve_main(args, np, torch, mrq, synth, dev)
+        return
+    if args.c4:
+        c4_main(args, np, torch, mrq, synth, dev)
         return
     if args.sweep_d:
         if not args.nlist:
@@ -667,6 +672,78 @@ def mrsq_main(args, np, torch, mrq, synth, dev):
                       "config": {"workload": f"{args.workload}: N={N} D={D} nq={nq} nlist={args.nlist} k={k}",
                                  "steps": args.steps, "rerank": R},
                       "rows": rows}), flush=True)
+
+
+def c4_main(args, np, torch, mrq, synth, dev):
+    """One hipGraph-captured launch of a mixed batch: the embedding-shaped index (N = 2,000,000, D = 1,536,
+    d_r = 256, 4-bit codes, nlist = 4,096) and its 20,000 queries, each with its own k ~ U{10..100} and
+    nprobe ~ U{8..64} (seeded), searched by mrq_search_mixed_dev (per-query k / nprobe on the device).  Times
+    K graph replays (and K eager calls) between synchronisations; reports queries/s, the replays' agreement
+    with the eager rows, and recall@10 of each query's first 10 results against exact brute force."""
+    t0 = time.time()
+    X, Q, _ = synth.workload("openai2m")
+    nq = Q.shape[0]
+    log(f"c4: data {X.shape[0]}x{X.shape[1]}, {nq} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    t1 = time.time()
+    ix = mrq.Index.build(Xd, d_r=256, bits=4, nlist=4096)
+    log(f"c4: build {time.time() - t1:.1f}s, index {ix.device_bytes / 2**30:.2f} GiB")
+    gt = ground_truth(torch, Xd, Qd, 10)
+    del Xd
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(4004)
+    ks = rng.integers(10, 101, nq).astype(np.int32)
+    nps = rng.integers(8, 65, nq).astype(np.int32)
+    off = np.zeros(nq, np.int64)
+    off[1:] = np.cumsum(ks[:-1].astype(np.int64))
+    tot = int(ks.sum())
+    kd, npd = torch.from_numpy(ks).to(dev), torch.from_numpy(nps).to(dev)
+    ib = torch.empty(tot, dtype=torch.int64, device=dev)
+    db = torch.empty(tot, dtype=torch.float32, device=dev)
+    group, growth = ix.tune(Qd, 50, 32)
+    log(f"c4: autotuned query group {group}, phase growth {growth} (k 50, nprobe 32)")
+    opts = mrq.search_opts(group=group, phase_growth=growth)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ix.search_mixed_dev(Qd, kd, npd, 100, 64, ib, db, opts=opts, stream=s)  # sizes the workspace
+    torch.cuda.synchronize()
+    ref_i, ref_d = ib.clone(), db.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s, capture_error_mode="thread_local"):
+        ix.search_mixed_dev(Qd, kd, npd, 100, 64, ib, db, opts=opts, stream=s)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el_graph = time.perf_counter() - ts
+    same = bool(torch.equal(ib, ref_i)) and bool(torch.equal(db.view(torch.int32), ref_d.view(torch.int32)))
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        ix.search_mixed_dev(Qd, kd, npd, 100, 64, ib, db, opts=opts, stream=s)
+    torch.cuda.synchronize()
+    el_eager = time.perf_counter() - ts
+    ih = ib.cpu().numpy()
+    hit = sum(len(set(ih[off[i]:off[i] + 10].tolist()) & set(gt[i, :10].tolist())) for i in range(nq))
+    rec = hit / (10.0 * nq)
+    qps = nq * args.steps / el_graph
+    log(f"c4: graph replay {qps:,.0f} QPS ({1e3 * el_graph / args.steps:.2f} ms), eager "
+        f"{nq * args.steps / el_eager:,.0f} QPS, replay rows equal eager: {same}, recall@10 {rec:.4f}")
+    print(json.dumps({"metric": "QPS of one hipGraph-captured mixed-k/nprobe launch (1 GPU)", "value": round(qps, 1),
+                      "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(1e3 * el_graph / args.steps, 4), "higher_is_better": True,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "openai2m: N=2000000 D=1536 nq=20000 nlist=4096 d_r=256 bits=4, "
+                                             "k ~ U{10..100}, nprobe ~ U{8..64} per query",
+                                 "query_group": group, "phase_growth": growth},
+                      "eager_qps": round(nq * args.steps / el_eager, 1), "replay_equals_eager": same,
+                      "recall_at_10": round(rec, 4), "mean_k": round(float(ks.mean()), 2),
+                      "mean_nprobe": round(float(nps.mean()), 2)}), flush=True)
+    ix.close()
 
 
 def serve_main(args, np, torch, mrq, synth, dev):
