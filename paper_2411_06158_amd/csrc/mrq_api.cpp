@@ -169,6 +169,15 @@ std::vector<double> haar_rotation(int d, uint64_t seed) {
     return Q;
 }
 
+// The split exact stage (||x - q||^2 = dis_o' - 2 <x_r, q_r>, Section 5.2's separate leading and tail
+// blocks) is taken when the tail is no wider than the leading block: its exact stage then reads at most half
+// of a row, and the query's tail coordinates, now needed in FP32, cost at most as much as the leading ones.
+void set_split(Index& ix) {
+    ix.Dr = ix.D - ix.d;
+    ix.split = ix.Dr <= ix.d;
+    ix.Dr4 = ix.split ? (ix.Dr + 3) & ~3 : 0;
+}
+
 void check_args_build(const float* X, int64_t N, int32_t D, int32_t d, int32_t B, int32_t nlist) {
     if (!X) throw Fail(MRQ_EINVAL, "X is NULL");
     if (N < 1 || N >= (int64_t)0x7fffffff) throw Fail(MRQ_EINVAL, "N must be in [1, 2^31 - 1)");
@@ -292,6 +301,7 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     ix->W = (d + 31) / 32;
     ix->WP = padded_words(d);
     ix->d4 = (d + 3) & ~3;
+    set_split(*ix);
     const int d4 = ix->d4;
     {
         std::vector<float> Pp32(V.begin(), V.end()), mu32(muh.begin(), muh.end());
@@ -435,6 +445,7 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     ix->xd = dalloc<float>(ix.get(), Np * d4);
     ix->ax = dalloc<float>(ix.get(), Np);
     ix->X = dalloc<float>(ix.get(), Np * ix->D4);
+    if (ix->split && ix->Dr4 > 0) ix->xr = dalloc<float>(ix.get(), Np * ix->Dr4);
     ix->nx = dalloc<float>(ix.get(), Np);
     ix->tx = dalloc<float>(ix.get(), Np);
     ix->xi1 = dalloc<float>(ix.get(), Np);
@@ -443,7 +454,8 @@ static mrq_index* build_index(const float* X, int64_t N, int32_t D, int32_t d, i
     DevTemp O(sizeof(float) * Np * d4), Xpp(sizeof(float) * Np * d4), txr(sizeof(double) * Np),
         rowl(sizeof(int32_t) * Np);
     hip_check(launch_gather_layout(*ix, Xd, permd.as<int32_t>(), xd_id.as<float>(), ax64.as<double>(),
-                                   tx64.as<double>(), txr.as<double>(), rowl.as<int32_t>(), O.as<float>(), s),
+                                   tx64.as<double>(), txr.as<double>(), rowl.as<int32_t>(), O.as<float>(),
+                                   xt_id.as<float>(), s),
               "layout");
 
     // random rotation P_r and the codes
@@ -804,6 +816,7 @@ std::vector<ArrayRef> device_arrays(Index& ix) {
         {(void**)&ix.xd, sizeof(float) * Np * d4},
         {(void**)&ix.ax, sizeof(float) * Np},
         {(void**)&ix.X, sizeof(float) * Np * ix.D4},
+        {(void**)&ix.xr, ix.split && ix.Dr4 > 0 ? sizeof(float) * Np * ix.Dr4 : 0},
         {(void**)&ix.nx, sizeof(float) * Np},
         {(void**)&ix.tx, sizeof(float) * Np},
         {(void**)&ix.xi1, sizeof(float) * Np},
@@ -1148,7 +1161,7 @@ mrq_status mrq_save(const mrq_index* cix, const char* path) {
         mrq_index* ix = const_cast<mrq_index*>(cix);
         hip_check(hipDeviceSynchronize(), "sync");
         File f(path, "wb");
-        f.w("MRQS0004", 8);
+        f.w("MRQS0005", 8);
         int64_t h64[2] = {ix->N, ix->Npad};
         int32_t h32[7] = {ix->D, ix->d, ix->B, ix->nlist, ix->WP, ix->max_list_len, ix->dq};
         f.w(h64, sizeof(h64));
@@ -1159,6 +1172,7 @@ mrq_status mrq_save(const mrq_index* cix, const char* path) {
         std::vector<ArrayRef> arrays = device_arrays(*ix), sq = sq8_arrays(*ix);
         arrays.insert(arrays.end(), sq.begin(), sq.end());
         for (auto& a : arrays) {
+            if (!a.bytes) continue;  // an array this index does not have
             std::vector<char> h(a.bytes);
             hip_check(hipMemcpy(h.data(), *a.p, a.bytes, hipMemcpyDeviceToHost), "download");
             f.w(h.data(), a.bytes);
@@ -1173,7 +1187,7 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         File f(path, "rb");
         char magic[8];
         f.r(magic, 8);
-        if (std::memcmp(magic, "MRQS0004", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0004 file");
+        if (std::memcmp(magic, "MRQS0005", 8) != 0) throw Fail(MRQ_EIO, "not an MRQS0005 file");
         std::unique_ptr<mrq_index> ix(new mrq_index());
         hip_check(hipGetDevice(&ix->device), "hipGetDevice");
         int64_t h64[2];
@@ -1195,6 +1209,7 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         ix->W = (ix->d + 31) / 32;
         ix->d4 = (ix->d + 3) & ~3;
         ix->D4 = (ix->D + 3) & ~3;
+        set_split(*ix);
         ix->lam64.resize(ix->D);
         f.r(ix->lam64.data(), sizeof(double) * ix->D);
         ix->h_off_real.resize(ix->nlist + 1);
@@ -1204,6 +1219,7 @@ mrq_status mrq_load(const char* path, mrq_index** out) {
         std::vector<ArrayRef> arrays = device_arrays(*ix), sq = sq8_arrays(*ix);
         arrays.insert(arrays.end(), sq.begin(), sq.end());
         for (auto& a : arrays) {
+            if (!a.bytes) continue;
             std::vector<char> h(a.bytes);
             f.r(h.data(), a.bytes);
             void* p = nullptr;

@@ -325,7 +325,8 @@ __global__ __launch_bounds__(256) void k_gather_layout(
     const float* __restrict__ xd_id, int d, int d4, const double* __restrict__ ax64,
     const double* __restrict__ tx64, const int64_t* __restrict__ list_off, int nlist,
     const float* __restrict__ C, float* __restrict__ Xl, float* __restrict__ xdl, float* __restrict__ axl,
-    double* __restrict__ txr, int32_t* __restrict__ ids, int32_t* __restrict__ row_list, float* __restrict__ O) {
+    double* __restrict__ txr, int32_t* __restrict__ ids, int32_t* __restrict__ row_list, float* __restrict__ O,
+    const float* __restrict__ xt_id, int Dr, int Dr4, float* __restrict__ xrl) {
     const int64_t r = blockIdx.x * 4ll + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (r >= Npad) return;
@@ -339,6 +340,9 @@ __global__ __launch_bounds__(256) void k_gather_layout(
     // the original vector, zero padded to D4 (the exact stage computes ||x - q||^2 = ||x_p - q_p||^2 from
     // it, so no projection rounding enters the exact distances)
     for (int i = lane; i < D4; i += 64) Xl[r * D4 + i] = (id >= 0 && i < D) ? Xraw[(int64_t)id * D + i] : 0.f;
+    // the tail coordinates of x_p (split exact stage), zero padded to Dr4
+    if (xrl)
+        for (int i = lane; i < Dr4; i += 64) xrl[r * Dr4 + i] = (id >= 0 && i < Dr) ? xt_id[(int64_t)id * Dr + i] : 0.f;
     for (int i = lane; i < d4; i += 64) {
         float v = (id >= 0 && i < d) ? xd_id[(int64_t)id * d4 + i] : 0.f;
         xdl[r * d4 + i] = v;
@@ -354,10 +358,10 @@ __global__ __launch_bounds__(256) void k_gather_layout(
 
 hipError_t launch_gather_layout(const Index& ix, const float* Xraw, const int32_t* perm, const float* xd_id,
                                 const double* ax64, const double* tx64, double* txr, int32_t* row_list, float* O,
-                                hipStream_t s) {
+                                const float* xt_id, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_layout, dim3((unsigned)((ix.Npad + 3) / 4)), dim3(256), 0, s, Xraw, ix.D, ix.D4,
                        perm, ix.Npad, xd_id, ix.d, ix.d4, ax64, tx64, ix.list_off, ix.nlist, ix.C, ix.X, ix.xd,
-                       ix.ax, txr, ix.ids, row_list, O);
+                       ix.ax, txr, ix.ids, row_list, O, xt_id, ix.Dr, ix.Dr4, ix.xr);
     return hipGetLastError();
 }
 

@@ -96,6 +96,12 @@ struct Index {
     float* xd = nullptr;         // Npad x d4 leading coordinates of x_p
     float* ax = nullptr;         // Npad: ||x - mu||^2
     float* X = nullptr;          // Npad x D4 original vectors (zero padded), list order: the exact stage
+    // split exact stage (when the tail is no wider than the leading block, D - d <= d): the exact distance
+    // is the stage-2 value minus twice the tail product, ||x - q||^2 = dis_o' - 2 <x_r, q_r>, so stage 3
+    // reads only the tail coordinates (d = D: nothing)
+    bool split = false;
+    int32_t Dr = 0, Dr4 = 0;     // tail width D - d and its padding to a multiple of 4
+    float* xr = nullptr;         // Npad x Dr4 tail coordinates of x_p (zero padded), list order
     // export-only per-row summaries (list order)
     float *nx = nullptr, *tx = nullptr, *xi1 = nullptr, *xiB = nullptr, *yn = nullptr;
     // MR-SQ codes (built on request): dq = 16 ceil(d / 16) (0 = none); per coordinate the grid lo / delta
@@ -212,7 +218,7 @@ hipError_t launch_kmeans_centroids(const double* sums, const int32_t* cnt, int k
 hipError_t launch_sqnorms(const float* A, int64_t n, int lda, int dim, float* out, hipStream_t s);
 hipError_t launch_gather_layout(const Index& ix, const float* Xraw, const int32_t* perm,
                                 const float* xd_id, const double* ax64, const double* tx64, double* txr,
-                                int32_t* row_list, float* O, hipStream_t s);
+                                int32_t* row_list, float* O, const float* xt_id, hipStream_t s);
 hipError_t launch_encode(const Index& ix, const float* O, const float* Xpp, const double* tx64_rows,
                          hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);

@@ -86,9 +86,19 @@ __device__ __forceinline__ void acc_sqdiff(float& s, const float4& a, const floa
     t = a.z - b.z; s = fmaf(t, t, s);
     t = a.w - b.w; s = fmaf(t, t, s);
 }
-__device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, const float* __restrict__ q,
-                                                  int D4, int l16) {
-    const int nc = D4 >> 2;  // float4 chunks per row
+// Split exact stage: <x_r, q_r> of zero-padded tail rows (Dr4 floats), the same group layout and chunk order;
+// the exact distance is then fmaf(-2, <x_r, q_r>, dis_o').
+__device__ __forceinline__ void acc_dot4(float& s, const float4& a, const float4& b) {
+    s = fmaf(a.x, b.x, s);
+    s = fmaf(a.y, b.y, s);
+    s = fmaf(a.z, b.z, s);
+    s = fmaf(a.w, b.w, s);
+}
+// One routine for both terms (dot = false: squared differences, true: products), so a kernel that may compute
+// either holds one set of row registers.
+__device__ __forceinline__ float row_group(const float* __restrict__ x, const float* __restrict__ q, int n4x4,
+                                           int l16, bool dot) {
+    const int nc = n4x4 >> 2;  // float4 chunks per row
     const float4* __restrict__ xa = reinterpret_cast<const float4*>(x);
     const float4* __restrict__ qa = reinterpret_cast<const float4*>(q);
     float s = 0.f;
@@ -103,7 +113,8 @@ __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, c
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             if (base + 16 * u + l16 >= nc) break;
-            acc_sqdiff(s, a[u], b[u]);
+            if (dot) acc_dot4(s, a[u], b[u]);
+            else acc_sqdiff(s, a[u], b[u]);
         }
     }
     for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
@@ -111,9 +122,9 @@ __device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, c
 }
 // The same with the query row in LDS and up to 16 chunks per lane in flight (one round for D <= 1024);
 // same operation order, hence the same results.
-__device__ __forceinline__ float exact_dist_group_lds(const float* __restrict__ x, const float4* qs, int D4,
-                                                      int l16) {
-    const int nc = D4 >> 2;
+__device__ __forceinline__ float row_group_lds(const float* __restrict__ x, const float4* qs, int n4x4, int l16,
+                                               bool dot) {
+    const int nc = n4x4 >> 2;
     const float4* __restrict__ xa = reinterpret_cast<const float4*>(x);
     float s = 0.f;
     for (int base = 0; base < nc; base += 256) {
@@ -127,7 +138,8 @@ __device__ __forceinline__ float exact_dist_group_lds(const float* __restrict__ 
         for (int u = 0; u < 16; u++) {
             const int ci = base + 16 * u + l16;
             if (ci >= nc) break;
-            acc_sqdiff(s, a[u], qs[ci]);
+            if (dot) acc_dot4(s, a[u], qs[ci]);
+            else acc_sqdiff(s, a[u], qs[ci]);
         }
     }
     for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
@@ -135,13 +147,27 @@ __device__ __forceinline__ float exact_dist_group_lds(const float* __restrict__ 
 }
 // Low-register form with the same operation order (hence the same results), for the rarely taken
 // in-place path of the scan kernel.
-__device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
-                                                        int D4, int l16) {
+__device__ __forceinline__ float row_group_small(const float* __restrict__ x, const float* __restrict__ q, int n4x4,
+                                                 int l16, bool dot) {
     float s = 0.f;
-    for (int ci = l16; ci < (D4 >> 2); ci += 16)
-        acc_sqdiff(s, reinterpret_cast<const float4*>(x)[ci], reinterpret_cast<const float4*>(q)[ci]);
+    for (int ci = l16; ci < (n4x4 >> 2); ci += 16) {
+        const float4 a = reinterpret_cast<const float4*>(x)[ci], b = reinterpret_cast<const float4*>(q)[ci];
+        if (dot) acc_dot4(s, a, b);
+        else acc_sqdiff(s, a, b);
+    }
     for (int o = 8; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     return s;
+}
+__device__ __forceinline__ float exact_dist_group(const float* __restrict__ x, const float* __restrict__ q, int D4,
+                                                  int l16) {
+    return row_group(x, q, D4, l16, false);
+}
+__device__ __forceinline__ float exact_dist_group_lds(const float* __restrict__ x, const float4* qs, int D4, int l16) {
+    return row_group_lds(x, qs, D4, l16, false);
+}
+__device__ __forceinline__ float exact_dist_group_small(const float* __restrict__ x, const float* __restrict__ q,
+                                                        int D4, int l16) {
+    return row_group_small(x, q, D4, l16, false);
 }
 
 // <x_d, q_d> of Eq 7 (rows zero padded to d4) as one chain of fused multiply-adds, in the order in which
@@ -614,10 +640,11 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
     return hipGetLastError();
 }
 
-// The query's tail coordinates (axes d .. D-1 of q_p = P_p (q - mu)) on the BF16 matrix cores.  They only
-// feed sigma and eps_r (Eq 6): the exact stage reads the original vectors and q_d comes from the FP32
-// product.  The operands are first converted once per search into BF16 rows of Kp = 32 ceil(K / 32)
-// elements, zero beyond K: bf16(q - mu) per query and bf16(P_p row) per tail axis.
+// The query's tail coordinates (axes d .. D-1 of q_p = P_p (q - mu)) on the BF16 matrix cores, when they only
+// feed sigma and eps_r (Eq 6): the exact stage then reads the original vectors and q_d comes from the FP32
+// product.  (The split exact stage needs them in FP32 and takes the FP32 product of all D axes instead.)  The
+// operands are first converted once per search into BF16 rows of Kp = 32 ceil(K / 32) elements, zero beyond
+// K: bf16(q - mu) per query and bf16(P_p row) per tail axis.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // out[r][k] = bf16(src[r][k] - sub[k]) for k < K (sub may be null), 0 for K <= k < Kp; one thread per element
@@ -690,10 +717,14 @@ static int64_t bf16_stage_elems(const Index& ix, int64_t nq) {
 // and the tail coordinates for Eq 6 (BF16 matrix cores when a staging buffer of bf16_stage_elems is given,
 // else FP32 with q_d in the same product).
 static hipError_t launch_query_projection(const Index& ix, const float* Q, int64_t nq, float* qd, float* qtail,
-                                          __bf16* stage, hipStream_t s) {
+                                          int64_t ldt, __bf16* stage, hipStream_t s) {
     const int D = ix.D, d = ix.d, d4 = ix.d4;
     hipError_t e = launch_fill_f32(qd, 0.f, nq * d4, s);
     if (e != hipSuccess) return e;
+    if (ldt > D - d) {  // padded tail rows: zero beyond D - d
+        e = launch_fill_f32(qtail, 0.f, nq * ldt, s);
+        if (e != hipSuccess) return e;
+    }
     if (stage && D > d) {
         e = launch_gemm_mfma<0>(Q, D, ix.mu, ix.Pp, D, qd, d4, nq, d, D, nullptr, nullptr, nullptr, 0, 0, s);
         if (e != hipSuccess) return e;
@@ -706,11 +737,11 @@ static hipError_t launch_query_projection(const Index& ix, const float* Q, int64
         hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((npe + 255) / 256)), dim3(256), 0, s, ix.Pp + (size_t)d * D,
                            (int64_t)D, (const float*)nullptr, D, Kp, (int64_t)(D - d), pb);
         const dim3 grid((unsigned)((nq + 255) / 256), (unsigned)((D - d + 63) / 64));
-        hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, qb, pb, Kp, qtail, (int64_t)(D - d), nq, D - d);
+        hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, qb, pb, Kp, qtail, ldt, nq, D - d);
         return hipGetLastError();
     }
-    // all D axes in one product: columns < d are q_d, the rest the tail coordinates
-    return launch_gemm_mfma<2>(Q, D, ix.mu, ix.Pp, D, qd, d4, nq, D, D, nullptr, nullptr, qtail, D - d, d, s);
+    // all D axes in one FP32 product: columns < d are q_d, the rest the tail coordinates
+    return launch_gemm_mfma<2>(Q, D, ix.mu, ix.Pp, D, qd, d4, nq, D, D, nullptr, nullptr, qtail, ldt, d, s);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -786,7 +817,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const int32_t* __res
 __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q, int D, int D4,
                                                     const float* __restrict__ mu,
                                                     const float* __restrict__ qd, int d, int d4,
-                                                    const float* __restrict__ qtail,
+                                                    const float* __restrict__ qtail, int64_t ldt,
                                                     const float* __restrict__ lam_tail, float m,
                                                     float* __restrict__ qpad, float* __restrict__ qn2,
                                                     float* __restrict__ qd2, float* __restrict__ Tq,
@@ -813,7 +844,7 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
     sd = wave_sum(sd);
     float var = 0.f;
     for (int i = lane; i < r; i += 64) {
-        float v = qtail[q * (int64_t)r + i];
+        float v = qtail[q * ldt + i];
         var = fmaf(lam_tail[i], v * v, var);
     }
     var = wave_sum(var);
@@ -1538,6 +1569,12 @@ struct ScanCtx {
     const float* Tq;
     const TraceSink* tr;  // tracing instantiations only
     int cnt_ext;          // counters has 16 entries: the scan also counts its work units into [8..11]
+    int split;            // split exact stage: exact = fmaf(-2, <x_r, q_r>, dis_o') from the tail rows
+    int Dr4;              // tail row length (split)
+    int RX4;              // length of the row the exact stage reads: Dr4 (split) or D4
+    const float* xr;      // Npad x Dr4 tail rows (split)
+    const float* qr;      // nq x Dr4 query tails, FP32 (split)
+    float* survd;         // split: dis_o' of each exact-stage candidate, beside surv
     float eps0;
     int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, cq;
 };
@@ -1592,15 +1629,19 @@ __device__ __forceinline__ i32x4 piece_bytes(uint32_t p) {
 
 // Exact distances of the sub-tile entries in mask m (bit l: row rbase + (l & 15), query of pair slot
 // cbase + 4 (l >> 4) + v) that did not fit the buffer, four at a time, into the result queues.
+template <bool SPL>
 __device__ void finish_inline(const ScanCtx& c, const PairRec* rec, unsigned long long m, int64_t rbase,
-                              int cbase, int v, int lane) {
+                              int cbase, int v, int lane, const float* dso) {
     const int first = __ffsll((long long)m) - 1;  // a valid entry, evaluated by groups without one
     while (m) {
         const int src = take4(&m, lane);
         const int s0 = src < 0 ? first : src;
         const int64_t row = rbase + (s0 & 15);
         const int q = rec[cbase + 4 * (s0 >> 4) + v].q;
-        const float dist = exact_dist_group_small(c.X + row * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
+        // split: dis_o' of the entry from the wave's stash (lane s0 of the sub-tile's slot)
+        const float dist = SPL ? fmaf(-2.f, row_group_small(c.xr + row * c.Dr4, c.qr + (int64_t)q * c.Dr4, c.Dr4,
+                                                            lane & 15, true), dso[s0])
+                               : exact_dist_group_small(c.X + row * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         if (src >= 0 && (lane & 15) == 0) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
             topk_insert(c.slots + c.slot_off[q], c.kq[q], key);
@@ -1695,7 +1736,7 @@ __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slo
 // The LDS-staged form at 16 queries per item sits at the edge of two waves per SIMD (VGPRs + AGPRs <= 256).
 // Declaring that occupancy (a minimum of two waves) made the compiler keep the accumulators out of AGPRs and
 // the scan 25 % slower (measured), so the budget is left to the compiler's own heuristic.
-template <int GT, int KIT, bool QL, bool TR>
+template <int GT, int KIT, bool QL, bool TR, bool SPL>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
@@ -1727,6 +1768,9 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     unsigned long long* msk = sh_m[wv];
     uint4* pf = sh_pf[wv];
     float4* qsh = qsh_dyn + (QL ? wv * GT * nf4 : 0);
+    // split: the stage-2 value of each entry, indexed like the masks (slot (ct * 4 + rt) * 4 + v, lane), after
+    // the q_d rows in dynamic LDS
+    float* dstash = reinterpret_cast<float*>(qsh_dyn + (QL ? 4 * GT * nf4 : 0)) + wv * (NCT * 16 * 64);
     const int wid = uniform(blockIdx.x * 4 + wv);
     int nreg = 0;  // candidates this wave passed to the exact stage (bins or in place)
     long long nscan = 0, n1 = 0, next = 0;
@@ -2047,13 +2091,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             bool ps = (mv[v] >> lane) & 1ull;
                             if (ps) {
                                 const PairRec& R = rec[ct * 16 + 4 * kg + v];
-                                ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                                const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                ps = dso - R.er < R.tau;
+                                if constexpr (SPL) dstash[((ct * 4 + rt) * 4 + v) * 64 + lane] = dso;
                                 if constexpr (TR) {
-                                    if (trace_on(c.tr, R.q)) {
-                                        const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                    if (trace_on(c.tr, R.q))
                                         trace_cand(c.tr, MRQ_TRACE_STAGE2, p, R.q, R.list, c.ids[row0 + 16 * rt + li], 0, 0,
                                                    dso, R.er, dso - R.er, R.tau);
-                                    }
                                 }
                             }
                             const unsigned long long nm = __ballot(ps);
@@ -2084,13 +2128,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             bool ps = (mv[v] >> lane) & 1ull;
                             if (ps) {
                                 const PairRec& R = rec[ct * 16 + 4 * kg + v];
-                                ps = fmaf(-2.f, dot[v], axr + R.qn2) - R.er < R.tau;
+                                const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                ps = dso - R.er < R.tau;
+                                if constexpr (SPL) dstash[((ct * 4 + rt) * 4 + v) * 64 + lane] = dso;
                                 if constexpr (TR) {
-                                    if (trace_on(c.tr, R.q)) {
-                                        const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
+                                    if (trace_on(c.tr, R.q))
                                         trace_cand(c.tr, MRQ_TRACE_STAGE2, p, R.q, R.list, c.ids[row], 0, 0, dso, R.er,
                                                    dso - R.er, R.tau);
-                                    }
                                 }
                             }
                             const unsigned long long nm = __ballot(ps);
@@ -2134,10 +2178,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                         const int pos = bb[v] + off[v] + __popc(gm & ((1u << li) - 1u));
                         off[v] += __popc(gm);
                         const bool fits = mine && pos < c.cq;
-                        if (fits)
-                            c.surv[(int64_t)rec[ct * 16 + 4 * kg + v].q * c.cq + pos] = (int)(row0 + 16 * rt + li);
+                        const int slot = ((ct * 4 + rt) * 4 + v) * 64;
+                        if (fits) {
+                            const int64_t at = (int64_t)rec[ct * 16 + 4 * kg + v].q * c.cq + pos;
+                            c.surv[at] = (int)(row0 + 16 * rt + li);
+                            if constexpr (SPL) c.survd[at] = dstash[slot + lane];
+                        }
                         const unsigned long long rest = __ballot(mine && !fits);
-                        if (rest) finish_inline(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane);
+                        if (rest) finish_inline<SPL>(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane, dstash + slot);
                         nreg += __popcll(mv);
                     }
                 }
@@ -2167,12 +2215,12 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 // (QL, D4 <= kExactLdsFloats), then k_max keys.  The bin's count is cleared for the next phase.
 constexpr int kExactLdsFloats = 8192;
 
-template <bool QL, bool TR>
+template <bool QL, bool TR, bool SPL>
 __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     extern __shared__ float4 dyn_x[];
     __shared__ int n_s;
     float4* qs = dyn_x;
-    unsigned long long* queue = reinterpret_cast<unsigned long long*>(dyn_x + (QL ? (c.D4 >> 2) : 0));
+    unsigned long long* queue = reinterpret_cast<unsigned long long*>(dyn_x + (QL ? (c.RX4 >> 2) : 0));
     const int q = blockIdx.x;
     const int lane = lane_id();
     if (threadIdx.x == 0) n_s = c.qcnt[q];
@@ -2180,9 +2228,11 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     const int n = min(n_s, c.cq);
     if (n == 0) return;
     if (threadIdx.x == 0) c.qcnt[q] = 0;
-    const float* qrow = c.qpad + (int64_t)q * c.D4;
+    // the row the exact stage reads: the query (original coordinates), or its tail (split exact stage)
+    const int RX4 = c.RX4;
+    const float* qrow = SPL ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
     if (QL)
-        for (int i = threadIdx.x; i < (c.D4 >> 2); i += 256) qs[i] = reinterpret_cast<const float4*>(qrow)[i];
+        for (int i = threadIdx.x; i < (RX4 >> 2); i += 256) qs[i] = reinterpret_cast<const float4*>(qrow)[i];
     unsigned long long* slots = c.slots + c.slot_off[q];
     const int k = c.kq[q];
     for (int i = threadIdx.x; i < k; i += 256) queue[i] = slots[i];
@@ -2191,8 +2241,10 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
         const bool valid = i < n;
         const int64_t row = bin[valid ? i : 0];
-        const float dist = QL ? exact_dist_group_lds(c.X + row * c.D4, qs, c.D4, lane & 15)
-                              : exact_dist_group(c.X + row * c.D4, qrow, c.D4, lane & 15);
+        // the exact distance, or (split) the tail product with dis_o' - 2 <x_r, q_r>
+        const float* xrow = SPL ? c.xr + row * c.Dr4 : c.X + row * c.D4;
+        const float r = QL ? row_group_lds(xrow, qs, RX4, lane & 15, SPL) : row_group(xrow, qrow, RX4, lane & 15, SPL);
+        const float dist = SPL ? fmaf(-2.f, r, c.survd[(int64_t)q * c.cq + (valid ? i : 0)]) : r;
         if (valid && (lane & 15) == 0) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
             topk_insert(queue, k, key);
@@ -2251,14 +2303,18 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
         pass = lb < st.tau;
     }
     *next += __popcll(__ballot(pass));
-    if (pass && !open && c.stage2) {
-        const float dot = qlds ? dot_lane_lds(c.xd + row * c.d4, qs + (c.D4 >> 2), c.d4)
+    // dis_o' (Eq 7): tested once the queue is full; the split exact stage also needs it for every candidate
+    // that reaches the exact distance
+    float dso = 0.f;
+    if (pass && ((!open && c.stage2) || c.split)) {
+        const float dot = qlds ? dot_lane_lds(c.xd + row * c.d4, qs + (c.RX4 >> 2), c.d4)
                                : dot_lane(c.xd + row * c.d4, c.qd + (int64_t)q * c.d4, c.d4);
-        pass = fmaf(-2.f, dot, c.ax[row] + R.qn2) - er < st.tau;
-        if constexpr (TR) {
-            if (trace_on(c.tr, q)) {
-                const float dso = fmaf(-2.f, dot, c.ax[row] + R.qn2);
-                trace_cand(c.tr, MRQ_TRACE_STAGE2, 0, q, R.list, c.ids[row], 0, 0, dso, er, dso - er, st.tau);
+        dso = fmaf(-2.f, dot, c.ax[row] + R.qn2);
+        if (!open && c.stage2) {
+            pass = dso - er < st.tau;
+            if constexpr (TR) {
+                if (trace_on(c.tr, q))
+                    trace_cand(c.tr, MRQ_TRACE_STAGE2, 0, q, R.list, c.ids[row], 0, 0, dso, er, dso - er, st.tau);
             }
         }
     }
@@ -2272,8 +2328,12 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     while (mm) {
         const int src = take4(&mm, lane);
         const int64_t rs = __shfl(row, src < 0 ? first : src);
-        const float dist = qlds ? exact_dist_group_lds(c.X + rs * c.D4, qs, c.D4, lane & 15)
-                                : exact_dist_group(c.X + rs * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
+        // the exact distance, or (split) the tail product with dis_o' - 2 <x_r, q_r>
+        const float* xrow = c.split ? c.xr + rs * c.Dr4 : c.X + rs * c.D4;
+        const float* qrow = c.split ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
+        const float r = qlds ? row_group_lds(xrow, qs, c.RX4, lane & 15, c.split)
+                             : row_group(xrow, qrow, c.RX4, lane & 15, c.split);
+        const float dist = c.split ? fmaf(-2.f, r, __shfl(dso, src < 0 ? first : src)) : r;
         const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
         if constexpr (TR) {
             if (src >= 0 && (lane & 15) == 0 && trace_on(c.tr, q))
@@ -2340,12 +2400,13 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     st.tk[1] = dyn + c.k_max;
     unsigned long long* keys = dyn + 2 * c.k_max;
     // the query row (exact distances) and q_d (stage 2) in LDS, D4 + d4 floats (D4 <= kSeedLdsFloats)
-    const bool qlds = c.D4 <= kSeedLdsFloats;
+    const bool qlds = c.RX4 <= kSeedLdsFloats;
     float4* qs = reinterpret_cast<float4*>(keys + kSeedMax);
     if (qlds) {
-        for (int i = lane; i < (c.D4 >> 2); i += 64) qs[i] = reinterpret_cast<const float4*>(c.qpad + (int64_t)q * c.D4)[i];
+        const float* qx = c.split ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
+        for (int i = lane; i < (c.RX4 >> 2); i += 64) qs[i] = reinterpret_cast<const float4*>(qx)[i];
         for (int i = lane; i < (c.d4 >> 2); i += 64)
-            qs[(c.D4 >> 2) + i] = reinterpret_cast<const float4*>(c.qd + (int64_t)q * c.d4)[i];
+            qs[(c.RX4 >> 2) + i] = reinterpret_cast<const float4*>(c.qd + (int64_t)q * c.d4)[i];
     }
     st.cur = 0;
     st.k = c.kq[q];
@@ -2838,6 +2899,7 @@ struct WsPtrs {
     int8_t* qu8;
     unsigned long long* slots;
     int32_t* surv;
+    float* survd;  // split exact stage: dis_o' of each bin entry
 };
 
 // Exact-stage buffer capacity of a phase (entries): 1/16 of the candidates the search can scan, within
@@ -2866,7 +2928,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     WsPtrs w;
     const int64_t P = (int64_t)kPhases * ix.nlist;
     w.qd = c.take<float>(nq * ix.d4);
-    w.qtail = c.take<float>(nq * (int64_t)(ix.D - ix.d));
+    w.qtail = c.take<float>(nq * (int64_t)std::max(ix.D - ix.d, ix.Dr4));
     w.qpad = c.take<float>(nq * ix.D4);
     w.rq = c.take<float>(nq * ix.d4);
     w.qn2 = c.take<float>(nq);
@@ -2890,6 +2952,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.qbf = c.take<__bf16>(bf16_stage_elems(ix, nq));
     const int64_t cap = surv_capacity(ix, total_pairs);
     w.surv = c.take<int32_t>(cap);
+    w.survd = ix.split ? c.take<float>(cap) : nullptr;
     *used = c.used;
     return w;
 }
@@ -2915,14 +2978,14 @@ template <int WP, int BQT, bool TR>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
     hipLaunchKernelGGL((k_seed<WP, BQT, TR>), dim3((unsigned)nq), dim3(64),
                        sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
-                           (c.D4 <= kSeedLdsFloats ? sizeof(float) * (c.D4 + c.d4) : 0),
+                           (c.RX4 <= kSeedLdsFloats ? sizeof(float) * (c.RX4 + c.d4) : 0),
                        s, c);
 }
 
 // Blocks of a persistent kernel that are resident at once on the current device (cached per device).
 template <class K>
 static int resident_blocks(K kernel, int threads, int slot, size_t lds) {
-    static int cache[16][48];
+    static int cache[16][64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) dev = 0;
     int& v = cache[dev][slot];
@@ -2942,59 +3005,70 @@ static bool scan_ql(const ScanCtx& c) {
     return (KIT == 1 || KIT == 2) && c.d4 == 64 * KIT && c.stage2;
 }
 static size_t scan_lds(const ScanCtx& c, int GT) { return (size_t)4 * GT * c.d4 * sizeof(float); }
+// split: the stage-2 stash of the four waves (GT / 16 column tiles x 16 slots x 64 lanes each)
+static size_t scan_stash(const ScanCtx& c, int GT) { return c.split ? (size_t)4 * (GT / 16) * 16 * 64 * sizeof(float) : 0; }
 
 // TR: the tracing instantiations (c.tr set; query group 16 only).
-template <int GT, int KIT, bool TR>
+template <int GT, int KIT, bool TR, bool SPL>
 static void launch_scan_k(const ScanCtx& c, hipStream_t s, int blocks) {
     if constexpr (KIT == 1 || KIT == 2) {
         if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536) {
-            hipLaunchKernelGGL((k_scan<GT, KIT, true, TR>), dim3(blocks), dim3(256), scan_lds(c, GT), s, c);
+            hipLaunchKernelGGL((k_scan<GT, KIT, true, TR, SPL>), dim3(blocks), dim3(256),
+                               scan_lds(c, GT) + scan_stash(c, GT), s, c);
             return;
         }
     }
-    hipLaunchKernelGGL((k_scan<GT, KIT, false, TR>), dim3(blocks), dim3(256), 0, s, c);
+    hipLaunchKernelGGL((k_scan<GT, KIT, false, TR, SPL>), dim3(blocks), dim3(256), scan_stash(c, GT), s, c);
 }
 
-template <int GT, bool TR>
+template <int GT, bool TR, bool SPL>
 static void launch_scan_g(const ScanCtx& c, hipStream_t s, int blocks) {
     switch (c.KI) {
-        case 1: launch_scan_k<GT, 1, TR>(c, s, blocks); break;
-        case 2: launch_scan_k<GT, 2, TR>(c, s, blocks); break;
-        case 3: case 4: launch_scan_k<GT, 4, TR>(c, s, blocks); break;
-        default: launch_scan_k<GT, 0, TR>(c, s, blocks); break;
+        case 1: launch_scan_k<GT, 1, TR, SPL>(c, s, blocks); break;
+        case 2: launch_scan_k<GT, 2, TR, SPL>(c, s, blocks); break;
+        case 3: case 4: launch_scan_k<GT, 4, TR, SPL>(c, s, blocks); break;
+        default: launch_scan_k<GT, 0, TR, SPL>(c, s, blocks); break;
     }
 }
 
+// Query groups: 16 (the tracing instantiations), 16 / 32 with the split exact stage, 16 / 32 / 64 otherwise.
 static void launch_scan(const ScanCtx& c, hipStream_t s, int blocks) {
-    if (c.tr) launch_scan_g<16, true>(c, s, blocks);
-    else if (c.G <= 16) launch_scan_g<16, false>(c, s, blocks);
-    else if (c.G <= 32) launch_scan_g<32, false>(c, s, blocks);
-    else launch_scan_g<64, false>(c, s, blocks);
+    if (c.tr && c.split) launch_scan_g<16, true, true>(c, s, blocks);
+    else if (c.tr) launch_scan_g<16, true, false>(c, s, blocks);
+    else if (c.split && c.G <= 16) launch_scan_g<16, false, true>(c, s, blocks);
+    else if (c.split) launch_scan_g<32, false, true>(c, s, blocks);
+    else if (c.G <= 16) launch_scan_g<16, false, false>(c, s, blocks);
+    else if (c.G <= 32) launch_scan_g<32, false, false>(c, s, blocks);
+    else launch_scan_g<64, false, false>(c, s, blocks);
 }
 
 // Blocks of the persistent scan grid: what is resident at once on the device, at most kMaxScanBlocks.
-template <int GT, int KIT, bool TR>
+template <int GT, int KIT, bool TR, bool SPL>
 static int scan_grid_k(const ScanCtx& c, int slot) {
     if constexpr (KIT == 1 || KIT == 2) {
         if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536)
-            return std::min(resident_blocks(k_scan<GT, KIT, true, TR>, 256, slot, scan_lds(c, GT)), kMaxScanBlocks);
+            return std::min(resident_blocks(k_scan<GT, KIT, true, TR, SPL>, 256, slot, scan_lds(c, GT) + scan_stash(c, GT)),
+                            kMaxScanBlocks);
     }
-    return std::min(resident_blocks(k_scan<GT, KIT, false, TR>, 256, slot + 1, 0), kMaxScanBlocks);
+    return std::min(resident_blocks(k_scan<GT, KIT, false, TR, SPL>, 256, slot + 1, scan_stash(c, GT)), kMaxScanBlocks);
 }
-template <int GT, bool TR>
+template <int GT, bool TR, bool SPL>
 static int scan_grid_g(const ScanCtx& c, int slot) {
     switch (c.KI) {
-        case 1: return scan_grid_k<GT, 1, TR>(c, slot + 0);
-        case 2: return scan_grid_k<GT, 2, TR>(c, slot + 2);
-        case 3: case 4: return scan_grid_k<GT, 4, TR>(c, slot + 4);
-        default: return scan_grid_k<GT, 0, TR>(c, slot + 6);
+        case 1: return scan_grid_k<GT, 1, TR, SPL>(c, slot + 0);
+        case 2: return scan_grid_k<GT, 2, TR, SPL>(c, slot + 2);
+        case 3: case 4: return scan_grid_k<GT, 4, TR, SPL>(c, slot + 4);
+        default: return scan_grid_k<GT, 0, TR, SPL>(c, slot + 6);
     }
 }
 static int scan_grid(const ScanCtx& c) {
-    if (c.tr) return scan_grid_g<16, true>(c, 32);
-    if (c.G <= 16) return scan_grid_g<16, false>(c, 0);
-    if (c.G <= 32) return scan_grid_g<32, false>(c, 8);
-    return scan_grid_g<64, false>(c, 16);
+    if (c.tr && c.split) return scan_grid_g<16, true, true>(c, 40);
+    if (c.tr) return scan_grid_g<16, true, false>(c, 32);
+    if (c.split && c.G <= 16) return scan_grid_g<16, false, true>(c, 48);
+    if (c.split) return scan_grid_g<32, false, true>(c, 56);
+    if (c.G <= 16) return scan_grid_g<16, false, false>(c, 0);
+    if (c.G <= 32) return scan_grid_g<32, false, false>(c, 8);
+    return scan_grid_g<64, false, false>(c, 16);
 }
 
 template <int WP, bool TR>
@@ -3133,9 +3207,9 @@ static hipError_t launch_search_mrsq(const SearchArgs& a, void* ws, size_t ws_by
     const int G = a.group > 16 ? 32 : 16;
     {   // the projection and the centroid ranking of the MRQ path
         Timed t(tm, s, "project");
-        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, nullptr, s));
+        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, (int64_t)(D - d), nullptr, s));
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4, w.qtail,
-                           ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
+                           (int64_t)(D - d), ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
         HIP_TRY(hipGetLastError());
     }
     {
@@ -3267,14 +3341,20 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     int nph = 1;
     while (nph < kPhases && phase_lo(nph, a.phase_shift) < a.np_max) nph++;
     const int64_t P = (int64_t)nph * nlist;
-    // queries per scan work item (the tracing instantiations exist for 16 only)
-    const int G = a.trace || a.group <= 16 ? 16 : (a.group <= 32 ? 32 : 64);
+    // queries per scan work item (the tracing instantiations exist for 16 only, the split ones for 16 and 32)
+    const bool split_g = ix.split && a.stage2;
+    const int G = a.trace || a.group <= 16 ? 16 : (a.group <= 32 || split_g ? 32 : 64);
 
+    // the split exact stage (an index whose tail is no wider than its leading block, with the Eq 7 stage on)
+    // needs the query's tail coordinates in FP32 (rows padded to Dr4); otherwise they only feed Eq 6 and come
+    // from the BF16 product
+    const bool split = ix.split && a.stage2;
+    const int64_t ldt = split ? (int64_t)ix.Dr4 : (int64_t)(D - d);
     {   // Algorithm 2, projection: q_d = P_p[:d] (q - mu) and the tail coordinates for Eq 6
         Timed t(tm, s, "project");
-        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, w.qbf, s));
+        HIP_TRY(launch_query_projection(ix, a.Q, nq, w.qd, w.qtail, ldt, split ? nullptr : w.qbf, s));
         hipLaunchKernelGGL(k_query_stats, dim3((unsigned)nq), dim3(64), 0, s, a.Q, D, D4, ix.mu, w.qd, d, d4,
-                           w.qtail, ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
+                           w.qtail, ldt, ix.lamTail, a.m, w.qpad, w.qn2, w.qd2, w.Tq, w.er);
         HIP_TRY(hipGetLastError());
         HIP_TRY(launch_gemm_mfma<0>(w.qd, d4, nullptr, ix.PrT, d4, w.rq, d4, nq, d, d, nullptr, nullptr, nullptr, 0,
                                     0, s));
@@ -3295,6 +3375,12 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     c.slots = w.slots; c.surv = w.surv; c.qcnt = w.qcnt; c.counters = a.counters;
     c.pair_list = w.pair_list; c.rq = w.rq; c.RC = ix.RC; c.Tq = w.Tq; c.eps0 = a.eps0; c.tr = a.trace;
     c.cnt_ext = a.counters && a.ncounters >= 16;
+    c.split = split;
+    c.Dr4 = ix.Dr4;
+    c.RX4 = split ? ix.Dr4 : ix.D4;
+    c.xr = ix.xr;
+    c.qr = w.qtail;
+    c.survd = w.survd;
     c.nlist = nlist; c.d = d; c.d4 = d4; c.D4 = D4; c.B = ix.B; c.bq = a.bq; c.G = G;
     c.WP = ix.WP; c.KI = (d + 63) / 64; c.KP = level_bytes(d);
     c.stage2 = a.stage2; c.use_ext = a.use_ext; c.phase = 0; c.k_max = a.k_max;
@@ -3385,14 +3471,14 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         {
             Timed t(tm, s, "exact");
             const size_t qk = (size_t)a.k_max * sizeof(unsigned long long);
-            const size_t ql = (size_t)D4 * sizeof(float) + qk;
-            if (D4 <= kExactLdsFloats) {
-                if (a.trace) hipLaunchKernelGGL((k_exact<true, true>), dim3((unsigned)nq), dim3(256), ql, s, c);
-                else hipLaunchKernelGGL((k_exact<true, false>), dim3((unsigned)nq), dim3(256), ql, s, c);
-            } else {
-                if (a.trace) hipLaunchKernelGGL((k_exact<false, true>), dim3((unsigned)nq), dim3(256), qk, s, c);
-                else hipLaunchKernelGGL((k_exact<false, false>), dim3((unsigned)nq), dim3(256), qk, s, c);
-            }
+            const size_t ql = (size_t)c.RX4 * sizeof(float) + qk;
+#define EXACT(QLV, TRV, SPV, LDS) hipLaunchKernelGGL((k_exact<QLV, TRV, SPV>), dim3((unsigned)nq), dim3(256), LDS, s, c)
+            const bool ql_ex = c.RX4 <= kExactLdsFloats;
+            if (ql_ex && split) { if (a.trace) EXACT(true, true, true, ql); else EXACT(true, false, true, ql); }
+            else if (ql_ex) { if (a.trace) EXACT(true, true, false, ql); else EXACT(true, false, false, ql); }
+            else if (split) { if (a.trace) EXACT(false, true, true, qk); else EXACT(false, false, true, qk); }
+            else { if (a.trace) EXACT(false, true, false, qk); else EXACT(false, false, false, qk); }
+#undef EXACT
             HIP_TRY(hipGetLastError());
         }
     }

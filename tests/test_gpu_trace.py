@@ -245,6 +245,20 @@ def test_trace_c1_without_pruning_reaches_every_stage(c1):
     assert st["stage2"] + st["exact"] >= st["stage1"]
 
 
+@pytest.fixture(scope="module")
+def deep_split():
+    env = _env(128, 64, 1, 20000, 64)  # tail no wider than the leading block: the split exact stage
+    yield env
+    env["ix"].close()
+
+
+def test_trace_split_exact_stage(deep_split):
+    """d_r = D / 2: exact distances come from dis_o' - 2 <x_r, q_r> (FP32 tail coordinates); every exact record
+    is within 1e-5 of the oracle's FP64 distance, and eps_r (from the FP32 tail now) within 1e-5 relative."""
+    st = _compare(deep_split, 10, 8)
+    assert st["exact"] > 0 and st["stage2"] > 0
+
+
 def test_trace_d128_b1(gist_b1):
     st = _compare(gist_b1, 10, 6)
     assert st["stage1"] > 0 and st["stage2"] > 0
