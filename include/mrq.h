@@ -96,9 +96,10 @@ typedef struct {
                                and exact_cap do not apply to MR-SQ; counters [0] and [3] count its
                                scanned candidates and exact distances */
     int32_t phase_growth;   /* MRQ: probe ranks are scanned in phases [1, g), [g, g^2), ... (after the nearest
-                               list), each against the threshold tau reached before it; g in {2, 4, 8}, 0 =
-                               the index default (4, or what mrq_tune chose).  A result may differ between
-                               values only where an error bound fails */
+                               list), each against the threshold tau reached before it; g a power of two
+                               in [2, 1024] (1024: one phase after the nearest list), 0 = the index default
+                               (4, or what mrq_tune chose).  A result may differ between values only where
+                               an error bound fails */
     int32_t ncounters;      /* entries of `counters`: 8 (0 = 8) or 16.  With 16, [8] and [9] also count the
                                batched scan's work: work items (a 64-vector list block against up to `group`
                                pairs) and 16-row tiles whose x_d rows entered stage 2; [10..15] are left
@@ -287,10 +288,11 @@ mrq_status mrq_index_info(const mrq_index *index, int64_t *N, int32_t *D, int32_
  * the original vectors, which the caller keeps).  Synchronous. */
 mrq_status mrq_export(const mrq_index *index, const char *path);
 
-/* Persist / restore a complete index: "MRQS0004", the shape (N, padded rows, D, d_r, bits, nlist, code
+/* Persist / restore a complete index: "MRQS0005", the shape (N, padded rows, D, d_r, bits, nlist, code
  * words per row, longest list, MR-SQ flag), the FP64 eigenvalues, the list offsets, then every device
  * array of the index (projection, rotation, centroids, codes, factors, x_d, the vectors in PCA
- * coordinates, the MR-SQ codes when present) in a fixed order.  The format is private to this library version.  mrq_load allocates on the current device.
+ * coordinates, the tail rows x_r of the split exact stage and the MR-SQ codes when present) in a fixed
+ * order.  The format is private to this library version.  mrq_load allocates on the current device.
  * Synchronous. */
 mrq_status mrq_save(const mrq_index *index, const char *path);
 mrq_status mrq_load(const char *path, mrq_index **out);

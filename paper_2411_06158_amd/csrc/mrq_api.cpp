@@ -533,8 +533,8 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     if (o.group < 0 || o.group > 64) throw Fail(MRQ_EINVAL, "group must be in [0, 64]");
     if (o.exact_cap < 0) throw Fail(MRQ_EINVAL, "exact_cap must be >= 0");
     if (o.method != MRQ_METHOD_MRQ && o.method != MRQ_METHOD_MRSQ) throw Fail(MRQ_EINVAL, "unknown method");
-    if (o.phase_growth != 0 && o.phase_growth != 2 && o.phase_growth != 4 && o.phase_growth != 8)
-        throw Fail(MRQ_EINVAL, "phase_growth must be 0, 2, 4 or 8");
+    if (phase_shift_of(o.phase_growth, 1) < 0)
+        throw Fail(MRQ_EINVAL, "phase_growth must be 0 or a power of two in [2, 1024]");
     if (o.ncounters != 0 && o.ncounters != 8 && o.ncounters != 16) throw Fail(MRQ_EINVAL, "ncounters must be 0, 8 or 16");
     const int ncnt = o.ncounters == 16 ? 16 : 8;
     const int rerank = o.rerank == 0 ? 500 : o.rerank;
@@ -713,7 +713,7 @@ mrq_status run_search(const mrq_index* cix, const float* Q, int64_t nq, bool uni
     a.exact_cap = o.exact_cap;
     a.method = o.method;
     a.rerank = rerank;
-    a.phase_shift = o.phase_growth == 2 ? 1 : (o.phase_growth == 4 ? 2 : (o.phase_growth == 8 ? 3 : ix->phase_shift_default));
+    a.phase_shift = phase_shift_of(o.phase_growth, ix->phase_shift_default);
     a.counters = cnt_d;
     a.ncounters = ncnt;
     a.trace = trace;
@@ -1108,7 +1108,7 @@ mrq_status mrq_tune(mrq_index* index, const float* Q, int64_t nq, int32_t k, int
         (void)hipEventDestroy(e1);
         if (st != MRQ_OK) return st;
         index->group_default = best_g;
-        index->phase_shift_default = best_p == 2 ? 1 : (best_p == 4 ? 2 : 3);
+        index->phase_shift_default = phase_shift_of(best_p, index->phase_shift_default);
         if (group) *group = best_g;
         if (phase_growth) *phase_growth = best_p;
         return MRQ_OK;

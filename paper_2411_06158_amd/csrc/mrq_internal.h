@@ -15,6 +15,13 @@ namespace mrq {
 constexpr int kWave = 64;        // gfx950 wavefront width
 constexpr int kBlockVecs = 64;   // vectors per code block = one vector per lane
 constexpr int kPhases = 11;      // probe-rank phases: {0}, [1,2), [2,4), [4,8), ..., [512,1024)
+// log2 of a phase growth g (a power of two in [2, 1024]); 0 -> `dflt`; -1 for any other value
+inline int phase_shift_of(int g, int dflt) {
+    if (g == 0) return dflt;
+    for (int sh = 1; sh <= 10; sh++)
+        if (g == (1 << sh)) return sh;
+    return -1;
+}
 constexpr int kMaxK = 1024;
 constexpr int kMaxProbe = 1024;
 constexpr uint64_t kEmptyKey = ~0ull;

@@ -265,6 +265,19 @@ __device__ void topk_insert(unsigned long long* slots, int k, unsigned long long
     }
 }
 
+// ||x - q||^2 of the split exact stage, dis_o' - 2 <x_r, q_r>, clamped at zero (a near-duplicate of the
+// query can round below it, and a negative value's bit pattern would not order as a distance).
+__device__ __forceinline__ float split_dist(float dso, float r) {
+    const float v = fmaf(-2.f, r, dso);
+    return v > 0.f ? v : 0.f;
+}
+
+// The bit pattern of the distance in a sorted k-slot array's last key (the array's admission bound: a key
+// with a larger distance cannot enter, so its id need not be read).
+__device__ __forceinline__ uint32_t last_dist_bits(const unsigned long long* slots, int k) {
+    return (uint32_t)(((const volatile unsigned long long*)slots)[k - 1] >> 32);
+}
+
 // Probe-rank phases for a growth g = 2^sh: rank 0 (the seed pass), then [1, g), [g, g^2), ... up to
 // rank 1023 (at most 10 more phases).
 __device__ __forceinline__ int phase_of(int r, int sh) { return r == 0 ? 0 : (32 - __clz(r) + sh - 1) / sh; }
@@ -858,10 +871,26 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
 
 // ------------------------------------------------------------------------------------------------
 // Probe selection (Algorithm 2, centroid ranking): the np nearest lists by g_j = ||q_d - c_j||^2,
-// ties -> smaller list id, nearest first.  One block per query, each thread holding up to kSelV of the
-// query's nlist distances (non-negative, so their bit patterns order like the values): a bitwise search
-// for the np-th smallest pattern T (32 block-wide counting rounds), then every j with g_j <= T is
-// gathered in LDS and the gathered (g, j) keys are sorted; the first np are the probe lists.
+// ties -> smaller list id, nearest first.  One block per query, each thread holding up to 64 of the
+// query's nlist distances in registers (non-negative, so their bit patterns order like the values), the
+// row read once.  Up to np = 256 the keys at or below the np-th smallest per-thread minimum are gathered
+// and ranked; otherwise (or when too many keys fall there) a bitwise search for the np-th smallest
+// pattern T (32 block-wide counting rounds), then every j with g_j <= T is gathered in LDS and the
+// gathered (g, j) keys are sorted; the first np are the probe lists.
+
+// sort 64 keys held one per lane, ascending (bitonic network over shuffles)
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
+    for (int size = 2; size <= 64; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            unsigned long long o = __shfl_xor(v, stride);
+            bool up = (lane & size) == 0;
+            bool lower = (lane & stride) == 0;
+            unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
+            v = (lower == up) ? mn : mx;
+        }
+    }
+    return v;
+}
 
 constexpr int kSelMaxList = 16384;          // nlist <= 256 x 64
 constexpr int kSelCap = kMaxProbe + 1024;   // gathered keys (np plus ties at T)
@@ -882,6 +911,8 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
                                                int32_t* __restrict__ pair_list,
                                                int32_t* __restrict__ pair_q) {
     __shared__ unsigned long long sel[kSelCap];
+    __shared__ unsigned long long mins[4][64];
+    __shared__ unsigned long long s_thr;
     __shared__ int red[4];
     __shared__ int s_cnt, s_wt[4];
     const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -893,6 +924,68 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     for (int u = 0; u < V; u++) {
         const int j = t + 256 * u;
         v[u] = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
+    }
+    if (np <= 256) {
+        // Keys (g_j, j) are unique.  The np-th smallest of the 256 per-thread minimum keys, thr, has at least
+        // np keys at or below it (those np minima), so the np smallest keys are among the keys <= thr, which
+        // are usually few: they are gathered and ranked by counting.  (Keys of j >= nlist exceed every real
+        // key and are never gathered.)
+        unsigned long long mk = kEmptyKey;
+#pragma unroll
+        for (int u = 0; u < V; u++) {
+            const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u);
+            mk = key < mk ? key : mk;
+        }
+        const unsigned long long sk = wave_sort64(mk, lane);
+        mins[w][lane] = sk;
+        __syncthreads();
+        int r = lane;  // rank of sk among the 256 minima
+        for (int w2 = 0; w2 < 4; w2++) {
+            if (w2 == w) continue;
+            int lo = 0, hi = 64;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (mins[w2][mid] < sk) lo = mid + 1; else hi = mid;
+            }
+            r += lo;
+        }
+        if (r == np - 1) s_thr = sk;
+        __syncthreads();
+        const unsigned long long thr = s_thr;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < V; u++)
+            cnt += t + 256 * u < nlist && (((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u)) <= thr;
+        int inc = cnt;  // inclusive prefix over the wave
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) s_wt[w] = inc;
+        __syncthreads();
+        const int m = s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+        if (m <= kSelCap) {  // block-uniform
+            int at = inc - cnt;
+            for (int i = 0; i < w; i++) at += s_wt[i];
+#pragma unroll
+            for (int u = 0; u < V; u++) {
+                const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u);
+                if (t + 256 * u < nlist && key <= thr) sel[at++] = key;
+            }
+            __syncthreads();
+            const int64_t o = pair_off[q];
+            for (int i = t; i < m; i += 256) {
+                const unsigned long long key = sel[i];
+                int rk = 0;
+                for (int x = 0; x < m; x++) rk += sel[x] < key;
+                if (rk < np) {
+                    pair_list[o + rk] = (int32_t)(key & 0xFFFFFFFFull);
+                    pair_q[o + rk] = q;
+                }
+            }
+            return;
+        }
+        __syncthreads();  // more than kSelCap keys at or below thr: the bitwise search below
     }
     uint32_t T = 0;  // the np-th smallest pattern: the largest value with fewer than np patterns below it
     for (int b = 31; b >= 0; b--) {
@@ -961,19 +1054,6 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     }
 }
 
-// sort 64 keys held one per lane, ascending (bitonic network over shuffles)
-__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
-    for (int size = 2; size <= 64; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            unsigned long long o = __shfl_xor(v, stride);
-            bool up = (lane & size) == 0;
-            bool lower = (lane & stride) == 0;
-            unsigned long long mn = v < o ? v : o, mx = v < o ? o : v;
-            v = (lower == up) ? mn : mx;
-        }
-    }
-    return v;
-}
 
 // The same selection for np <= 64 and nlist <= 64 V, one wave per query (four per block, no barriers):
 // lane l holds the patterns of lists j = l + 64 u.  The np-th smallest of the 64 lane minima is a
@@ -1070,105 +1150,6 @@ __global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, i
     }
 }
 
-// The same selection for np <= 64 and any nlist, one wave per query streaming its row of g twice (no
-// values held in registers): pass 1 takes the minimum of each lane's lists j = l + 64 u, whose np-th
-// smallest is a threshold t with at least np patterns <= t; pass 2 gathers the lists with g_j <= t in list
-// order into LDS (up to kSelStreamCap) and each gathered key (g_j, j) finds its rank by counting the
-// smaller ones; ranks below np are the output positions.  With more lists at or below t than fit, the
-// np-th smallest key is found bitwise, counting over the row in each round (pattern, then list id among
-// the ties), and the np lists are gathered and sorted.  The lists and their order are those of k_select.
-constexpr int kSelStreamCap = 256;  // about 64 ln 65 ~ 267 lists fall at or below the threshold at np = 64
-
-__global__ __launch_bounds__(256) void k_select_s(const float* __restrict__ G, int nlist,
-                                                  const int32_t* __restrict__ npq,
-                                                  const int64_t* __restrict__ pair_off,
-                                                  int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q,
-                                                  int64_t nq) {
-    __shared__ unsigned long long sel_s[4][kSelStreamCap];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t q = blockIdx.x * 4ll + w;
-    if (q >= nq) return;
-    const uint32_t* g = reinterpret_cast<const uint32_t*>(G + q * nlist);  // non-negative: patterns order like values
-    const int np = npq[q];
-    if (np == 0) return;  // wave-uniform
-    const int64_t o = pair_off[q];
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    uint32_t mn = 0xFFFFFFFFu;
-    for (int j0 = 0; j0 < nlist; j0 += 512) {
-        uint32_t x[8];
-#pragma unroll
-        for (int t = 0; t < 8; t++) {
-            const int j = j0 + 64 * t + lane;
-            x[t] = j < nlist ? g[j] : 0xFFFFFFFFu;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; t++) mn = min(mn, x[t]);
-    }
-    const uint32_t thr = (uint32_t)__shfl(wave_sort64(mn, lane), np - 1);
-    int at = 0;
-    for (int j0 = 0; j0 < nlist; j0 += 512) {
-        uint32_t x[8];
-#pragma unroll
-        for (int t = 0; t < 8; t++) {
-            const int j = j0 + 64 * t + lane;
-            x[t] = j < nlist ? g[j] : 0xFFFFFFFFu;
-        }
-#pragma unroll
-        for (int t = 0; t < 8; t++) {
-            const int j = j0 + 64 * t + lane;
-            const bool sel = j < nlist && x[t] <= thr;
-            const unsigned long long m = __ballot(sel);
-            const int pos = at + __popcll(m & lt);
-            if (sel && pos < kSelStreamCap) sel_s[w][pos] = ((unsigned long long)x[t] << 32) | (uint32_t)j;
-            at += __popcll(m);
-        }
-    }
-    wave_lds_fence();
-    if (at <= kSelStreamCap) {
-        for (int i = lane; i < at; i += 64) {
-            const unsigned long long key = sel_s[w][i];
-            int r = 0;
-            for (int x = 0; x < at; x++) r += sel_s[w][x] < key;
-            if (r < np) {
-                pair_list[o + r] = (int32_t)(key & 0xFFFFFFFFull);
-                pair_q[o + r] = (int32_t)q;
-            }
-        }
-        return;
-    }
-    auto count_row = [&](auto pred) __attribute__((always_inline)) {
-        int c = 0;
-        for (int j = lane; j < nlist; j += 64) c += pred(g[j], j);
-        return wave_sum_i(c);
-    };
-    uint32_t T = 0;  // the np-th smallest pattern
-    for (int b = 31; b >= 0; b--) {
-        const uint32_t cand = T | (1u << b);
-        if (count_row([&](uint32_t v, int) { return v < cand; }) < np) T = cand;
-    }
-    const int need = np - count_row([&](uint32_t v, int) { return v < T; });  // ties at T to take (>= 1)
-    uint32_t Jb = 0;  // the need-th smallest tied list id
-    for (int b = 31 - __clz(nlist - 1 > 0 ? nlist - 1 : 1); b >= 0; b--) {
-        const uint32_t cand = Jb | (1u << b);
-        if (count_row([&](uint32_t v, int j) { return v == T && (uint32_t)j < cand; }) < need) Jb = cand;
-    }
-    at = 0;
-    for (int j0 = 0; j0 < nlist; j0 += 64) {
-        const int j = j0 + lane;
-        const uint32_t v = j < nlist ? g[j] : 0xFFFFFFFFu;
-        const bool sel = j < nlist && (v < T || (v == T && (uint32_t)j <= Jb));
-        const unsigned long long m = __ballot(sel);
-        if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v << 32) | (uint32_t)j;
-        at += __popcll(m);
-    }
-    wave_lds_fence();
-    const unsigned long long key = wave_sort64(lane < np ? sel_s[w][lane] : kEmptyKey, lane);
-    if (lane < np) {
-        pair_list[o + lane] = (int32_t)(key & 0xFFFFFFFFull);
-        pair_q[o + lane] = (int32_t)q;
-    }
-}
-
 static void launch_select(const float* G, int nlist, const int32_t* npq, const int64_t* pair_off, int32_t* pair_list,
                           int32_t* pair_q, int64_t nq, int np_max, hipStream_t s) {
     if (np_max <= 64 && nlist <= 64 * 64) {
@@ -1176,11 +1157,6 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
         if (nlist <= 64 * 16) hipLaunchKernelGGL(k_select_w<16>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
         else if (nlist <= 64 * 32) hipLaunchKernelGGL(k_select_w<32>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
         else hipLaunchKernelGGL(k_select_w<64>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
-        return;
-    }
-    if (np_max <= 64) {
-        hipLaunchKernelGGL(k_select_s, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, G, nlist, npq, pair_off,
-                           pair_list, pair_q, nq);
         return;
     }
     const dim3 grid((unsigned)nq), blk(256);
@@ -1639,12 +1615,14 @@ __device__ void finish_inline(const ScanCtx& c, const PairRec* rec, unsigned lon
         const int64_t row = rbase + (s0 & 15);
         const int q = rec[cbase + 4 * (s0 >> 4) + v].q;
         // split: dis_o' of the entry from the wave's stash (lane s0 of the sub-tile's slot)
-        const float dist = SPL ? fmaf(-2.f, row_group_small(c.xr + row * c.Dr4, c.qr + (int64_t)q * c.Dr4, c.Dr4,
-                                                            lane & 15, true), dso[s0])
+        const float dist = SPL ? split_dist(dso[s0], row_group_small(c.xr + row * c.Dr4, c.qr + (int64_t)q * c.Dr4,
+                                                                      c.Dr4, lane & 15, true))
                                : exact_dist_group_small(c.X + row * c.D4, c.qpad + (int64_t)q * c.D4, c.D4, lane & 15);
         if (src >= 0 && (lane & 15) == 0) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
-            topk_insert(c.slots + c.slot_off[q], c.kq[q], key);
+            unsigned long long* slots = c.slots + c.slot_off[q];
+            const int k = c.kq[q];
+            const uint32_t db = __float_as_uint(dist);
+            if (db <= last_dist_bits(slots, k)) topk_insert(slots, k, ((unsigned long long)db << 32) | (uint32_t)c.ids[row]);
         }
     }
 }
@@ -2244,10 +2222,10 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
         // the exact distance, or (split) the tail product with dis_o' - 2 <x_r, q_r>
         const float* xrow = SPL ? c.xr + row * c.Dr4 : c.X + row * c.D4;
         const float r = QL ? row_group_lds(xrow, qs, RX4, lane & 15, SPL) : row_group(xrow, qrow, RX4, lane & 15, SPL);
-        const float dist = SPL ? fmaf(-2.f, r, c.survd[(int64_t)q * c.cq + (valid ? i : 0)]) : r;
+        const float dist = SPL ? split_dist(c.survd[(int64_t)q * c.cq + (valid ? i : 0)], r) : r;
         if (valid && (lane & 15) == 0) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[row];
-            topk_insert(queue, k, key);
+            const uint32_t db = __float_as_uint(dist);
+            if (db <= last_dist_bits(queue, k)) topk_insert(queue, k, ((unsigned long long)db << 32) | (uint32_t)c.ids[row]);
             if constexpr (TR) {
                 if (trace_on(c.tr, q))
                     trace_cand(c.tr, MRQ_TRACE_EXACT, c.phase, q, -1, c.ids[row], 0, 0, dist, 0.f, 0.f, 0.f);
@@ -2333,8 +2311,11 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
         const float* qrow = c.split ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
         const float r = qlds ? row_group_lds(xrow, qs, c.RX4, lane & 15, c.split)
                              : row_group(xrow, qrow, c.RX4, lane & 15, c.split);
-        const float dist = c.split ? fmaf(-2.f, r, __shfl(dso, src < 0 ? first : src)) : r;
-        const unsigned long long key = ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs];
+        const float dist = c.split ? split_dist(__shfl(dso, src < 0 ? first : src), r) : r;
+        // a key whose distance is above a full queue's last cannot survive the merge: its id is not read
+        const unsigned long long key = (src >= 0 && (st.tau == INFINITY || dist <= st.tau))
+                                           ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs]
+                                           : kEmptyKey;
         if constexpr (TR) {
             if (src >= 0 && (lane & 15) == 0 && trace_on(c.tr, q))
                 trace_cand(c.tr, MRQ_TRACE_EXACT, 0, q, R.list, c.ids[rs], 0, 0, dist, 0.f, 0.f, st.tau);

@@ -206,8 +206,7 @@ bool launch_batch(mrq_server* sv, Slot& sl) {
     a.group = sv->opts.group > 0 ? sv->opts.group : ix.group_default;
     a.method = sv->opts.method;
     a.rerank = sv->opts.rerank;
-    const int pg = sv->opts.phase_growth;
-    a.phase_shift = pg == 2 ? 1 : (pg == 4 ? 2 : (pg == 8 ? 3 : ix.phase_shift_default));
+    a.phase_shift = mrq::phase_shift_of(sv->opts.phase_growth, ix.phase_shift_default);
     a.ids = d_ids;
     a.dists = d_d;
     a.counters = nullptr;
@@ -343,8 +342,7 @@ mrq_status mrq_server_create(const mrq_index* index, size_t mem_budget, int32_t 
     if ((sv->opts.method != MRQ_METHOD_MRQ && sv->opts.method != MRQ_METHOD_MRSQ) || sv->opts.rerank < 1 ||
         sv->opts.rerank > 16384) { delete sv; return MRQ_EINVAL; }
     if (sv->opts.method == MRQ_METHOD_MRSQ && sv->core->dq == 0) { delete sv; return MRQ_ESTATE; }
-    if (sv->opts.phase_growth != 0 && sv->opts.phase_growth != 2 && sv->opts.phase_growth != 4 &&
-        sv->opts.phase_growth != 8) { delete sv; return MRQ_EINVAL; }
+    if (mrq::phase_shift_of(sv->opts.phase_growth, 1) < 0) { delete sv; return MRQ_EINVAL; }
     (void)hipSetDevice(sv->core->device);
     const mrq::Index& ix = *sv->core;
     for (Slot& sl : sv->slots) {

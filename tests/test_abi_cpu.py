@@ -111,7 +111,7 @@ def test_load_rejects_missing_and_corrupt_files():
         path = f.name
     try:
         assert mrq.lib().mrq_load(path.encode(), C.byref(h)) == mrq.MRQ_EIO
-        assert "MRQS0004" in mrq.lib().mrq_last_error().decode()
+        assert "MRQS0005" in mrq.lib().mrq_last_error().decode()
     finally:
         os.unlink(path)
 

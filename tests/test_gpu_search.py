@@ -245,37 +245,33 @@ def test_mixed_batch_replays_from_a_captured_graph(small):
 
 @pytest.mark.parametrize("nlist", [256, 1500, 5000])
 def test_probe_selection_kernels_agree(nlist):
-    """Batches whose largest nprobe is at most 64 rank the lists one wave per query, larger ones one block
-    per query; both take the np smallest (g_j, j), so a row is the same under either (nlist 256 and 1500:
-    16 and 32 lists per lane held in registers; 5000: the streaming form, whose gathered set exceeds its
-    LDS capacity for some queries at nprobe 64, so its bitwise fallback runs too)."""
+    """The probe ranking has three forms: one wave per query for nprobe <= 64 and nlist <= 4096 (16, 32 or 64
+    lists per lane in registers), and one block per query otherwise, which gathers the keys at or below the
+    np-th smallest per-thread minimum when np <= 256 and takes a bitwise search of the np-th smallest
+    pattern beyond.  All take the np smallest (g_j, j) in that order, so a row is the same under each
+    (nlist 256 and 1500: wave against block); at nlist 5000 every form is the block kernel, and rows at
+    nprobe 64 (gathering) and 300 (bitwise search) are checked against the oracle row by row."""
     print(f"\n[gpu] selection kernels agree: nlist={nlist}", flush=True)
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
     ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
     try:
-        if nlist > 4096:
-            # the streaming form's fallback runs where more than 256 lists fall at or below the np-th smallest
-            # lane minimum (lane l: lists l + 64 u): check on the exported centroids that some query does
-            path = os.path.join(tempfile.mkdtemp(), "ix.mrqx")
-            ix.export(path)
-            raw = oracle.Index.load_export(path)
-            mu, Pp, C = raw.get("mu"), raw.get("Pp"), raw.get("C").astype(np.float64)
-            qd = (Q.astype(np.float64) - mu) @ Pp[:C.shape[1]].T
-            g = ((qd[:, None, :] - C[None, :, :]) ** 2).sum(-1)
-            pad = np.full((g.shape[0], (-nlist) % 64), np.inf)
-            mins = np.concatenate([g, pad], 1).reshape(g.shape[0], -1, 64).min(1)
-            thr = np.sort(mins, 1)[:, 63]
-            assert ((g <= thr[:, None]).sum(1) > 256).any()
         Qd = torch.from_numpy(Q).cuda()
         for np_small in (1, 7, 20, 64):
             ks = np.full(60, 10, np.int32)
             nps = np.full(60, np_small, np.int32)
             nps[-1] = 100                                   # np_max 100: the block kernel for every row
             ids, dists, off = ix.search_mixed(Qd, ks, nps)
-            a, b = ix.search(Qd[:59].contiguous(), 10, np_small)  # np_max <= 64: the wave kernel
+            a, b = ix.search(Qd[:59].contiguous(), 10, np_small)  # np_max <= 64: the wave kernel up to 4096
             torch.cuda.synchronize()
             assert np.array_equal(ids[:590].reshape(59, 10), a.cpu().numpy())
             assert np.array_equal(dists[:590].reshape(59, 10).view(np.uint32), b.cpu().numpy().view(np.uint32))
+        if nlist > 4096:
+            path = os.path.join(tempfile.mkdtemp(), "ix.mrqx")
+            ix.export(path)
+            env = dict(X=X, Q=Q, ix=ix, Qd=Qd, orc=oracle.Index.load_export(path, X))
+            for nprobe in (64, 300):
+                ids, dists = _search(env, 10, nprobe)
+                _assert_parity(env, ids, dists, 10, nprobe)
     finally:
         ix.close()
 
@@ -405,7 +401,7 @@ def test_exact_buffer_overflow_gives_same_results(small, small_ext):
         assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
 
 
-@pytest.mark.parametrize("growth", [2, 4, 8])
+@pytest.mark.parametrize("growth", [2, 4, 8, 1024])
 @pytest.mark.parametrize("group", [16, 32, 64])
 def test_group_size_does_not_change_results(small, group, growth):
     ix, Q = small["ix"], small["Q"]
@@ -415,9 +411,10 @@ def test_group_size_does_not_change_results(small, group, growth):
     assert np.array_equal(a_d.view(np.uint32), b_d.view(np.uint32))
 
 
-@pytest.mark.parametrize("growth", [2, 4, 8])
+@pytest.mark.parametrize("growth", [2, 4, 8, 64, 1024])
 def test_phase_growth_rows_match_oracle(small, growth):
-    """Phases [1, g), [g, g^2), ...: any growth gives the oracle's result wherever the bounds hold."""
+    """Phases [1, g), [g, g^2), ...: any growth gives the oracle's result wherever the bounds hold (1024: one
+    batched phase after the nearest list)."""
     ids, dists = _search(small, 10, 32, phase_growth=growth)
     _assert_parity(small, ids, dists, 10, 32)
 
@@ -425,6 +422,9 @@ def test_phase_growth_rows_match_oracle(small, growth):
 def test_phase_growth_rejects_other_values(small):
     with pytest.raises(mrq.MRQError) as e:
         small["ix"].search(small["Q"][:2], 10, 8, phase_growth=3)
+    assert e.value.status == mrq.MRQ_EINVAL
+    with pytest.raises(mrq.MRQError) as e:
+        small["ix"].search(small["Q"][:2], 10, 8, phase_growth=2048)
     assert e.value.status == mrq.MRQ_EINVAL
 
 
