@@ -1677,15 +1677,14 @@ __device__ __forceinline__ f32x4 dot_tile(const float* __restrict__ qp, const fl
     return acc;
 }
 
-// The same product with the row tile's x_d slices already in registers (SU slices, zero beyond d4).
+// The same product with the row tile's x_d slices already in registers (SU slices covering d4 = 16 SU
+// exactly, the LDS-staged form's shape: no slice needs zeroing, so nothing touches the loaded registers
+// before their products and the loads stay in flight until then).
 template <int SU>
-__device__ __forceinline__ void load_x_slices(float4 (&xa)[SU], const float* __restrict__ xp, int d4, int kg) {
+__device__ __forceinline__ void load_x_slices(float4 (&xa)[SU], const float* __restrict__ xp) {
     const float4* __restrict__ x4 = reinterpret_cast<const float4*>(xp);
 #pragma unroll
-    for (int t = 0; t < SU; t++) {
-        const bool in = 16 * t + 4 * kg < d4;
-        xa[t] = zero_unless(x4[in ? 4 * t : 0], in);
-    }
+    for (int t = 0; t < SU; t++) xa[t] = x4[4 * t];
 }
 template <int SU>
 __device__ __forceinline__ f32x4 dot_tile_x(const float4 (&xa)[SU], const float* __restrict__ qp, bool qv, int d4,
@@ -1789,7 +1788,10 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     if (wid < total) {
         dcur = const_load4(c.desc + base_item + wid);
         fetch_recs(dcur, r0, r1, r2);
-        if (QL) stage_operands(dcur);
+        if (QL) {
+            stage_operands(dcur);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the first item's staged operands have landed
+        }
         if (wid + nwaves < total) dnext = const_load4(c.desc + base_item + wid + nwaves);
     }
     for (int it = wid; it < total; it += nwaves) {
@@ -1802,22 +1804,6 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             rw[1] = r1;
             rw[2] = r2;
         }
-        if (QL && c.stage2) {
-            // the item's q_d rows into LDS, landed before stage 2; LDS float4 f of slot s holds column
-            // f ^ (s & 15) of the slot's query (the swizzle of qsh_index, applied on the source side)
-            constexpr int NF4 = 16 * KA;
-            const int myq = __float_as_int(r2.x);  // query of the pair held by this lane
-            const float4* q4 = reinterpret_cast<const float4*>(c.qd);
-            const int tot = ng * NF4;
-            for (int e0 = 0; e0 < tot; e0 += 64) {
-                const int e = e0 + lane;
-                const int slot = e / NF4, f = e - slot * NF4;
-                const int qr = __shfl(myq, slot < ng ? slot : 0);
-                if (e < tot)
-                    __builtin_amdgcn_global_load_lds((const void*)(q4 + (int64_t)qr * NF4 + (f ^ (slot & 15))),
-                                                     (lds_ptr)(qsh + e0), 16, 0, 0);
-            }
-        }
         // stage-1 operands of this item into registers: QL from the staging area (which is then refilled
         // for the next item), otherwise from global memory
         uint32_t cw[4][KA];
@@ -1825,7 +1811,9 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         i32x4 qa[NCT][KA];
         if (KIT > 0) {
             if (QL) {
-                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this item's staged operands have landed
+                // this item's staged operands have landed: the previous item waited for them before its stage
+                // 2 (the first item, in the prologue), so the stores still in flight from the previous item's
+                // bins are not waited for here
                 wave_lds_fence();
                 const uint32_t* pcode = reinterpret_cast<const uint32_t*>(pf);
                 const float* pfac = reinterpret_cast<const float*>(pf + PF_CODE / 16);
@@ -1875,19 +1863,48 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                 }
             }
         }
-        // requests for the next item, then the x_d slices and norms of row tile 0 (nearly every tile
-        // reaches stage 2)
+        if (QL && c.stage2) {
+            // the item's q_d rows into LDS, requested once its stage-1 operands are read out (so that they
+            // land during stage 1) and waited for before stage 2; LDS float4 f of slot s holds column
+            // f ^ (s & 15) of the slot's query (the swizzle of qsh_index, applied on the source side)
+            constexpr int NF4 = 16 * KA;
+            const int myq = __float_as_int(r2.x);  // query of the pair held by this lane
+            const float4* q4 = reinterpret_cast<const float4*>(c.qd);
+            const int tot = ng * NF4;
+            for (int e0 = 0; e0 < tot; e0 += 64) {
+                const int e = e0 + lane;
+                const int slot = e / NF4, f = e - slot * NF4;
+                const int qr = __shfl(myq, slot < ng ? slot : 0);
+                if (e < tot)
+                    __builtin_amdgcn_global_load_lds((const void*)(q4 + (int64_t)qr * NF4 + (f ^ (slot & 15))),
+                                                     (lds_ptr)(qsh + e0), 16, 0, 0);
+            }
+        }
+        // requests for the next item, then the x_d slices and norms of the row tiles (nearly every tile
+        // reaches stage 2): tile 0, or at d4 = 64 all four, whose loads are then in flight together
+        // (the records are fetched unconditionally, from a valid descriptor either way: a conditional
+        // fetch makes the compiler merge the registers right after it, waiting for the loads there)
         int4 dnn = dnext;
+        fetch_recs(dnext, r0, r1, r2);
         if (it + nwaves < total) {
-            fetch_recs(dnext, r0, r1, r2);
             if (QL) stage_operands(dnext);
             if (it + 2 * nwaves < total) dnn = const_load4(c.desc + base_item + it + 2 * nwaves);
         }
+        constexpr bool XALL = QL && KIT == 1;
         float4 xs0[XS];
         float ax0 = 0.f;
+        float4 xall[XALL ? 3 : 1][XS];
+        float axall[XALL ? 3 : 1];
         if (QL && c.stage2) {
-            load_x_slices<XS>(xs0, c.xd + (row0 + li) * c.d4 + 4 * kg, c.d4, kg);
+            load_x_slices<XS>(xs0, c.xd + (row0 + li) * c.d4 + 4 * kg);
             ax0 = c.ax[row0 + li];
+            if constexpr (XALL) {
+#pragma unroll
+                for (int rt = 1; rt < 4; rt++) {
+                    load_x_slices<XS>(xall[rt - 1], c.xd + (row0 + 16 * rt + li) * c.d4 + 4 * kg);
+                    axall[rt - 1] = c.ax[row0 + 16 * rt + li];
+                }
+            }
         }
 
         // ---- stage 1 for every 16 x 16 sub-tile: pass masks into msk ----
@@ -2043,14 +2060,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 #pragma unroll
                 for (int rt = 0; rt < 4; rt++) {
                     // the next tile's slices and norms are requested before this tile's products
-                    if (rt < 3 && ((rtany >> (rt + 1)) & 1u)) {
+                    if (!XALL && rt < 3 && ((rtany >> (rt + 1)) & 1u)) {
                         const int64_t rn = row0 + 16 * (rt + 1) + li;
-                        load_x_slices<XS>(xb[(rt + 1) & 1], c.xd + rn * c.d4 + 4 * kg, c.d4, kg);
+                        load_x_slices<XS>(xb[(rt + 1) & 1], c.xd + rn * c.d4 + 4 * kg);
                         axb[(rt + 1) & 1] = c.ax[rn];
                     }
                     if (!((rtany >> rt) & 1u)) continue;
-                    const float4(&xa)[XS] = rt == 0 ? xs0 : xb[rt & 1];
-                    const float axr = rt == 0 ? ax0 : axb[rt & 1];
+                    const float4(&xa)[XS] = rt == 0 ? xs0 : (XALL ? xall[rt - 1] : xb[rt & 1]);
+                    const float axr = rt == 0 ? ax0 : (XALL ? axall[rt - 1] : axb[rt & 1]);
                     for (int ct = 0; ct < nct; ct++) {
                         unsigned long long mv[4];
                         bool any = false;
