@@ -2039,7 +2039,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             wave_lds_fence();
         }
         next += cnt;
-        if (QL && c.stage2) {
+        if constexpr (QL) {  // (the staged form always runs stage 2; a compile-time branch keeps the
+                             // compiler's own wait tracking aware of this wait)
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the item's q_d rows have landed in LDS
             wave_lds_fence();
         }
@@ -2156,6 +2157,9 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                     n += __popcll((msk[(tc * 4 + rt) * 4 + tv] >> (16 * tg)) & 0xFFFFull);
                 if (n) base = atomicAdd(&c.qcnt[rec[lane].q], n);
             }
+            // the reservation is consumed here on every path (an unconsumed result register would make the
+            // next item wait for all memory operations in flight before its first write to that register)
+            asm volatile("" ::"v"(base));
             for (int ct = 0; ct < nct; ct++) {
                 int bb[4], off[4];
 #pragma unroll
