@@ -2213,6 +2213,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 // query row is staged in LDS too and read from memory once per block.  Dynamic shared memory: D4 floats
 // (QL, D4 <= kExactLdsFloats), then k_max keys.  The bin's count is cleared for the next phase.
 constexpr int kExactLdsFloats = 8192;
+constexpr int kExactRows = 4;  // candidates per 16-lane group at a time when rows are at most 64 floats
 
 template <bool QL, bool TR, bool SPL>
 __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
@@ -2237,6 +2238,54 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
     for (int i = threadIdx.x; i < k; i += 256) queue[i] = slots[i];
     __syncthreads();
     const int32_t* bin = c.surv + (int64_t)q * c.cq;
+    if (RX4 <= 64) {
+        // rows of at most 16 float4 (the split form's short tails): one chunk per lane, so a group takes
+        // kExactRows candidates at a time with their loads in flight together; each candidate's sum is the
+        // same as the one-candidate form's (its lane's single chunk, then the same 16-lane reduction)
+        const int l16 = lane & 15, nc = RX4 >> 2;
+        const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 qv = l16 < nc ? (QL ? qs[l16] : reinterpret_cast<const float4*>(qrow)[l16]) : zero4;
+        const float* xbase = SPL ? c.xr : c.X;
+        const int ld = SPL ? c.Dr4 : c.D4;
+        for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16 * kExactRows) {
+            int64_t row[kExactRows];
+            float4 xa[kExactRows];
+            float dso[kExactRows];
+#pragma unroll
+            for (int u = 0; u < kExactRows; u++) {
+                const int iu = i + 16 * u < n ? i + 16 * u : 0;
+                row[u] = bin[iu];
+                dso[u] = SPL ? c.survd[(int64_t)q * c.cq + iu] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kExactRows; u++)
+                xa[u] = l16 < nc ? reinterpret_cast<const float4*>(xbase + row[u] * ld)[l16] : zero4;
+#pragma unroll
+            for (int u = 0; u < kExactRows; u++) {
+                const int iu = i + 16 * u;
+                const bool valid = iu < n;
+                float r = 0.f;
+                if (l16 < nc) {
+                    if (SPL) acc_dot4(r, xa[u], qv);
+                    else acc_sqdiff(r, xa[u], qv);
+                }
+                for (int o = 8; o >= 1; o >>= 1) r += __shfl_xor(r, o);
+                const float dist = SPL ? split_dist(dso[u], r) : r;
+                if (valid && l16 == 0) {
+                    const uint32_t db = __float_as_uint(dist);
+                    if (db <= last_dist_bits(queue, k))
+                        topk_insert(queue, k, ((unsigned long long)db << 32) | (uint32_t)c.ids[row[u]]);
+                    if constexpr (TR) {
+                        if (trace_on(c.tr, q))
+                            trace_cand(c.tr, MRQ_TRACE_EXACT, c.phase, q, -1, c.ids[row[u]], 0, 0, dist, 0.f, 0.f, 0.f);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += 256) slots[i] = queue[i];
+        return;
+    }
     for (int i = threadIdx.x >> 4; i - (lane >> 4) < n; i += 16) {
         const bool valid = i < n;
         const int64_t row = bin[valid ? i : 0];

@@ -298,6 +298,33 @@ def test_dimensions_off_the_tiles(D):
         ix.close()
 
 
+@pytest.mark.parametrize("D,d", [(128, 64), (64, 32), (48, 40)])
+def test_short_exact_rows_match_oracle(D, d):
+    """Tails no wider than the leading block: the exact stage takes dis_o' - 2 <x_r, q_r> from rows of D - d
+    floats (64, 32 and 8 here), four candidates per lane group at a time; with stage 2 off it reads the whole
+    rows (at most 64 floats at D = 64 and 48: the same short-row form).  Rows match the oracle, and the
+    in-place form of the scan (exact_cap 1) and the per-query path give the same rows bit for bit."""
+    N = 12000
+    print(f"\n[gpu] short exact rows: build N={N} D={D} d={d} B=1 nlist=48", flush=True)
+    m = synth.build_model(synth.MixtureSpec(D=D, n_comp=24, decay=1.0, cluster_dims=8, model_seed=17))
+    X, Q = synth.sample(m, N, 1), synth.sample(m, 50, 2)
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=d, bits=1, nlist=48)
+    try:
+        path = os.path.join(tempfile.mkdtemp(), "ix.mrqx")
+        ix.export(path)
+        env = dict(X=X, Q=Q, ix=ix, Qd=torch.from_numpy(Q).cuda(), orc=oracle.Index.load_export(path, X))
+        for k, nprobe, kw in ((10, 8, {}), (50, 16, {}), (10, 8, dict(stage2=False))):
+            ids, dists = _search(env, k, nprobe, **kw)
+            prm = oracle.params(**kw)
+            _assert_parity(env, ids, dists, k, nprobe, prm)
+            for alt in (dict(exact_cap=1), dict(mode=mrq.MRQ_PER_QUERY)):
+                b_ids, b_d = _search(env, k, nprobe, **kw, **alt)
+                assert np.array_equal(ids, b_ids), (k, nprobe, kw, alt)
+                assert np.array_equal(dists.view(np.uint32), b_d.view(np.uint32)), (k, nprobe, kw, alt)
+    finally:
+        ix.close()
+
+
 def test_counters_monotone(small):
     cnt = np.zeros(8, dtype=np.int64)
     small["ix"].search(small["Q"][:20].copy(), 10, 8, counters=cnt)
