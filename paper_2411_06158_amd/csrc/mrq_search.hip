@@ -2320,6 +2320,7 @@ __global__ __launch_bounds__(256) void k_exact(ScanCtx c) {
 constexpr int kSeedMax = 512;  // candidate keys held in LDS for the round-1 selection
 constexpr int kSeedFirst = 32;  // round 1 takes at least this many best-bound candidates
 constexpr int kSeedLdsFloats = 2048;  // query rows up to this length are staged in LDS
+constexpr int kSeedRows = 4;  // short exact rows per lane group at a time
 
 struct QueryState {
     unsigned long long* tk[2];
@@ -2333,7 +2334,7 @@ struct QueryState {
 // One batch of at most 64 candidates (one per lane; `pass` = passed stage 1 against st.tau): B-bit
 // refinement, Eq 7 re-check, exact distances four at a time, then a merge of the new keys into the
 // sorted queue and the new tau.
-template <int WP, bool TR>
+template <int WP, bool TR, bool SR>
 __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, const PairRec& R, const uint32_t* U, bool pass, int64_t row,
                            QueryState& st, unsigned long long* nk, const float4* qs, bool qlds, int lane,
                            long long* n1, long long* next, long long* n2) {
@@ -2369,11 +2370,53 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     const unsigned long long m2 = __ballot(pass);
     *n2 += __popcll(m2);
     if (!m2) return;
-    // exact distances, four candidates at a time (16 lanes each)
+    // exact distances, four candidates at a time (16 lanes each); rows of at most 64 floats (one chunk per
+    // lane) 4 kSeedRows at a time, kSeedRows per lane group, with the same arithmetic per candidate
     unsigned long long mine = kEmptyKey;
     unsigned long long mm = m2;
     const int first = __ffsll((long long)m2) - 1;
-    while (mm) {
+    if constexpr (SR) {
+        const int l16 = lane & 15, nc = c.RX4 >> 2;
+        const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float* qx = c.split ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
+        const float4 qv = l16 < nc ? (qlds ? qs[l16] : reinterpret_cast<const float4*>(qx)[l16]) : zero4;
+        const float* xbase = c.split ? c.xr : c.X;
+        const int ld = c.split ? c.Dr4 : c.D4;
+        while (mm) {
+            int sr[kSeedRows];
+            int64_t rs[kSeedRows];
+            float4 xa[kSeedRows];
+#pragma unroll
+            for (int u = 0; u < kSeedRows; u++) {
+                sr[u] = take4(&mm, lane);
+                rs[u] = __shfl(row, sr[u] < 0 ? first : sr[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kSeedRows; u++) xa[u] = l16 < nc ? reinterpret_cast<const float4*>(xbase + rs[u] * ld)[l16] : zero4;
+#pragma unroll
+            for (int u = 0; u < kSeedRows; u++) {
+                float r = 0.f;
+                if (l16 < nc) {
+                    if (c.split) acc_dot4(r, xa[u], qv);
+                    else acc_sqdiff(r, xa[u], qv);
+                }
+                for (int o = 8; o >= 1; o >>= 1) r += __shfl_xor(r, o);
+                const float dist = c.split ? split_dist(__shfl(dso, sr[u] < 0 ? first : sr[u]), r) : r;
+                const unsigned long long key = (sr[u] >= 0 && (st.tau == INFINITY || dist <= st.tau))
+                                                   ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs[u]]
+                                                   : kEmptyKey;
+                if constexpr (TR) {
+                    if (sr[u] >= 0 && l16 == 0 && trace_on(c.tr, q))
+                        trace_cand(c.tr, MRQ_TRACE_EXACT, 0, q, R.list, c.ids[rs[u]], 0, 0, dist, 0.f, 0.f, st.tau);
+                }
+                for (int g = 0; g < 4; g++) {
+                    const int sg = __shfl(sr[u], g * 16);
+                    const unsigned long long kgv = __shfl(key, g * 16);
+                    if (sg >= 0 && lane == sg) mine = kgv;
+                }
+            }
+        }
+    } else while (mm) {
         const int src = take4(&mm, lane);
         const int64_t rs = __shfl(row, src < 0 ? first : src);
         // the exact distance, or (split) the tail product with dis_o' - 2 <x_r, q_r>
@@ -2437,7 +2480,8 @@ __device__ __forceinline__ float seed_lb(const ScanCtx& c, int64_t row, const Pa
     return lb;
 }
 
-template <int WP, int BQT, bool TR>
+// SR: rows of the exact stage of at most 64 floats (RX4 <= 64), taken several per lane group at a time
+template <int WP, int BQT, bool TR, bool SR>
 __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     __shared__ unsigned long long nk[64];
     __shared__ int32_t pend_row[128];
@@ -2518,7 +2562,7 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
         const bool in = lane < cnt;
         const int i = in ? pend_row[lane] : 0;
         const float lb = in ? pend_lb[lane] : INFINITY;
-        seed_batch<WP, TR>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, qs, qlds, lane, &n1, &next, &n2);
+        seed_batch<WP, TR, SR>(c, q, er, R, U, in && lb < st.tau, base + i, st, nk, qs, qlds, lane, &n1, &next, &n2);
         const int rest = np - cnt;  // move the remaining entries to the front
         int r_row = 0;
         float r_lb = 0.f;
@@ -3027,10 +3071,10 @@ size_t search_workspace_bytes(const Index& ix, int64_t nq, int64_t total_slots, 
 
 template <int WP, int BQT, bool TR>
 static void launch_seed_t(const ScanCtx& c, int64_t nq, hipStream_t s) {
-    hipLaunchKernelGGL((k_seed<WP, BQT, TR>), dim3((unsigned)nq), dim3(64),
-                       sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
-                           (c.RX4 <= kSeedLdsFloats ? sizeof(float) * (c.RX4 + c.d4) : 0),
-                       s, c);
+    const size_t lds = sizeof(unsigned long long) * (2 * c.k_max + kSeedMax) +
+                       (c.RX4 <= kSeedLdsFloats ? sizeof(float) * (c.RX4 + c.d4) : 0);
+    if (c.RX4 <= 64) hipLaunchKernelGGL((k_seed<WP, BQT, TR, true>), dim3((unsigned)nq), dim3(64), lds, s, c);
+    else hipLaunchKernelGGL((k_seed<WP, BQT, TR, false>), dim3((unsigned)nq), dim3(64), lds, s, c);
 }
 
 // Blocks of a persistent kernel that are resident at once on the current device (cached per device).
