@@ -599,20 +599,28 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
                 for (int j = 0; j < 4; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
     }
-    // lane holds C[m0 + 16 i + 4 kg + v][n0 + 16 j + li]
+    // lane holds C[m0 + 16 i + 4 kg + v][n0 + 16 j + li]; the four column sub-tiles of an output row are
+    // stored by consecutive instructions (64 B of the row per lane group each), so its 256 B reach the
+    // cache together
+    float cv[4];
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int n = n0 + 16 * j + li;
-        if (n >= N) continue;
-        const float cv = EPI == 1 ? colv[n] : 0.f;
+        cv[j] = EPI == 1 && n < N ? colv[n] : 0.f;
+    }
 #pragma unroll
-        for (int i = 0; i < MI; i++) {
+    for (int i = 0; i < MI; i++) {
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int64_t m = m0 + 16 * i + 4 * kg + v;
-                if (m >= M) continue;
+        for (int v = 0; v < 4; v++) {
+            const int64_t m = m0 + 16 * i + 4 * kg + v;
+            if (m >= M) continue;
+            const float rv = EPI == 1 ? rowv[m] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int n = n0 + 16 * j + li;
+                if (n >= N) continue;
                 float r = acc[i][j][v];
-                if (EPI == 1) r = fmaxf(0.f, fmaf(-2.f, r, rowv[m] + cv));
+                if (EPI == 1) r = fmaxf(0.f, fmaf(-2.f, r, rv + cv[j]));
                 if (EPI == 2 && n >= nsplit) C2[m * ldc2 + (n - nsplit)] = r;
                 else Cm[m * ldc + n] = r;
             }
@@ -871,10 +879,10 @@ __global__ __launch_bounds__(64) void k_query_stats(const float* __restrict__ Q,
 
 // ------------------------------------------------------------------------------------------------
 // Probe selection (Algorithm 2, centroid ranking): the np nearest lists by g_j = ||q_d - c_j||^2,
-// ties -> smaller list id, nearest first.  One block per query, each thread holding up to 64 of the
-// query's nlist distances in registers (non-negative, so their bit patterns order like the values), the
-// row read once.  Up to np = 256 the keys at or below the np-th smallest per-thread minimum are gathered
-// and ranked; otherwise (or when too many keys fall there) a bitwise search for the np-th smallest
+// ties -> smaller list id, nearest first.  One block per query (4 or 8 waves), each thread holding up to 32
+// of the query's nlist distances in registers (non-negative, so their bit patterns order like the values),
+// the row read once.  Up to np = one per thread the keys at or below the np-th smallest per-thread minimum
+// are gathered and ranked; otherwise (or when too many keys fall there) a bitwise search for the np-th smallest
 // pattern T (32 block-wide counting rounds), then every j with g_j <= T is gathered in LDS and the
 // gathered (g, j) keys are sorted; the first np are the probe lists.
 
@@ -892,29 +900,34 @@ __device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, 
     return v;
 }
 
-constexpr int kSelMaxList = 16384;          // nlist <= 256 x 64
 constexpr int kSelCap = kMaxProbe + 1024;   // gathered keys (np plus ties at T)
 
-__device__ __forceinline__ int block_sum256(int v, int* red) {
+template <int NW>
+__device__ __forceinline__ int block_sum_w(int v, int* red) {
     v = wave_sum_i(v);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) r += red[i];
+    return r;
 }
 
-template <int V>
-__global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int nlist,
+// NW waves per block, V values per thread (nlist <= 64 NW V)
+template <int V, int NW>
+__global__ __launch_bounds__(64 * NW) void k_select(const float* __restrict__ G, int nlist,
                                                const int32_t* __restrict__ npq,
                                                const int64_t* __restrict__ pair_off,
                                                int32_t* __restrict__ pair_list,
                                                int32_t* __restrict__ pair_q) {
     __shared__ unsigned long long sel[kSelCap];
-    __shared__ unsigned long long mins[4][64];
+    __shared__ unsigned long long mins[NW][64];
     __shared__ unsigned long long s_thr;
-    __shared__ int red[4];
-    __shared__ int s_cnt, s_wt[4];
+    __shared__ int red[NW];
+    __shared__ int s_cnt, s_wt[NW];
+    constexpr int NT = 64 * NW;
     const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
     const float* g = G + (int64_t)q * nlist;
     const int np = npq[q];
@@ -922,25 +935,25 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     uint32_t v[V];
 #pragma unroll
     for (int u = 0; u < V; u++) {
-        const int j = t + 256 * u;
+        const int j = t + NT * u;
         v[u] = j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
     }
-    if (np <= 256) {
-        // Keys (g_j, j) are unique.  The np-th smallest of the 256 per-thread minimum keys, thr, has at least
+    if (np <= NT) {
+        // Keys (g_j, j) are unique.  The np-th smallest of the NT per-thread minimum keys, thr, has at least
         // np keys at or below it (those np minima), so the np smallest keys are among the keys <= thr, which
         // are usually few: they are gathered and ranked by counting.  (Keys of j >= nlist exceed every real
         // key and are never gathered.)
         unsigned long long mk = kEmptyKey;
 #pragma unroll
         for (int u = 0; u < V; u++) {
-            const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u);
+            const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + NT * u);
             mk = key < mk ? key : mk;
         }
         const unsigned long long sk = wave_sort64(mk, lane);
         mins[w][lane] = sk;
         __syncthreads();
-        int r = lane;  // rank of sk among the 256 minima
-        for (int w2 = 0; w2 < 4; w2++) {
+        int r = lane;  // rank of sk among the NT minima
+        for (int w2 = 0; w2 < NW; w2++) {
             if (w2 == w) continue;
             int lo = 0, hi = 64;
             while (lo < hi) {
@@ -955,7 +968,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         int cnt = 0;
 #pragma unroll
         for (int u = 0; u < V; u++)
-            cnt += t + 256 * u < nlist && (((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u)) <= thr;
+            cnt += t + NT * u < nlist && (((unsigned long long)v[u] << 32) | (uint32_t)(t + NT * u)) <= thr;
         int inc = cnt;  // inclusive prefix over the wave
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(inc, o);
@@ -963,18 +976,20 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         }
         if (lane == 63) s_wt[w] = inc;
         __syncthreads();
-        const int m = s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+        int m = 0;
+#pragma unroll
+        for (int i = 0; i < NW; i++) m += s_wt[i];
         if (m <= kSelCap) {  // block-uniform
             int at = inc - cnt;
             for (int i = 0; i < w; i++) at += s_wt[i];
 #pragma unroll
             for (int u = 0; u < V; u++) {
-                const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + 256 * u);
-                if (t + 256 * u < nlist && key <= thr) sel[at++] = key;
+                const unsigned long long key = ((unsigned long long)v[u] << 32) | (uint32_t)(t + NT * u);
+                if (t + NT * u < nlist && key <= thr) sel[at++] = key;
             }
             __syncthreads();
             const int64_t o = pair_off[q];
-            for (int i = t; i < m; i += 256) {
+            for (int i = t; i < m; i += NT) {
                 const unsigned long long key = sel[i];
                 int rk = 0;
                 for (int x = 0; x < m; x++) rk += sel[x] < key;
@@ -993,19 +1008,19 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         int c = 0;
 #pragma unroll
         for (int u = 0; u < V; u++) c += v[u] < cand;
-        if (block_sum256(c, red) < np) T = cand;
+        if (block_sum_w<NW>(c, red) < np) T = cand;
     }
     int cl = 0, ce = 0;
 #pragma unroll
     for (int u = 0; u < V; u++) { cl += v[u] < T; ce += v[u] == T; }
-    const int nless = block_sum256(cl, red);  // < np
-    const int neq = block_sum256(ce, red);    // >= np - nless
+    const int nless = block_sum_w<NW>(cl, red);  // < np
+    const int neq = block_sum_w<NW>(ce, red);    // >= np - nless
     if (t == 0) s_cnt = 0;
     __syncthreads();
     const bool all_ties = nless + neq <= kSelCap;
 #pragma unroll
     for (int u = 0; u < V; u++) {
-        const int j = t + 256 * u;
+        const int j = t + NT * u;
         if (j < nlist && (v[u] < T || (all_ties && v[u] == T))) {
             const int at = atomicAdd(&s_cnt, 1);
             sel[at] = ((unsigned long long)v[u] << 32) | (uint32_t)j;
@@ -1016,7 +1031,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
     if (!all_ties) {  // more ties at T than fit: take the first np - nless of them in list order
         int taken = 0;
         for (int u = 0; u < V && taken < np - nless; u++) {
-            const int j = t + 256 * u;
+            const int j = t + NT * u;
             // re-read rather than index v (a runtime index would move v out of registers)
             const bool eq = j < nlist && __float_as_uint(g[j]) == T;
             const unsigned long long bm = __ballot(eq);
@@ -1025,18 +1040,19 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
             int r = taken + __popcll(bm & ((1ull << lane) - 1ull));
             for (int i = 0; i < w; i++) r += s_wt[i];
             if (eq && r < np - nless) sel[nless + r] = ((unsigned long long)T << 32) | (uint32_t)j;
-            taken += s_wt[0] + s_wt[1] + s_wt[2] + s_wt[3];
+#pragma unroll
+            for (int i = 0; i < NW; i++) taken += s_wt[i];
             __syncthreads();
         }
         m = np;
     }
     int P = 64;
     while (P < m) P <<= 1;
-    for (int i = m + t; i < P; i += 256) sel[i] = kEmptyKey;
+    for (int i = m + t; i < P; i += NT) sel[i] = kEmptyKey;
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = t; i < P; i += 256) {
+            for (int i = t; i < P; i += NT) {
                 const int ixj = i ^ stride;
                 if (ixj > i) {
                     const bool asc = (i & size) == 0;
@@ -1048,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_select(const float* __restrict__ G, int
         }
     }
     const int64_t o = pair_off[q];
-    for (int r = t; r < np; r += 256) {
+    for (int r = t; r < np; r += NT) {
         pair_list[o + r] = (int32_t)(sel[r] & 0xFFFFFFFFull);
         pair_q[o + r] = q;
     }
@@ -1159,10 +1175,11 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
         else hipLaunchKernelGGL(k_select_w<64>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
         return;
     }
-    const dim3 grid((unsigned)nq), blk(256);
-    if (nlist <= 256 * 16) hipLaunchKernelGGL(k_select<16>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
-    else if (nlist <= 256 * 32) hipLaunchKernelGGL(k_select<32>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
-    else hipLaunchKernelGGL(k_select<64>, grid, blk, 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
+    // one block per query, at most 32 values per thread (blocks of up to 8 waves)
+    const dim3 grid((unsigned)nq);
+    if (nlist <= 256 * 16) hipLaunchKernelGGL((k_select<16, 4>), grid, dim3(256), 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
+    else if (nlist <= 256 * 32) hipLaunchKernelGGL((k_select<32, 4>), grid, dim3(256), 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
+    else hipLaunchKernelGGL((k_select<32, 8>), grid, dim3(512), 0, s, G, nlist, npq, pair_off, pair_list, pair_q);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -243,14 +243,15 @@ def test_mixed_batch_replays_from_a_captured_graph(small):
         assert torch.equal(db.view(torch.int32), ref_d.view(torch.int32)), rep
 
 
-@pytest.mark.parametrize("nlist", [256, 1500, 5000])
+@pytest.mark.parametrize("nlist", [256, 1500, 5000, 9000])
 def test_probe_selection_kernels_agree(nlist):
     """The probe ranking has three forms: one wave per query for nprobe <= 64 and nlist <= 4096 (16, 32 or 64
     lists per lane in registers), and one block per query otherwise, which gathers the keys at or below the
     np-th smallest per-thread minimum when np <= 256 and takes a bitwise search of the np-th smallest
     pattern beyond.  All take the np smallest (g_j, j) in that order, so a row is the same under each
-    (nlist 256 and 1500: wave against block); at nlist 5000 every form is the block kernel, and rows at
-    nprobe 64 (gathering) and 300 (bitwise search) are checked against the oracle row by row."""
+    (nlist 256 and 1500: wave against block); at nlist 5000 and 9000 (blocks of 4 and 8 waves) every form is
+    the block kernel, and rows at nprobe 64 (gathering) and 300 (bitwise search) are checked against the
+    oracle row by row."""
     print(f"\n[gpu] selection kernels agree: nlist={nlist}", flush=True)
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
     ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
