@@ -266,8 +266,14 @@ def measure(args, name, np, torch, mrq, synth, dev, headline, copy_gbs):
     i8_ops = items * 2 * 64 * G * KP                  # stage-1 int8 products (64 rows x G queries x KP)
     f32_ops = tiles2 * 2 * 16 * G * d4                # stage-2 FP32 products
     valu_ops = items * 64 * G * 12                    # the Eq 4-6 epilogue per (row, query) entry
+    # exact stage per candidate: its bin entry and its row of D floats, or (the split form: tail no wider than
+    # the leading block, stage 2 on) the bin entry, dis_o' and the D - d tail floats; the id is read only for
+    # candidates that can enter the result queue and is not counted
+    split = D - d <= d
+    rx = (D - d + 3) // 4 * 4 if split else (D + 3) // 4 * 4
+    ex_b = 4 + 4 * rx + (4 if split else 0)
     kern = {"scan": dict(bytes=pair_bytes, unique=unique_bytes, ops=scanned * 2 * d + pext * 2 * d),
-            "exact": dict(bytes=p2 * (8 + 4 * D), unique=p2 * (8 + 4 * D), ops=p2 * 3 * D)}
+            "exact": dict(bytes=p2 * ex_b, unique=p2 * ex_b, ops=p2 * (2 if split else 3) * rx)}
     rows = {}
     for kn, kb in kern.items():
         ms_tot, launches = kt.get(kn, (0.0, 0))
