@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_I8_PEAK = 5.0e15      # dense int8 matrix-core ops/s
 MFMA_F32_PEAK = 157.3e12   # FP32 matrix-core FLOP/s
-VALU_F32_PEAK = 157.3e12   # FP32 vector FLOP/s
+VALU_OPS_PEAK = 256 * 64 * 2.4e9   # vector lane-operations/s (256 CUs x 64 lanes x 2.4 GHz, one op per lane per
+                                   # clock; the 157.3 TFLOP/s FP32 figure counts an FMA as two and packed FP32)
 SEARCH_SOURCES = ["paper_2411_06158_amd/csrc/mrq_search.hip", "paper_2411_06158_amd/csrc/mrq_internal.h"]
 
 
@@ -292,7 +293,7 @@ def measure(args, name, np, torch, mrq, synth, dev, headline, copy_gbs):
         t = r["launch_ms"] * 1e-3
         lps = r["launches"]
         t_hbm = r["unique_per_launch"] / (HBM_PEAK_GBS * 1e9)
-        t_cmp = (i8_ops / lps) / MFMA_I8_PEAK + (f32_ops / lps) / MFMA_F32_PEAK + (valu_ops / lps) / VALU_F32_PEAK
+        t_cmp = (i8_ops / lps) / MFMA_I8_PEAK + (f32_ops / lps) / MFMA_F32_PEAK + (valu_ops / lps) / VALU_OPS_PEAK
         tag = f"{name}_d{d}_b{B}_np{chosen}_k{k}"
         traffic = counter_traffic(tag, "k_scan")
         roof = {"bound": "hbm", "achieved": round(r["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
