@@ -2161,48 +2161,89 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             wave_lds_fence();
         }
 
-        // ---- exact-stage candidates into their queries' bins: lane t < ng counts the survivors of query
-        // column t (column tile t / 16, lane group t / 4 % 4, v = t % 4) over the item's masks and reserves
-        // room for them with one atomic, one instruction for the whole item; a column's entries follow in
-        // (row tile, row) order ----
+        // ---- exact-stage candidates into their queries' bins: lane t < ng gathers the rows of query column t
+        // (column tile t / 16, lane group t / 4 % 4, v = t % 4) that survived, in (row tile, row) order, reserves
+        // room for them with one atomic (one instruction for the whole item) and writes them itself, four at a
+        // time with their stage-2 values read together; no step of the writes needs another lane ----
         if (cnt > 0) {
-            int base = 0;
+            const int tc = lane >> 4, tg = (lane >> 2) & 3, tv = lane & 3;
+            unsigned long long cm = 0ull;  // bit r: row r of the block survived for this lane's column
+            int base = 0, n = 0, qcol = 0;
             if (lane < ng) {
-                const int tc = lane >> 4, tg = (lane >> 2) & 3, tv = lane & 3;
-                int n = 0;
+#pragma unroll
                 for (int rt = 0; rt < 4; rt++)
-                    n += __popcll((msk[(tc * 4 + rt) * 4 + tv] >> (16 * tg)) & 0xFFFFull);
-                if (n) base = atomicAdd(&c.qcnt[rec[lane].q], n);
+                    cm |= ((msk[(tc * 4 + rt) * 4 + tv] >> (16 * tg)) & 0xFFFFull) << (16 * rt);
+                n = __popcll(cm);
+                qcol = rec[lane].q;
+                if (n) base = atomicAdd(&c.qcnt[qcol], n);
+            }
+            // entry (row 16 rt + l, column t) of the stage-2 values sits at slot (tc * 4 + rt) * 4 + tv, lane
+            // l + 16 tg (lanes without a column read a slot of column 0, within the wave's stash)
+            const float* cst = dstash + (lane < ng ? tc * 1024 + tv * 64 + 16 * tg : 0);
+            int r[4];
+            float sv[4];
+            auto take4 = [&]() {  // the column's next four rows (-1 past its last) and their stage-2 values
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    r[u] = cm ? (int)__builtin_ctzll(cm) : -1;
+                    cm &= cm - 1ull;
+                }
+                if constexpr (SPL) {
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int ru = r[u] < 0 ? 0 : r[u];
+                        sv[u] = cst[(ru >> 4) * 256 + (ru & 15)];
+                    }
+                }
+            };
+            take4();  // requested before the reservation's result is needed
+            for (int i = 0;; i += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int pos = base + i + u;
+                    if (r[u] >= 0 && pos < c.cq) {
+                        const int64_t at = (int64_t)qcol * c.cq + pos;
+                        c.surv[at] = (int)(row0 + r[u]);
+                        if constexpr (SPL) c.survd[at] = sv[u];
+                    }
+                }
+                if (!__ballot(cm != 0ull)) break;
+                take4();
             }
             // the reservation is consumed here on every path (an unconsumed result register would make the
-            // next item wait for all memory operations in flight before its first write to that register)
+            // next item wait for all memory operations in flight before its first write to that register);
+            // the writes above wait for it only where they use it, after the stage-2 values are requested
             asm volatile("" ::"v"(base));
-            for (int ct = 0; ct < nct; ct++) {
-                int bb[4], off[4];
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    bb[v] = __shfl(base, ct * 16 + 4 * kg + v);
-                    off[v] = 0;
-                }
-                for (int rt = 0; rt < 4; rt++) {
+            nreg += cnt;
+            // a bin that overflowed: its entries beyond the capacity are finished in place, found by the
+            // sub-tile walk (which writes the fitting entries again, with the same values)
+            if (__ballot(lane < ng && base + n > c.cq)) {
+                for (int ct = 0; ct < nct; ct++) {
+                    int bb[4], off[4];
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
-                        const unsigned long long mv = msk[(ct * 4 + rt) * 4 + v];
-                        if (!mv) continue;
-                        const bool mine = (mv >> lane) & 1ull;
-                        const uint32_t gm = (uint32_t)(mv >> (lane & 48)) & 0xFFFFu;
-                        const int pos = bb[v] + off[v] + __popc(gm & ((1u << li) - 1u));
-                        off[v] += __popc(gm);
-                        const bool fits = mine && pos < c.cq;
-                        const int slot = ((ct * 4 + rt) * 4 + v) * 64;
-                        if (fits) {
-                            const int64_t at = (int64_t)rec[ct * 16 + 4 * kg + v].q * c.cq + pos;
-                            c.surv[at] = (int)(row0 + 16 * rt + li);
-                            if constexpr (SPL) c.survd[at] = dstash[slot + lane];
+                        bb[v] = __shfl(base, ct * 16 + 4 * kg + v);
+                        off[v] = 0;
+                    }
+                    for (int rt = 0; rt < 4; rt++) {
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const unsigned long long mv = msk[(ct * 4 + rt) * 4 + v];
+                            if (!mv) continue;
+                            const bool mine = (mv >> lane) & 1ull;
+                            const uint32_t gm = (uint32_t)(mv >> (lane & 48)) & 0xFFFFu;
+                            const int pos = bb[v] + off[v] + __popc(gm & ((1u << li) - 1u));
+                            off[v] += __popc(gm);
+                            const bool fits = mine && pos < c.cq;
+                            const int slot = ((ct * 4 + rt) * 4 + v) * 64;
+                            if (fits) {
+                                const int64_t at = (int64_t)rec[ct * 16 + 4 * kg + v].q * c.cq + pos;
+                                c.surv[at] = (int)(row0 + 16 * rt + li);
+                                if constexpr (SPL) c.survd[at] = dstash[slot + lane];
+                            }
+                            const unsigned long long rest = __ballot(mine && !fits);
+                            if (rest) finish_inline<SPL>(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane, dstash + slot);
                         }
-                        const unsigned long long rest = __ballot(mine && !fits);
-                        if (rest) finish_inline<SPL>(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane, dstash + slot);
-                        nreg += __popcll(mv);
                     }
                 }
             }
