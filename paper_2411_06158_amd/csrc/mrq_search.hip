@@ -508,7 +508,8 @@ static hipError_t launch_gemm_dist(const float* A, int64_t lda, const float* Bm,
 // fragment and 16-wide K step (lane group g feeds k = 16s + 4g + e in multiply step e), VEC = 1: one
 // float per lane per 4-wide K step.  Every element is one chain of fused multiply-adds over k in a fixed
 // order that depends only on K and VEC, so a row's result does not depend on the other rows.
-// EPI 0: C[m][n];  EPI 1: max(0, rowv[m] + colv[n] - 2 C) (squared distances);  EPI 2: columns below
+// EPI 0: C[m][n];  EPI 1: max(0, rowv[m] + colv[n] - 2 C) (squared distances), and with tmin the smallest
+// distance of each row within each 64-column tile, tmin[m * gridDim.y + tile];  EPI 2: columns below
 // nsplit go to C (ldc), the others to C2 (ldc2) at column n - nsplit.
 template <int VEC, int EPI, int MI>
 __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, int64_t lda,
@@ -516,7 +517,8 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
                                                    const float* __restrict__ Bm, int64_t ldb,
                                                    float* __restrict__ Cm, int64_t ldc, int64_t M, int N, int K,
                                                    const float* __restrict__ rowv, const float* __restrict__ colv,
-                                                   float* __restrict__ C2, int64_t ldc2, int nsplit) {
+                                                   float* __restrict__ C2, int64_t ldc2, int nsplit,
+                                                   float* __restrict__ tmin) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, kg = lane >> 4;
     const int64_t m0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * MI);
@@ -613,16 +615,26 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const float* __restrict__ A, 
 #pragma unroll
         for (int v = 0; v < 4; v++) {
             const int64_t m = m0 + 16 * i + 4 * kg + v;
-            if (m >= M) continue;
-            const float rv = EPI == 1 ? rowv[m] : 0.f;
+            const bool mok = m < M;
+            const float rv = EPI == 1 && mok ? rowv[m] : 0.f;
+            float mn = __int_as_float(0x7f800000);  // the row's smallest stored value in this tile
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int n = n0 + 16 * j + li;
-                if (n >= N) continue;
                 float r = acc[i][j][v];
                 if (EPI == 1) r = fmaxf(0.f, fmaf(-2.f, r, rv + cv[j]));
-                if (EPI == 2 && n >= nsplit) C2[m * ldc2 + (n - nsplit)] = r;
-                else Cm[m * ldc + n] = r;
+                if (mok && n < N) {
+                    if (EPI == 2 && n >= nsplit) C2[m * ldc2 + (n - nsplit)] = r;
+                    else Cm[m * ldc + n] = r;
+                }
+                if (EPI == 1 && n < N) mn = fminf(mn, r);
+            }
+            if (EPI == 1 && tmin) {  // (kernel-uniform) the 16 lanes of the row's lane group
+                mn = fminf(mn, __shfl_xor(mn, 1));
+                mn = fminf(mn, __shfl_xor(mn, 2));
+                mn = fminf(mn, __shfl_xor(mn, 4));
+                mn = fminf(mn, __shfl_xor(mn, 8));
+                if (li == 0 && mok) tmin[m * gridDim.y + blockIdx.y] = mn;
             }
         }
     }
@@ -633,7 +645,8 @@ static bool vec4_ok(const void* p, int64_t ld) { return ((uintptr_t)p & 15) == 0
 template <int EPI>
 static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
                                    float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
-                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s);
+                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s,
+                                   float* tmin = nullptr);
 
 hipError_t launch_project(const float* X, int64_t M, int D, const float* mu, const float* Pp, int d, float* lead,
                           int64_t ld_lead, float* tail, int64_t ld_tail, hipStream_t s) {
@@ -643,7 +656,8 @@ hipError_t launch_project(const float* X, int64_t M, int D, const float* mu, con
 template <int EPI>
 static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asub, const float* Bm, int64_t ldb,
                                    float* Cm, int64_t ldc, int64_t M, int N, int K, const float* rowv,
-                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s) {
+                                   const float* colv, float* C2, int64_t ldc2, int nsplit, hipStream_t s,
+                                   float* tmin) {
     if (M <= 0 || N <= 0) return hipSuccess;
     // 64 x 64 output tiles per wave, or 32 x 64 when that gives fewer than about 4 waves per SIMD (the
     // projection): the products of an output element are the same chain either way
@@ -652,7 +666,7 @@ static hipError_t launch_gemm_mfma(const float* A, int64_t lda, const float* asu
     const dim3 grid((unsigned)((M + (half ? 127 : 255)) / (half ? 128 : 256)), (unsigned)((N + 63) / 64));
 #define GEMM_LAUNCH(V, MIV) \
     hipLaunchKernelGGL((k_gemm_mfma<V, EPI, MIV>), grid, dim3(256), 0, s, A, lda, asub, Bm, ldb, Cm, ldc, M, N, K, \
-                       rowv, colv, C2, ldc2, nsplit)
+                       rowv, colv, C2, ldc2, nsplit, tmin)
     if (v4 && half) GEMM_LAUNCH(4, 2);
     else if (v4) GEMM_LAUNCH(4, 4);
     else if (half) GEMM_LAUNCH(1, 2);
@@ -915,20 +929,19 @@ __device__ __forceinline__ int block_sum_w(int v, int* red) {
     return r;
 }
 
-// NW waves per block, V values per thread (nlist <= 64 NW V)
+// NW waves per block, V values per thread (nlist <= 64 NW V); query q (block-uniform); every thread of the
+// block returns at the same point
 template <int V, int NW>
-__global__ __launch_bounds__(64 * NW) void k_select(const float* __restrict__ G, int nlist,
-                                               const int32_t* __restrict__ npq,
-                                               const int64_t* __restrict__ pair_off,
-                                               int32_t* __restrict__ pair_list,
-                                               int32_t* __restrict__ pair_q) {
+__device__ __forceinline__ void select_block(const int q, const float* __restrict__ G, int nlist,
+                                             const int32_t* __restrict__ npq, const int64_t* __restrict__ pair_off,
+                                             int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q) {
     __shared__ unsigned long long sel[kSelCap];
     __shared__ unsigned long long mins[NW][64];
     __shared__ unsigned long long s_thr;
     __shared__ int red[NW];
     __shared__ int s_cnt, s_wt[NW];
     constexpr int NT = 64 * NW;
-    const int q = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const float* g = G + (int64_t)q * nlist;
     const int np = npq[q];
     if (np == 0) return;  // block-uniform
@@ -1070,6 +1083,30 @@ __global__ __launch_bounds__(64 * NW) void k_select(const float* __restrict__ G,
     }
 }
 
+template <int V, int NW>
+__global__ __launch_bounds__(64 * NW) void k_select(const float* __restrict__ G, int nlist,
+                                               const int32_t* __restrict__ npq,
+                                               const int64_t* __restrict__ pair_off,
+                                               int32_t* __restrict__ pair_list,
+                                               int32_t* __restrict__ pair_q) {
+    select_block<V, NW>(blockIdx.x, G, nlist, npq, pair_off, pair_list, pair_q);
+}
+
+// The block selection of the queries listed in redo[1 .. redo[0]] (those the tile selection below hands
+// back), blocks striding over the list.
+template <int V, int NW>
+__global__ __launch_bounds__(64 * NW) void k_select_redo(const float* __restrict__ G, int nlist,
+                                                    const int32_t* __restrict__ npq,
+                                                    const int64_t* __restrict__ pair_off,
+                                                    int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q,
+                                                    const int32_t* __restrict__ redo) {
+    const int n = redo[0];
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        select_block<V, NW>(redo[1 + i], G, nlist, npq, pair_off, pair_list, pair_q);
+        __syncthreads();  // the shared arrays are reused by the next query
+    }
+}
+
 
 // The same selection for np <= 64 and nlist <= 64 V, one wave per query (four per block, no barriers):
 // lane l holds the patterns of lists j = l + 64 u.  The np-th smallest of the 64 lane minima is a
@@ -1166,8 +1203,146 @@ __global__ __launch_bounds__(256) void k_select_w(const float* __restrict__ G, i
     }
 }
 
+// Selection from the tile minima of the distance product (np <= 64, nlist in (4096, 16384]), one wave per
+// query.  Tile t holds lists 64 t .. 64 t + 63 and m_t is their smallest distance.  Let T be the np-th
+// smallest tile minimum: the np tiles whose minima are at most T hold np distinct lists at most T, so the
+// np-th smallest distance is at most T, and every list among the np smallest keys (g_j, j) lies in a tile
+// with m_t <= T.  Those tiles (np of them, more only with ties at T) are the candidates: with at most 64,
+// slot u of lane l holds list 64 tile_u + l and the wave ranks the candidates as k_select_w ranks a row
+// (the np-th smallest lane minimum bounds the selection; the keys at or below it, when at most 64, are
+// sorted; otherwise a bitwise search of the np-th pattern, then of the last list id taken among its
+// ties).  A query with more candidate tiles is listed in redo for the block selection.  Same lists, same
+// order as k_select.
+constexpr int kTileSlots = 64;
+template <int VT>
+__global__ __launch_bounds__(256) void k_select_t(const float* __restrict__ G, const float* __restrict__ TM,
+                                                 int nlist, int ntiles, const int32_t* __restrict__ npq,
+                                                 const int64_t* __restrict__ pair_off,
+                                                 int32_t* __restrict__ pair_list, int32_t* __restrict__ pair_q,
+                                                 int64_t nq, int32_t* __restrict__ redo) {
+    __shared__ unsigned long long sel_s[4][64];
+    __shared__ int tile_s[4][kTileSlots];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = blockIdx.x * 4ll + w;
+    if (q >= nq) return;
+    const int np = npq[q];
+    if (np == 0) return;  // wave-uniform
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    // T: the np-th smallest tile-minimum pattern (the largest pattern with fewer than np below it)
+    uint32_t tv[VT];
+#pragma unroll
+    for (int u = 0; u < VT; u++) {
+        const int t = lane + 64 * u;
+        tv[u] = t < ntiles ? __float_as_uint(TM[q * ntiles + t]) : 0xFFFFFFFFu;
+    }
+    uint32_t T = 0;
+    for (int b = 31; b >= 0; b--) {
+        const uint32_t cand = T | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < VT; u++) c += tv[u] < cand;
+        if (wave_sum_i(c) < np) T = cand;
+    }
+    int mt = 0;  // candidate tiles, in increasing tile order
+#pragma unroll
+    for (int u = 0; u < VT; u++) {
+        const bool sel = lane + 64 * u < ntiles && tv[u] <= T;
+        const unsigned long long m = __ballot(sel);
+        const int at = mt + __popcll(m & lt);
+        if (sel && at < kTileSlots) tile_s[w][at] = lane + 64 * u;
+        mt += __popcll(m);
+    }
+    if (mt > kTileSlots) {  // wave-uniform
+        if (lane == 0) redo[1 + atomicAdd(redo, 1)] = (int32_t)q;
+        return;
+    }
+    wave_lds_fence();
+    // slot u: list 64 tile_u + lane (no list beyond the candidates or nlist: the empty pattern)
+    const float* g = G + q * nlist;
+    uint32_t v[kTileSlots];
+#pragma unroll
+    for (int u = 0; u < kTileSlots; u++) {
+        const int j = (u < mt ? tile_s[w][u] : 0) * 64 + lane;
+        v[u] = u < mt && j < nlist ? __float_as_uint(g[j]) : 0xFFFFFFFFu;
+    }
+    auto list_of = [&](int u) { return tile_s[w][u < mt ? u : 0] * 64 + lane; };
+    uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < kTileSlots; u++) mn = min(mn, v[u]);
+    const uint32_t t = (uint32_t)__shfl(wave_sort64(mn, lane), np - 1);
+    int cc = 0;
+#pragma unroll
+    for (int u = 0; u < kTileSlots; u++) cc += v[u] <= t;
+    int at = 0;
+    if (wave_sum_i(cc) <= 64) {
+#pragma unroll
+        for (int u = 0; u < kTileSlots; u++) {
+            const bool sel = v[u] <= t;
+            const unsigned long long m = __ballot(sel);
+            if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v[u] << 32) | (uint32_t)list_of(u);
+            at += __popcll(m);
+        }
+    } else {
+        uint32_t P = 0;  // the np-th smallest pattern
+        for (int b = 31; b >= 0; b--) {
+            const uint32_t cand = P | (1u << b);
+            int c = 0;
+#pragma unroll
+            for (int u = 0; u < kTileSlots; u++) c += v[u] < cand;
+            if (wave_sum_i(c) < np) P = cand;
+        }
+        int cl = 0, ce = 0;
+#pragma unroll
+        for (int u = 0; u < kTileSlots; u++) { cl += v[u] < P; ce += v[u] == P; }
+        const int need = np - wave_sum_i(cl);  // ties at P to take, smallest list ids first (>= 1)
+        int J = nlist;                         // lists j < J among the ties are taken
+        if (wave_sum_i(ce) > need) {
+            uint32_t Jb = 0;  // the need-th smallest tied list id
+            for (int b = 31 - __clz(nlist - 1); b >= 0; b--) {
+                const uint32_t cand = Jb | (1u << b);
+                int c = 0;
+#pragma unroll
+                for (int u = 0; u < kTileSlots; u++) c += v[u] == P && (uint32_t)list_of(u) < cand;
+                if (wave_sum_i(c) < need) Jb = cand;
+            }
+            J = (int)Jb + 1;
+        }
+#pragma unroll
+        for (int u = 0; u < kTileSlots; u++) {
+            const int j = list_of(u);
+            const bool sel = v[u] < P || (v[u] == P && j < J);
+            const unsigned long long m = __ballot(sel);
+            if (sel) sel_s[w][at + __popcll(m & lt)] = ((unsigned long long)v[u] << 32) | (uint32_t)j;
+            at += __popcll(m);
+        }
+    }
+    wave_lds_fence();
+    const unsigned long long key = wave_sort64(lane < at ? sel_s[w][lane] : kEmptyKey, lane);
+    if (lane < np) {
+        const int64_t o = pair_off[q];
+        pair_list[o + lane] = (int32_t)(key & 0xFFFFFFFFull);
+        pair_q[o + lane] = (int32_t)q;
+    }
+}
+
+// The tile selection serves np <= 64 with nlist in (4096, 16384] (at most 256 tiles, four per lane).
+static bool tile_select(int nlist, int np_max) { return np_max <= 64 && nlist > 64 * 64 && nlist <= 64 * 256; }
+
+// TM: the tile minima of the product (tile_select), with redo (nq + 1 entries) for the queries it hands back;
+// otherwise null.
 static void launch_select(const float* G, int nlist, const int32_t* npq, const int64_t* pair_off, int32_t* pair_list,
-                          int32_t* pair_q, int64_t nq, int np_max, hipStream_t s) {
+                          int32_t* pair_q, int64_t nq, int np_max, hipStream_t s, const float* TM = nullptr,
+                          int32_t* redo = nullptr) {
+    if (TM) {
+        const int ntiles = (nlist + 63) / 64;
+        launch_fill_i32(redo, 0, 1, s);
+        hipLaunchKernelGGL(k_select_t<4>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, G, TM, nlist, ntiles, npq,
+                           pair_off, pair_list, pair_q, nq, redo);
+        const unsigned rb = (unsigned)std::min<int64_t>(nq, 256);
+        if (nlist <= 256 * 32) hipLaunchKernelGGL((k_select_redo<32, 4>), dim3(rb), dim3(256), 0, s, G, nlist, npq, pair_off, pair_list, pair_q, redo);
+        else hipLaunchKernelGGL((k_select_redo<32, 8>), dim3(rb), dim3(512), 0, s, G, nlist, npq, pair_off, pair_list, pair_q, redo);
+        return;
+    }
     if (np_max <= 64 && nlist <= 64 * 64) {
         const dim3 gw((unsigned)((nq + 3) / 4)), bw(256);
         if (nlist <= 64 * 16) hipLaunchKernelGGL(k_select_w<16>, gw, bw, 0, s, G, nlist, npq, pair_off, pair_list, pair_q, nq);
@@ -3045,6 +3220,8 @@ struct Carve {
 
 struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
+    float* TM;      // tile minima of the probe distances (tile selection)
+    int32_t* redo;  // queries the tile selection hands back: count, then the list
     int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *qcnt;
     __bf16* qbf;  // BF16 staging of the tail product
     int4* desc;
@@ -3089,6 +3266,9 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.Tq = c.take<float>(nq);
     w.er = c.take<float>(nq);
     w.G = c.take<float>(nq * (int64_t)ix.nlist);
+    const bool ts = tile_select(ix.nlist, np_max);
+    w.TM = ts ? c.take<float>(nq * (int64_t)((ix.nlist + 63) / 64)) : nullptr;
+    w.redo = ts ? c.take<int32_t>(nq + 1) : nullptr;
     w.pair_list = c.take<int32_t>(total_pairs);
     w.pair_q = c.take<int32_t>(total_pairs);
     w.pair_pos = c.take<int32_t>(total_pairs);
@@ -3515,8 +3695,8 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
     {   // centroid ranking
         Timed t(tm, s, "probe");
         HIP_TRY(launch_gemm_mfma<1>(w.qd, d4, nullptr, ix.C, d4, w.G, nlist, nq, nlist, d, w.qd2, ix.Cn2, nullptr,
-                                    0, 0, s));
-        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, a.np_max, s);
+                                    0, 0, s, w.TM));
+        launch_select(w.G, nlist, a.npq, a.pair_off, w.pair_list, w.pair_q, nq, a.np_max, s, w.TM, w.redo);
         HIP_TRY(hipGetLastError());
     }
     ScanCtx c;

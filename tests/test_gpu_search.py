@@ -243,15 +243,15 @@ def test_mixed_batch_replays_from_a_captured_graph(small):
         assert torch.equal(db.view(torch.int32), ref_d.view(torch.int32)), rep
 
 
-@pytest.mark.parametrize("nlist", [256, 1500, 5000, 9000])
+@pytest.mark.parametrize("nlist", [256, 1500, 5000, 9000, 16000])
 def test_probe_selection_kernels_agree(nlist):
-    """The probe ranking has three forms: one wave per query for nprobe <= 64 and nlist <= 4096 (16, 32 or 64
-    lists per lane in registers), and one block per query otherwise, which gathers the keys at or below the
-    np-th smallest per-thread minimum when np <= 256 and takes a bitwise search of the np-th smallest
-    pattern beyond.  All take the np smallest (g_j, j) in that order, so a row is the same under each
-    (nlist 256 and 1500: wave against block); at nlist 5000 and 9000 (blocks of 4 and 8 waves) every form is
-    the block kernel, and rows at nprobe 64 (gathering) and 300 (bitwise search) are checked against the
-    oracle row by row."""
+    """The probe ranking has four forms: one wave per query for nprobe <= 64 and nlist <= 4096 (16, 32 or 64
+    lists per lane in registers), one wave per query from the product's tile minima for nprobe <= 64 and
+    nlist above 4096, and one block per query otherwise, which gathers the keys at or below the np-th
+    smallest per-thread minimum when np <= 256 and takes a bitwise search of the np-th smallest pattern
+    beyond.  All take the np smallest (g_j, j) in that order, so a row is the same under each (nlist 256
+    and 1500: wave against block; 5000, 9000 and 16000: tiles against blocks of 4 and 8 waves), and rows at nprobe
+    64 (tiles) and 300 (bitwise search) are checked against the oracle row by row."""
     print(f"\n[gpu] selection kernels agree: nlist={nlist}", flush=True)
     X, Q, _ = synth.workload("small", N=20000, nq=60, cache=False)
     ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=nlist)
@@ -273,6 +273,34 @@ def test_probe_selection_kernels_agree(nlist):
             for nprobe in (64, 300):
                 ids, dists = _search(env, 10, nprobe)
                 _assert_parity(env, ids, dists, 10, nprobe)
+    finally:
+        ix.close()
+
+
+def test_tile_selection_ties_and_hand_back():
+    """Above 4096 lists and up to nprobe 64 the ranking starts from the product's per-tile minima (64 lists
+    a tile): only the tiles whose minimum is at most the np-th smallest one are read.  Here the data repeats
+    48 points, so most of the 6000 centroids coincide and the probe distances tie exactly: most queries have
+    more than 64 tiles at that minimum and are handed to the block selection, the others rank ties inside
+    the tile kernel (bitwise search of the pattern, then of the last list id taken).  Either way the rows
+    equal those of the block selection run for the whole batch (nprobe_max 100)."""
+    print("\n[gpu] tile selection with tied probe distances: N=24000 D=64 nlist=6000", flush=True)
+    rng = np.random.default_rng(11)
+    base = rng.standard_normal((48, 64)).astype(np.float32)
+    X = np.ascontiguousarray(base[rng.integers(0, 48, 24000)])
+    Q = np.ascontiguousarray(base[rng.integers(0, 48, 60)] + 0.05 * rng.standard_normal((60, 64)).astype(np.float32))
+    ix = mrq.Index.build(torch.from_numpy(X).cuda(), d_r=32, bits=1, nlist=6000)
+    try:
+        Qd = torch.from_numpy(Q).cuda()
+        for np_small in (1, 10, 40, 64):
+            ks = np.full(60, 10, np.int32)
+            nps = np.full(60, np_small, np.int32)
+            nps[-1] = 100
+            ids, dists, _ = ix.search_mixed(Qd, ks, nps)
+            a, b = ix.search(Qd[:59].contiguous(), 10, np_small)
+            torch.cuda.synchronize()
+            assert np.array_equal(ids[:590].reshape(59, 10), a.cpu().numpy()), np_small
+            assert np.array_equal(dists[:590].reshape(59, 10).view(np.uint32), b.cpu().numpy().view(np.uint32))
     finally:
         ix.close()
 
