@@ -2101,8 +2101,17 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 
         // ---- stage 1 for every 16 x 16 sub-tile: pass masks into msk ----
         int cnt = 0;
+        // HR (the staged form with one column tile at d_r 64): the pair records of the lane's four query
+        // columns are read from LDS once per item and kept in registers for stages 1 and 2, so no row tile
+        // waits on them
+        constexpr bool HR = QL && NCT == 1 && KIT == 1;
+        PairRec Rh[HR ? 4 : 1];
         if (KIT > 0) {
             wave_lds_fence();
+            if constexpr (HR) {
+#pragma unroll
+                for (int v = 0; v < 4; v++) Rh[v] = rec[4 * kg + v < ng ? 4 * kg + v : 0];
+            }
 #pragma unroll
             for (int rt = 0; rt < 4; rt++) {
                 int sp = 0;
@@ -2120,7 +2129,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
                             const int g = ct * 16 + 4 * kg + v;
-                            const PairRec& R = rec[g < ng ? g : 0];
+                            const PairRec& R = HR ? Rh[HR ? v : 0] : rec[g < ng ? g : 0];
                             const bool ps = g < ng &&
                                             stage1_from_ip(acc[v] + ob * pc, pc, fa[rt], ff[rt], fe[rt], R, c.d) < R.tau;
                             if constexpr (TR) {
@@ -2250,6 +2259,12 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                 if (c.cnt_ext && lane == 0) sh_tiles[wv] += __popc(rtany);
                 float4 xb[2][XS];
                 float axb[2] = {0.f, 0.f};
+                // HR: the q_d slices of the lane's query row (the same for every row tile), read once
+                float4 qh[HR ? XS : 1];
+                if constexpr (HR) {
+#pragma unroll
+                    for (int t = 0; t < XS; t++) qh[t] = qsh[qsh_index(li, 4 * t + kg, nf4)];
+                }
 #pragma unroll
                 for (int rt = 0; rt < 4; rt++) {
                     // the next tile's slices and norms are requested before this tile's products
@@ -2269,16 +2284,21 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                         if (!any) continue;
                         // slots beyond ng hold stale rows: they only reach their own (never tested) outputs
                         f32x4 dot = {0.f, 0.f, 0.f, 0.f};
-                        float4 qv4[XS];
+                        if constexpr (HR) {
 #pragma unroll
-                        for (int t = 0; t < XS; t++) qv4[t] = qsh[qsh_index(ct * 16 + li, 4 * t + kg, nf4)];
+                            for (int t = 0; t < XS; t++) mfma4(dot, qh[t], xa[t]);
+                        } else {
+                            float4 qv4[XS];
 #pragma unroll
-                        for (int t = 0; t < XS; t++) mfma4(dot, qv4[t], xa[t]);
+                            for (int t = 0; t < XS; t++) qv4[t] = qsh[qsh_index(ct * 16 + li, 4 * t + kg, nf4)];
+#pragma unroll
+                            for (int t = 0; t < XS; t++) mfma4(dot, qv4[t], xa[t]);
+                        }
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
                             bool ps = (mv[v] >> lane) & 1ull;
                             if (ps) {
-                                const PairRec& R = rec[ct * 16 + 4 * kg + v];
+                                const PairRec& R = HR ? Rh[HR ? v : 0] : rec[ct * 16 + 4 * kg + v];
                                 const float dso = fmaf(-2.f, dot[v], axr + R.qn2);
                                 ps = dso - R.er < R.tau;
                                 if constexpr (SPL) dstash[((ct * 4 + rt) * 4 + v) * 64 + lane] = dso;
