@@ -844,6 +844,69 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_excl(const int32_t* __res
     if (t == 0) out[n] = carry_s;
 }
 
+// The same exclusive prefix sum over many workgroups (segments of kSeg entries): the segment sums, then
+// each segment's scan from the sum of the segments before it.  Beside a kernel that fills the GPU, a
+// single workgroup gets one CU's share of issue slots; these spread over as many CUs as segments.
+constexpr int kSegItems = 4;
+constexpr int kSeg = kScanThreads * kSegItems;
+
+__device__ __forceinline__ int block_sum_256(int v, int* red) {
+    v = wave_sum_i(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_sums(const int32_t* __restrict__ in, int64_t n,
+                                                          int32_t* __restrict__ sums) {
+    __shared__ int red[kScanThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kSeg + threadIdx.x * kSegItems;
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < kSegItems; i++) t += b0 + i < n ? in[b0 + i] : 0;
+    t = block_sum_256(t, red);
+    if (threadIdx.x == 0) sums[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_seg_scan(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                          int64_t n, const int32_t* __restrict__ sums) {
+    __shared__ int red[kScanThreads / 64], wsum[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int o = 0;  // the entries before this segment
+    for (int i = t; i < (int)blockIdx.x; i += kScanThreads) o += sums[i];
+    o = block_sum_256(o, red);
+    const int64_t b0 = (int64_t)blockIdx.x * kSeg + t * kSegItems;
+    int32_t v[kSegItems];
+    int32_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < kSegItems; i++) {
+        v[i] = b0 + i < n ? in[b0 + i] : 0;
+        tot += v[i];
+    }
+    int32_t incl = tot;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int32_t run = o + incl - tot;
+    for (int i = 0; i < w; i++) run += wsum[i];
+#pragma unroll
+    for (int i = 0; i < kSegItems; i++) {
+        if (b0 + i < n) out[b0 + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == kScanThreads - 1) out[n] = run;  // the total
+}
+
+// out[0..n]: the exclusive prefix sums of in[0..n-1] and the total; sums: ceil(n / kSeg) entries of scratch
+static void launch_scan_excl_seg(const int32_t* in, int32_t* out, int64_t n, int32_t* sums, hipStream_t s) {
+    const unsigned nseg = (unsigned)std::max<int64_t>(1, (n + kSeg - 1) / kSeg);
+    hipLaunchKernelGGL(k_seg_sums, dim3(nseg), dim3(kScanThreads), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_seg_scan, dim3(nseg), dim3(kScanThreads), 0, s, in, out, n, sums);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Per-query statistics (Algorithm 2, first three steps; Eq 6):
 //   qpad = q (zero padded to D4), ||q_p||^2 = ||q - mu||^2, ||q_d||^2, ||q_r||^2 = ||q_p||^2 - ||q_d||^2,
@@ -2646,6 +2709,9 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
             }
 #pragma unroll
             for (int u = 0; u < kSeedRows; u++) xa[u] = l16 < nc ? reinterpret_cast<const float4*>(xbase + rs[u] * ld)[l16] : zero4;
+            int idv[kSeedRows];  // requested with the rows, so no round trip follows the distances
+#pragma unroll
+            for (int u = 0; u < kSeedRows; u++) idv[u] = c.ids[rs[u]];
 #pragma unroll
             for (int u = 0; u < kSeedRows; u++) {
                 float r = 0.f;
@@ -2656,7 +2722,7 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
                 for (int o = 8; o >= 1; o >>= 1) r += __shfl_xor(r, o);
                 const float dist = c.split ? split_dist(__shfl(dso, sr[u] < 0 ? first : sr[u]), r) : r;
                 const unsigned long long key = (sr[u] >= 0 && (st.tau == INFINITY || dist <= st.tau))
-                                                   ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs[u]]
+                                                   ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)idv[u]
                                                    : kEmptyKey;
                 if constexpr (TR) {
                     if (sr[u] >= 0 && l16 == 0 && trace_on(c.tr, q))
@@ -2672,15 +2738,16 @@ __device__ __forceinline__ void seed_batch(const ScanCtx& c, int q, float er, co
     } else while (mm) {
         const int src = take4(&mm, lane);
         const int64_t rs = __shfl(row, src < 0 ? first : src);
+        const int idv = c.ids[rs];  // requested before the row, so no round trip follows the distance
         // the exact distance, or (split) the tail product with dis_o' - 2 <x_r, q_r>
         const float* xrow = c.split ? c.xr + rs * c.Dr4 : c.X + rs * c.D4;
         const float* qrow = c.split ? c.qr + (int64_t)q * c.Dr4 : c.qpad + (int64_t)q * c.D4;
         const float r = qlds ? row_group_lds(xrow, qs, c.RX4, lane & 15, c.split)
                              : row_group(xrow, qrow, c.RX4, lane & 15, c.split);
         const float dist = c.split ? split_dist(__shfl(dso, src < 0 ? first : src), r) : r;
-        // a key whose distance is above a full queue's last cannot survive the merge: its id is not read
+        // a key whose distance is above a full queue's last cannot survive the merge: it stays empty
         const unsigned long long key = (src >= 0 && (st.tau == INFINITY || dist <= st.tau))
-                                           ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)c.ids[rs]
+                                           ? ((unsigned long long)__float_as_uint(dist) << 32) | (uint32_t)idv
                                            : kEmptyKey;
         if constexpr (TR) {
             if (src >= 0 && (lane & 15) == 0 && trace_on(c.tr, q))
@@ -2783,7 +2850,9 @@ __global__ __launch_bounds__(64) void k_seed(ScanCtx c) {
     const int64_t base = c.list_off[j];
     const int nsel = n < kSeedMax ? n : kSeedMax;
     long long n1 = 0, next = 0, n2 = 0;
-    // round 1: keys (ord(lb), row) of the first nsel rows, and the s-th smallest of them
+    // round 1: keys (ord(lb), row) of the first nsel rows, and the s-th smallest of them (two chunks of 64
+    // rows with their loads in flight together)
+#pragma unroll 2
     for (int i = lane; i < nsel; i += 64) {
         const float lb = seed_lb<WP, BQT, TR>(c, base + i, R, U);
         keys[i] = ((unsigned long long)ord_bits(lb) << 32) | (uint32_t)i;
@@ -3242,6 +3311,7 @@ struct WsPtrs {
     float *qd, *qtail, *qpad, *rq, *qn2, *qd2, *Tq, *er, *G;
     float* TM;      // tile minima of the probe distances (tile selection)
     int32_t* redo;  // queries the tile selection hands back: count, then the list
+    int32_t* segsum;  // segment sums of the (phase, list) prefix sums
     int32_t *pair_list, *pair_q, *pair_pos, *cnt, *boff, *fill, *items, *ioff, *qcnt;
     __bf16* qbf;  // BF16 staging of the tail product
     int4* desc;
@@ -3292,6 +3362,7 @@ WsPtrs carve(void* base, const Index& ix, int64_t nq, int64_t total_slots, int64
     w.pair_list = c.take<int32_t>(total_pairs);
     w.pair_q = c.take<int32_t>(total_pairs);
     w.pair_pos = c.take<int32_t>(total_pairs);
+    w.segsum = c.take<int32_t>(P / kSeg + 1);
     w.cnt = c.take<int32_t>(P);
     w.boff = c.take<int32_t>(P + 1);
     w.fill = c.take<int32_t>(P);
@@ -3777,7 +3848,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
         HIP_TRY(launch_fill_i32(w.fill, 0, P, s));
         hipLaunchKernelGGL(k_pair_count, dim3((unsigned)((a.total_pairs + 255) / 256)), dim3(256), 0, s,
                            w.pair_list, w.pair_q, a.pair_off, a.pair_off + nq, nlist, a.phase_shift, w.cnt);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.cnt, w.boff, P);
+        launch_scan_excl_seg(w.cnt, w.boff, P, w.segsum, s);
         const int nh = (d + 63) / 64;
         const int KP = level_bytes(d);
         // 16 lanes per pair up to d = 256 (4 pairs per wave: the kernel is bound by the latency of its loads
@@ -3802,7 +3873,7 @@ hipError_t launch_search(const SearchArgs& a, void* ws, size_t ws_bytes, hipStre
 #undef PREP_T
         hipLaunchKernelGGL(k_items, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, w.cnt, ix.list_nb,
                            nlist, G, (int)P, w.items);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(kScanThreads), 0, s, w.items, w.ioff, P);
+        launch_scan_excl_seg(w.items, w.ioff, P, w.segsum, s);
         hipLaunchKernelGGL(k_item_desc, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, s, w.ioff, w.boff, ix.list_nb,
                            ix.list_off, nlist, G, P, w.desc);
         HIP_TRY(hipGetLastError());
