@@ -103,6 +103,18 @@ def cpu_description():
                 info[k] = v
     except Exception:
         pass
+    # lscpu may give neither clock inside a container: the kernel's per-core figures then
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and len(v) > len(info.get("Model name", "")):
+                    info["Model name"] = v
+                if k == "cpu MHz" and "CPU MHz" not in info:
+                    info["CPU MHz"] = v
+    except OSError:
+        pass
     return info
 
 
