@@ -2164,6 +2164,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
 
         // ---- stage 1 for every 16 x 16 sub-tile: pass masks into msk ----
         int cnt = 0;
+        uint32_t rt1 = 0;  // row tiles holding a stage-1 survivor (wave-uniform, from the ballots)
         // HR (the staged form with one column tile at d_r 64): the pair records of the lane's four query
         // columns are read from LDS once per item and kept in registers for stages 1 and 2, so no row tile
         // waits on them
@@ -2206,6 +2207,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             const unsigned long long mv = __ballot(ps);
                             if (lane == 0) msk[(ct * 4 + rt) * 4 + v] = mv;
                             cnt += __popcll(mv);
+                            rt1 |= (mv != 0ull ? 1u : 0u) << rt;
                         }
                     }
                 }
@@ -2313,12 +2315,17 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         if (cnt > 0 && c.stage2) {
             cnt = 0;
             if constexpr (QL) {
-                uint32_t rtany = 0;  // row tiles holding a surviving entry (wave-uniform)
+                // row tiles holding a surviving entry (wave-uniform): stage 1's, unless the B-bit refinement
+                // has since cleared entries
+                uint32_t rtany = rt1;
+                if (do_ext) {
+                    rtany = 0;
 #pragma unroll
-                for (int rt = 0; rt < 4; rt++)
-                    for (int ct = 0; ct < nct; ct++)
+                    for (int rt = 0; rt < 4; rt++)
+                        for (int ct = 0; ct < nct; ct++)
 #pragma unroll
-                        for (int v = 0; v < 4; v++) rtany |= (msk[(ct * 4 + rt) * 4 + v] != 0ull ? 1u : 0u) << rt;
+                            for (int v = 0; v < 4; v++) rtany |= (msk[(ct * 4 + rt) * 4 + v] != 0ull ? 1u : 0u) << rt;
+                }
                 if (c.cnt_ext && lane == 0) sh_tiles[wv] += __popc(rtany);
                 float4 xb[2][XS];
                 float axb[2] = {0.f, 0.f};
@@ -2344,7 +2351,9 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                         bool any = false;
 #pragma unroll
                         for (int v = 0; v < 4; v++) { mv[v] = msk[(ct * 4 + rt) * 4 + v]; any |= mv[v] != 0; }
-                        if (!any) continue;
+                        // (one column tile: the row tile's flag already says that a mask is set, so the
+                        // products need not wait for the masks)
+                        if (NCT > 1 && !any) continue;
                         // slots beyond ng hold stale rows: they only reach their own (never tested) outputs
                         f32x4 dot = {0.f, 0.f, 0.f, 0.f};
                         if constexpr (HR) {
