@@ -1398,7 +1398,7 @@ static void launch_select(const float* G, int nlist, const int32_t* npq, const i
                           int32_t* redo = nullptr) {
     if (TM) {
         const int ntiles = (nlist + 63) / 64;
-        launch_fill_i32(redo, 0, 1, s);
+        (void)launch_fill_i32(redo, 0, 1, s);  // (a launch error surfaces at the caller's hipGetLastError)
         hipLaunchKernelGGL(k_select_t<4>, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, G, TM, nlist, ntiles, npq,
                            pair_off, pair_list, pair_q, nq, redo);
         const unsigned rb = (unsigned)std::min<int64_t>(nq, 256);
@@ -1809,6 +1809,17 @@ struct ScanCtx {
     float eps0;
     int nlist, d, d4, D4, B, bq, WP, KI, KP, G, stage2, use_ext, phase, k_max, cq;
 };
+
+// The launch context of a kernel that takes a ScanCtx as its only argument, read again from the kernel-argument
+// segment through a pointer the compiler cannot see through: the fields that only rarely taken paths use are
+// then loaded where they are used, instead of being held in scalar registers across the whole kernel (which
+// spilled them into vector registers).
+__device__ __forceinline__ const ScanCtx& ctx_here() {
+    const __attribute__((address_space(4))) char* k =
+        (const __attribute__((address_space(4))) char*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return *reinterpret_cast<const ScanCtx*>((const char*)k);
+}
 
 __device__ __forceinline__ float ord_to_float(uint32_t o) {
     return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
@@ -2256,11 +2267,12 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
         wave_lds_fence();
         // ---- B-bit refinement of the stage-1 survivors ----
         if (cnt > 0 && do_ext) {
+            const ScanCtx& ce = ctx_here();  // (a rarely taken path: its fields loaded here)
             cnt = 0;
             for (int rt = 0; rt < 4; rt++) {
                 const int64_t row = row0 + 16 * rt + li;
-                const uint32_t* cp = c.code + row * WP;
-                const uint32_t* ew = c.ext + row * (int64_t)(c.B - 1) * WP;
+                const uint32_t* cp = ce.code + row * WP;
+                const uint32_t* ew = ce.ext + row * (int64_t)(ce.B - 1) * WP;
                 for (int ct = 0; ct < nct; ct++) {
                     unsigned long long mv[4];
                     bool any = false;
@@ -2269,16 +2281,16 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                     if (!any) continue;
                     const int qs = ct * 16 + li;
                     const bool qv = qs < ng;
-                    const int8_t* qb = c.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * c.KP + 16 * kg;
+                    const int8_t* qb = ce.qu8 + (int64_t)(pbeg + (qv ? qs : 0)) * ce.KP + 16 * kg;
                     i32x4 acc2 = {0, 0, 0, 0};
                     for (int m = 0; m < KI; m++) {
-                        i32x4 ub = piece_bytes(plane_piece(cp, WP, m, kg)) << (c.B - 1);
-                        for (int a = 0; a < c.B - 1; a++) ub |= piece_bytes(plane_piece(ew + a * WP, WP, m, kg)) << a;
+                        i32x4 ub = piece_bytes(plane_piece(cp, WP, m, kg)) << (ce.B - 1);
+                        for (int a = 0; a < ce.B - 1; a++) ub |= piece_bytes(plane_piece(ew + a * WP, WP, m, kg)) << a;
                         if (oa) ub ^= (int)0x80808080u;
                         acc2 = __builtin_amdgcn_mfma_i32_16x16x64_i8(qop(qb, m, qv), ub, acc2, 0, 0, 0);
                     }
-                    const float A = c.fA[row], FB = c.fFB[row], EB = c.fEB[row], SX = c.fSX[row];
-                    const long long sumux = ((long long)SX + (long long)((1 << c.B) - 1) * c.d) / 2;
+                    const float A = ce.fA[row], FB = ce.fFB[row], EB = ce.fEB[row], SX = ce.fSX[row];
+                    const long long sumux = ((long long)SX + (long long)((1 << ce.B) - 1) * ce.d) / 2;
 #pragma unroll
                     for (int v = 0; v < 4; v++) {
                         bool ps = (mv[v] >> lane) & 1ull;
@@ -2286,12 +2298,12 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                             const PairRec& R = rec[ct * 16 + 4 * kg + v];
                             // sum_i ux_i u_i from sum_i (ux_i - oa)(u_i - ob) over the d real dimensions
                             const long long ipB = (long long)acc2[v] + ob * sumux + oa * (long long)R.su -
-                                                  (long long)oa * ob * c.d;
-                            ps = ext_from_ip(ipB, c.B, A, FB, EB, SX, R) < R.tau;
+                                                  (long long)oa * ob * ce.d;
+                            ps = ext_from_ip(ipB, ce.B, A, FB, EB, SX, R) < R.tau;
                             if constexpr (TR) {
-                                if (trace_on(c.tr, R.q)) {
-                                    const float inB = ext_inner(ipB, c.B, A, FB, SX, R);
-                                    trace_cand(c.tr, MRQ_TRACE_EXT, p, R.q, R.list, c.ids[row], (int)ipB, 0, inB,
+                                if (trace_on(ce.tr, R.q)) {
+                                    const float inB = ext_inner(ipB, ce.B, A, FB, SX, R);
+                                    trace_cand(ce.tr, MRQ_TRACE_EXT, p, R.q, R.list, ce.ids[row], (int)ipB, 0, inB,
                                                R.ebc * EB, fmaf(-R.ebc, EB, inB), R.tau);
                                 }
                             }
@@ -2485,6 +2497,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
             // a bin that overflowed: its entries beyond the capacity are finished in place, found by the
             // sub-tile walk (which writes the fitting entries again, with the same values)
             if (__ballot(lane < ng && base + n > c.cq)) {
+                const ScanCtx& cf = ctx_here();  // (a rarely taken path: its fields loaded here)
                 for (int ct = 0; ct < nct; ct++) {
                     int bb[4], off[4];
 #pragma unroll
@@ -2509,7 +2522,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
                                 if constexpr (SPL) c.survd[at] = dstash[slot + lane];
                             }
                             const unsigned long long rest = __ballot(mine && !fits);
-                            if (rest) finish_inline<SPL>(c, rec, rest, row0 + 16 * rt, ct * 16, v, lane, dstash + slot);
+                            if (rest) finish_inline<SPL>(cf, rec, rest, row0 + 16 * rt, ct * 16, v, lane, dstash + slot);
                         }
                     }
                 }
