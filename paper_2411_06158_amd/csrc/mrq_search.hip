@@ -1979,7 +1979,9 @@ __device__ __forceinline__ int qsh_index(int slot, int f4, int nf4) { return slo
 // The LDS-staged form at 16 queries per item sits at the edge of two waves per SIMD (VGPRs + AGPRs <= 256).
 // Declaring that occupancy (a minimum of two waves) made the compiler keep the accumulators out of AGPRs and
 // the scan 25 % slower (measured), so the budget is left to the compiler's own heuristic.
-template <int GT, int KIT, bool QL, bool TR, bool SPL>
+// EXT = false: an index without extended codes (B = 1) or a search without the B-bit refinement; the
+// refinement's code (and the registers it holds) is then not in the kernel at all.
+template <int GT, int KIT, bool QL, bool TR, bool SPL, bool EXT = true>
 __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     constexpr int NCT = GT / 16;
     constexpr int KA = KIT > 0 ? KIT : 1;
@@ -2005,7 +2007,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanCtx c) {
     const int nf4 = c.d4 >> 2;
     const int ob = c.bq == 8 ? 128 : 0;  // query levels are stored as the signed bytes u - ob
     const int oa = c.B == 8 ? 128 : 0;   // extended levels enter the product as the signed bytes ux - oa
-    const bool do_ext = c.B > 1 && c.use_ext;
+    const bool do_ext = EXT && c.B > 1 && c.use_ext;
     const int WP = c.WP;
     PairRec* rec = sh_rec[wv];
     unsigned long long* msk = sh_m[wv];
@@ -3455,12 +3457,18 @@ static size_t scan_lds(const ScanCtx& c, int GT) { return (size_t)4 * GT * c.d4 
 static size_t scan_stash(const ScanCtx& c, int GT) { return c.split ? (size_t)4 * (GT / 16) * 16 * 64 * sizeof(float) : 0; }
 
 // TR: the tracing instantiations (c.tr set; query group 16 only).
+static bool scan_ext(const ScanCtx& c) { return c.B > 1 && c.use_ext; }
+
 template <int GT, int KIT, bool TR, bool SPL>
 static void launch_scan_k(const ScanCtx& c, hipStream_t s, int blocks) {
     if constexpr (KIT == 1 || KIT == 2) {
         if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536) {
-            hipLaunchKernelGGL((k_scan<GT, KIT, true, TR, SPL>), dim3(blocks), dim3(256),
-                               scan_lds(c, GT) + scan_stash(c, GT), s, c);
+            if (scan_ext(c))
+                hipLaunchKernelGGL((k_scan<GT, KIT, true, TR, SPL, true>), dim3(blocks), dim3(256),
+                                   scan_lds(c, GT) + scan_stash(c, GT), s, c);
+            else
+                hipLaunchKernelGGL((k_scan<GT, KIT, true, TR, SPL, false>), dim3(blocks), dim3(256),
+                                   scan_lds(c, GT) + scan_stash(c, GT), s, c);
             return;
         }
     }
@@ -3489,20 +3497,25 @@ static void launch_scan(const ScanCtx& c, hipStream_t s, int blocks) {
 }
 
 // Blocks of the persistent scan grid: what is resident at once on the device, at most kMaxScanBlocks.
+// slot: the resident-block cache entry of the staged form with the B-bit refinement; xslot: without it
 template <int GT, int KIT, bool TR, bool SPL>
-static int scan_grid_k(const ScanCtx& c, int slot) {
+static int scan_grid_k(const ScanCtx& c, int slot, int xslot = -1) {
     if constexpr (KIT == 1 || KIT == 2) {
-        if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536)
-            return std::min(resident_blocks(k_scan<GT, KIT, true, TR, SPL>, 256, slot, scan_lds(c, GT) + scan_stash(c, GT)),
+        if (scan_ql<GT, KIT>(c) && scan_lds(c, GT) <= 65536) {
+            const size_t lds = scan_lds(c, GT) + scan_stash(c, GT);
+            return std::min(scan_ext(c) ? resident_blocks(k_scan<GT, KIT, true, TR, SPL, true>, 256, slot, lds)
+                                        : resident_blocks(k_scan<GT, KIT, true, TR, SPL, false>, 256, xslot, lds),
                             kMaxScanBlocks);
+        }
     }
     return std::min(resident_blocks(k_scan<GT, KIT, false, TR, SPL>, 256, slot + 1, scan_stash(c, GT)), kMaxScanBlocks);
 }
 template <int GT, bool TR, bool SPL>
 static int scan_grid_g(const ScanCtx& c, int slot) {
     switch (c.KI) {
-        case 1: return scan_grid_k<GT, 1, TR, SPL>(c, slot + 0);
-        case 2: return scan_grid_k<GT, 2, TR, SPL>(c, slot + 2);
+        // (slots 4 and 6, which the forms below leave free, hold the staged forms without the refinement)
+        case 1: return scan_grid_k<GT, 1, TR, SPL>(c, slot + 0, slot + 4);
+        case 2: return scan_grid_k<GT, 2, TR, SPL>(c, slot + 2, slot + 6);
         case 3: case 4: return scan_grid_k<GT, 4, TR, SPL>(c, slot + 4);
         default: return scan_grid_k<GT, 0, TR, SPL>(c, slot + 6);
     }
